@@ -1,0 +1,391 @@
+"""Pins of the oracle's transport (Sec. 2.1 Woodcock tracking and interaction
+sampling; Sec. 2.2.1 batches; Sec. 2.2.5 spectrum stratification; Sec. 2.2.6
+source trajectory) against closed forms, invariances and brute force."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+from oracle import oracle as O
+from synth import physics as ph
+from synth import workloads as W
+from tests._helpers import frac_within, random_phantom, slab_workload
+
+THREADS = 8
+
+
+def _mu_node(name, rho, E, rayleigh):
+    return rho * float(ph.mu_rho_total(name, E, rayleigh))
+
+
+# ---------------- P1: narrow-beam primary transmission ----------------
+
+def test_narrow_beam_transmission_water():
+    wl = W.tiny(n_histories=1_000_000)
+    c = O.OracleCase(wl)
+    r = O.run(c, threads=THREADS)
+    t = c.mu_rho[0, 59].astype(np.float64)
+    mu = t[0] + t[1]                       # tables as stored, 60 keV node
+    assert mu == pytest.approx(0.198864, abs=2e-6)
+    p = np.exp(-mu * 16.0)
+    n = r["n_hist"]
+    z = (r["n_unscattered"] - n * p) / np.sqrt(n * p * (1 - p))
+    assert abs(z) < 4.0, z
+
+
+def test_layered_slab_transmission_exp_integral():
+    """Woodcock is exact in heterogeneous media: T = exp(-sum mu_i l_i)."""
+    layers = [("water", 1.0, 4), ("cortical_bone", 1.85, 2), ("lung", 0.3, 6),
+              ("air", 0.0012, 4), ("soft_tissue", 1.05, 4)]
+    wl = slab_workload(layers, e_kev=60.0, n_hist=1_000_000, dz=0.5)
+    c = O.OracleCase(wl)
+    r = O.run(c, threads=THREADS)
+    tab = c.mu_rho.astype(np.float64)
+    mats = wl.materials
+    line = sum(rho * tab[mats.index(m), 59].sum() * n * 0.5 for m, rho, n in layers)
+    # the stored rho is float32
+    line = sum(float(np.float32(rho)) * tab[mats.index(m), 59].sum() * n * 0.5
+               for m, rho, n in layers)
+    p = np.exp(-line)
+    n = r["n_hist"]
+    z = (r["n_unscattered"] - n * p) / np.sqrt(n * p * (1 - p))
+    assert abs(z) < 4.0, (z, p)
+    # majorant is set by bone
+    assert c.mu_max[59] >= np.float32(1.85) * np.float32(tab[mats.index("cortical_bone"), 59].sum())
+
+
+# ---------------- P4: energy conservation ----------------
+
+@pytest.mark.parametrize("name", ["water_cbct", "head"])
+def test_energy_conservation(name):
+    wl = W.by_name(name, n_histories=20_000, scale=8)
+    c = O.OracleCase(wl)
+    r = O.run(c, threads=THREADS)
+    assert r["n_hist"] == 20_000
+    assert abs(r["e_inc"] - r["e_dep"] - r["e_esc"]) <= 1e-12 * r["e_inc"]
+    n_q = r["n_hist"] + r["n_deposits"] + r["n_escapes"]
+    assert abs(r["q_inc"] - r["q_dep"] - r["q_esc"]) <= 0.5 * n_q
+    assert r["s1"].sum() == r["q_dep"]
+    assert r["shadow"].sum() == pytest.approx(r["e_dep"], rel=1e-12)
+
+
+# ---------------- P5: brute force on tiny phantoms ----------------
+
+@pytest.mark.parametrize("shape", [(2, 2, 2), (4, 4, 4)])
+def test_tally_equals_event_log(shape):
+    wl = random_phantom(shape, 3, seed=sum(shape), n_hist=10_000)
+    c = O.OracleCase(wl)
+    r = O.run(c, batches=[10_000], threads=3, log_range=(0, 10_000), log_cap=400_000)
+    ev = r["log"]
+    dep = ev[np.isin(ev["type"], [O.EV_PHOTO, O.EV_COMPTON, O.EV_CUTOFF])]
+    V = c.n_voxels
+    T = np.zeros(V, np.int64)
+    np.add.at(T, dep["vox"], np.rint(dep["e"] * O.Q_SCALE).astype(np.int64))
+    assert np.array_equal(T, r["s1"])
+    D = np.zeros(V)
+    np.add.at(D, dep["vox"], dep["e"])
+    assert np.allclose(D, r["shadow"], rtol=1e-12, atol=0)
+    # every history has one source event and ends exactly once
+    ends = ev[np.isin(ev["type"], [O.EV_PHOTO, O.EV_CUTOFF, O.EV_ESCAPE, O.EV_MISS])]
+    assert np.array_equal(np.sort(ends["h"]), np.arange(10_000))
+    # per-history balance: source E = deposits + escape
+    src = ev[ev["type"] == O.EV_SOURCE]
+    tot = np.zeros(10_000)
+    np.add.at(tot, dep["h"], dep["e"])
+    esc = ev[np.isin(ev["type"], [O.EV_ESCAPE, O.EV_MISS])]
+    np.add.at(tot, esc["h"], esc["e"])
+    assert np.allclose(tot, src["e"], rtol=1e-13)
+
+
+# ---------------- P7: special media ----------------
+
+def _table_only(wl, keep):
+    t = wl.mu_rho().copy()
+    for k in range(3):
+        if k not in keep:
+            t[..., k] = 0.0
+    return t
+
+
+def test_photoelectric_only_medium_exponential_law():
+    wl = W.tiny(n_histories=400_000)
+    c = O.OracleCase(wl, mu_rho=_table_only(wl, [0]))
+    r = O.run(c, batches=[400_000], threads=1, log_range=(0, 400_000), log_cap=900_000)
+    mu = float(c.mu_rho[0, 59, 0])
+    E = 60.0
+    n = r["n_hist"]
+    assert r["n_compton"] == 0 and r["n_rayleigh"] == 0
+    assert r["e_dep"] == pytest.approx(n * E - r["n_unscattered"] * E, rel=1e-14)
+    ev = r["log"]
+    pe = ev[ev["type"] == O.EV_PHOTO]
+    iz = pe["vox"] // (32 * 32)
+    assert np.all(pe["vox"] % (32 * 32) == 16 * 32 + 16)   # on the beam axis
+    obs = np.bincount(iz, minlength=32)
+    zc = np.arange(33) * 0.5
+    exp = n * (np.exp(-mu * zc[:-1]) - np.exp(-mu * zc[1:]))
+    chi2 = ((obs - exp) ** 2 / exp).sum()
+    assert stats.chi2.sf(chi2, 31) > 1e-3
+
+
+def test_rayleigh_only_medium_zero_dose():
+    wl = W.tiny(n_histories=20_000)
+    wl.rayleigh = True
+    c = O.OracleCase(wl, mu_rho=_table_only(wl, [2]))
+    r = O.run(c, threads=THREADS)
+    assert r["n_rayleigh"] > 0
+    assert np.all(r["s1"] == 0) and r["e_dep"] == 0.0
+    assert r["n_escapes"] == r["n_hist"]
+
+
+def test_compton_only_with_cutoff_at_source_energy():
+    wl = W.tiny(n_histories=50_000)
+    wl.e_cut = 60.0 + 1e-9
+    c = O.OracleCase(wl, mu_rho=_table_only(wl, [1]))
+    r = O.run(c, threads=THREADS)
+    n_int = r["n_hist"] - r["n_unscattered"]
+    assert r["n_compton"] == n_int == r["n_cutoff"]
+    assert r["n_deposits"] == 2 * n_int
+    assert r["e_dep"] == pytest.approx(60.0 * n_int, rel=1e-13)
+
+
+# ---------------- P8: Woodcock invariances ----------------
+
+def test_majorant_scaling_invariance():
+    wl = W.head(n_histories=300_000, scale=8)
+    res = []
+    for f in [1.0, 2.0, 4.0]:
+        c = O.OracleCase(wl, majorant_scale=f)
+        r = O.run(c, threads=THREADS)
+        d, s = O.dose_and_sigma(r, c, wl.n_histories)
+        res.append((d, s, r))
+    steps = [x[2]["n_steps"] for x in res]
+    assert steps[0] < steps[1] < steps[2]
+    d0, s0, r0 = res[0]
+    mask = d0 > 0.1 * d0.max()
+    for d, s, r in res[1:]:
+        assert frac_within(d0, s0, d, s, mask) >= 0.99
+        # mean deposited energy per history: |diff| within 4 sigma (E_max bound)
+        tol = 4 * 100.0 / np.sqrt(wl.n_histories) * np.sqrt(2)
+        assert abs(r["e_dep"] - r0["e_dep"]) / wl.n_histories < tol
+
+
+def test_voxel_split_invariance():
+    """Splitting every voxel into 2x2x2 identical voxels leaves every
+    trajectory unchanged; the re-binned tally equals the coarse one."""
+    coarse = random_phantom((6, 8, 8), 4, seed=5, n_hist=40_000, dxyz=1.0)
+    fine = random_phantom((6, 8, 8), 4, seed=5, n_hist=40_000, dxyz=1.0)
+    fine.mat = np.repeat(np.repeat(np.repeat(coarse.mat, 2, 0), 2, 1), 2, 2)
+    fine.rho = np.repeat(np.repeat(np.repeat(coarse.rho, 2, 0), 2, 1), 2, 2)
+    g = dict(coarse.grid)
+    g.update(nx=16, ny=16, nz=12, dx=0.5, dy=0.5, dz=0.5)
+    fine.grid = g
+    rc = O.run(O.OracleCase(coarse), threads=THREADS)
+    rf = O.run(O.OracleCase(fine), threads=THREADS)
+    binned = rf["s1"].reshape(6, 2, 8, 2, 8, 2).sum(axis=(1, 3, 5)).reshape(-1)
+    same = np.mean(binned == rc["s1"])
+    assert same >= 0.999
+    assert rf["n_steps"] == rc["n_steps"] or abs(rf["n_steps"] - rc["n_steps"]) < 1e-4 * rc["n_steps"]
+    assert rf["e_dep"] == pytest.approx(rc["e_dep"], rel=1e-4)
+
+
+# ---------------- P9: source sampling ----------------
+
+def _hamilton_exact(n, w):
+    fw = [Fraction(x) for x in w]
+    W_ = sum(fw)
+    q = [Fraction(n) * x / W_ for x in fw]
+    base = [int(x) for x in q]
+    rem = n - sum(base)
+    order = sorted(range(len(w)), key=lambda j: (-(q[j] - base[j]), j))
+    for j in order[:rem]:
+        base[j] += 1
+    return base
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 99_991, 10**9 + 7])
+def test_bin_allocation_largest_remainder(n):
+    lo, w = ph.kramers_spectrum(120)
+    got = O.alloc_bins(n, w)
+    assert int(got.sum()) == n
+    assert list(map(int, got)) == _hamilton_exact(n, w)
+
+
+def test_source_sampling_uniformity():
+    wl = W.water_cbct(scale=8)
+    c = O.OracleCase(wl)
+    geo = wl.geometry
+    N = 20_000
+    S = np.array([O.sample_source(c, h, 7) for h in range(N)])
+    iso = np.array(geo["iso"])
+    # source on the orbit of radius SAD at one of nproj angles
+    r = np.hypot(S[:, 0] - iso[0], S[:, 1] - iso[1])
+    assert np.allclose(r, geo["sad"], rtol=1e-12)
+    phi = np.degrees(np.arctan2(S[:, 0], S[:, 1])) % 360.0
+    p = np.rint(phi * geo["nproj"] / geo["arc_deg"]).astype(int) % geo["nproj"]
+    assert np.allclose(phi, p * geo["arc_deg"] / geo["nproj"], atol=1e-9)
+    cnt = np.bincount(p, minlength=geo["nproj"])
+    assert stats.chisquare(cnt).pvalue > 1e-3
+    # energy uniform within bin 7
+    e = S[:, 6] - wl.spectrum_lo[7]
+    assert stats.kstest(e, "uniform").pvalue > 1e-3
+    # hit point on the isocentre plane uniform on the field rectangle
+    ph_ = np.radians(p * geo["arc_deg"] / geo["nproj"])
+    axis = -np.stack([np.sin(ph_), np.cos(ph_), 0 * ph_], 1)
+    t = -np.einsum("ij,ij->i", S[:, :3] - iso, axis) / np.einsum("ij,ij->i", S[:, 3:6], axis)
+    P = S[:, :3] + t[:, None] * S[:, 3:6] - iso
+    elat = np.stack([np.cos(ph_), -np.sin(ph_), 0 * ph_], 1)
+    a = np.einsum("ij,ij->i", P, elat)
+    b = P[:, 2]
+    assert stats.kstest((a - geo["a0"]) / (geo["a1"] - geo["a0"]), "uniform").pvalue > 1e-3
+    assert stats.kstest((b - geo["b0"]) / (geo["b1"] - geo["b0"]), "uniform").pvalue > 1e-3
+
+
+def test_history_layout_bin_major():
+    wl = W.water_cbct(scale=8, n_histories=1000)
+    c = O.OracleCase(wl)
+    batches = O.batch_sizes(1000, 10)
+    cnt = O.alloc_bins(100, c.bin_w)
+    pref = np.concatenate([[0], np.cumsum(cnt)])
+    for h in [0, 1, 57, 99, 100, 250, 999]:
+        j = O.bin_of_history(c, h, batches)
+        assert pref[j] <= h % 100 < pref[j + 1]
+        e = O.sample_source(c, h, j)[6]
+        assert wl.spectrum_lo[j] <= e < wl.spectrum_lo[j] + 1.0
+
+
+# ---------------- P10: symmetry ----------------
+
+def test_pencil_mirror_symmetry():
+    """Beam through the centre of the middle voxel of a 31x31 cross-section:
+    the geometry is symmetric under x- and y-mirrors and the x<->y swap."""
+    wl = W.tiny(n_histories=1_000_000)
+    wl.grid = dict(wl.grid, nx=31, ny=31)
+    wl.mat = np.zeros((32, 31, 31), np.uint8)
+    wl.rho = np.ones((32, 31, 31), np.float32)
+    wl.geometry = dict(kind="pencil", src=(7.75, 7.75, 0.0), dir=(0.0, 0.0, 1.0))
+    c = O.OracleCase(wl)
+    r = O.run(c, threads=THREADS)
+    d, s = O.dose_and_sigma(r, c, wl.n_histories)
+    d, s = d.reshape(32, 31, 31), s.reshape(32, 31, 31)
+    mask = d > 0.01 * d.max()
+    for op in [lambda a: np.flip(a, 2), lambda a: np.flip(a, 1),
+               lambda a: np.swapaxes(a, 1, 2)]:
+        assert frac_within(d, s, op(d), op(s), mask & op(mask)) >= 0.99
+
+
+def test_cylinder_rotational_symmetry():
+    """360-deg orbit around a centred cylinder: the energy deposited in each
+    ring is the same in the four azimuthal quadrants (chi-square over the
+    batch-to-batch spread)."""
+    wl = W.water_cbct(scale=4, n_histories=400_000)
+    c = O.OracleCase(wl)
+    g = wl.grid
+    x = g["ox"] + (np.arange(32) + 0.5) * g["dx"]
+    X, Y = np.meshgrid(x, x)
+    R, A = np.hypot(X, Y), np.arctan2(Y, X)
+    masks = [((A >= -np.pi + q * np.pi / 2) & (A < -np.pi / 2 + q * np.pi / 2)
+              & (R >= r0) & (R < r0 + 3)) for r0 in range(0, 15, 3) for q in range(4)]
+    n = 40_000
+    per_batch = []
+    for b in range(10):
+        r = O.run(c, batches=[n], h0=b * n, threads=THREADS)
+        e = r["shadow"].reshape(25, 32, 32)[8:17].sum(0)
+        per_batch.append([e[m].sum() for m in masks])
+    pb = np.array(per_batch).reshape(10, 5, 4)
+    mean = pb.mean(0)
+    se2 = pb.var(0, ddof=1) / 10
+    ring = (mean / se2).sum(1) / (1 / se2).sum(1)
+    chi2 = (((mean - ring[:, None]) ** 2) / se2).sum()
+    assert stats.chi2.sf(chi2, 15) > 1e-3, chi2
+
+
+# ---------------- P11 / resume / threads ----------------
+
+def test_batch_stats_exact_vs_two_pass():
+    wl = random_phantom((4, 6, 6), 3, seed=9, n_hist=5000, dxyz=1.0)
+    c = O.OracleCase(wl)
+    n = 500
+    Tb = []
+    for b in range(10):
+        rb = O.run(c, batches=[n], h0=b * n, threads=2)
+        Tb.append(rb["s1"].copy())
+    Tb = np.array(Tb)
+    r = O.run(c, batches=[n] * 10, threads=4)
+    assert np.array_equal(Tb.sum(0), r["s1"])
+    s2 = [sum(int(t) ** 2 for t in Tb[:, v]) for v in range(Tb.shape[1])]
+    got = [(int(h) << 64) | int(l) for h, l in zip(r["s2_hi"], r["s2_lo"])]
+    assert got == s2
+    mean, var = O.batch_stats(r["s1"], r["s2_hi"], r["s2_lo"], 10)
+    Tf = Tb.astype(np.float64)
+    assert np.allclose(mean, Tf.mean(0), rtol=1e-15)
+    ref = Tf.var(0, ddof=1) / 10
+    assert np.allclose(var, ref, rtol=1e-9, atol=1e-6)
+
+
+def test_thread_count_invariance_and_resume():
+    wl = W.water_cbct(scale=8, n_histories=30_000)
+    c = O.OracleCase(wl)
+    r1 = O.run(c, threads=1)
+    r8 = O.run(c, threads=8)
+    for k in ["s1", "s2_hi", "s2_lo"]:
+        assert np.array_equal(r1[k], r8[k])
+    assert r1["q_dep"] == r8["q_dep"] and r1["n_steps"] == r8["n_steps"]
+    bs = O.batch_sizes(30_000, 10)
+    ra = O.run(c, batches=bs[:4], h0=0, threads=3)
+    rb = O.run(c, batches=bs[4:], h0=sum(bs[:4]), threads=5)
+    assert np.array_equal(ra["s1"] + rb["s1"], r1["s1"])
+
+
+# ---------------- P6: first-collision kerma along the pencil axis ----------------
+
+def test_first_collision_kerma_along_axis():
+    wl = W.tiny(n_histories=300_000)
+    c = O.OracleCase(wl)
+    r = O.run(c, batches=[300_000], threads=1, log_range=(0, 300_000), log_cap=1_500_000)
+    ev = r["log"]
+    real = ev[np.isin(ev["type"], [O.EV_PHOTO, O.EV_COMPTON])]
+    first = real[np.r_[True, real["h"][1:] != real["h"][:-1]]]
+    iz = first["vox"] // (32 * 32)
+    E = 60.0
+    t = c.mu_rho[0, 59].astype(np.float64)
+    mu = t[0] + t[1]
+    k = E / ph.ME_C2_KEV
+    f = lambda m: float(ph.kn_dsigma_dmu(E, m)) * (1 - 1 / (1 + k * (1 - m)))
+    ftr = integrate.quad(f, -1, 1, epsrel=1e-13)[0] / integrate.quad(
+        lambda m: float(ph.kn_dsigma_dmu(E, m)), -1, 1, epsrel=1e-13)[0]
+    z = np.arange(33) * 0.5
+    n = r["n_hist"]
+    expect = n * E * (t[0] + t[1] * ftr) / mu * (np.exp(-mu * z[:-1]) - np.exp(-mu * z[1:]))
+    got = np.bincount(iz, weights=first["e"], minlength=32)
+    var = np.bincount(iz, weights=first["e"] ** 2, minlength=32)
+    zs = (got - expect) / np.sqrt(var)
+    assert np.sum(zs ** 2) < stats.chi2.ppf(1 - 1e-3, 32)
+
+
+# ---------------- direction update after a scatter ----------------
+
+@pytest.mark.parametrize("d", [(0.0, 0.0, 1.0), (0.0, 0.0, -1.0), (0.6, 0.0, 0.8),
+                               (0.3, -0.5, 0.1), (1e-4, 2e-4, 0.99999998)])
+def test_rotation_deflection_and_azimuth(d):
+    d = np.array(d) / np.linalg.norm(d)
+    rng = np.random.default_rng(3)
+    mus = rng.uniform(-1, 1, 2000)
+    phis = rng.uniform(0, 2 * np.pi, 2000)
+    out = np.array([O.rotate(d, m, p) for m, p in zip(mus, phis)])
+    assert np.allclose(np.linalg.norm(out, axis=1), 1.0, atol=1e-14)
+    # exact off the pole; inside |w| >= 1 - 1e-5 the frame takes d = (0, 0, +-1)
+    tol = 1e-12 if abs(d[2]) < 1 - 1e-5 else 2 * np.sqrt(1 - d[2] ** 2) + 1e-12
+    assert np.allclose(out @ d, mus, atol=tol)
+    # azimuth of the new direction around d is uniform
+    ref = np.array([1.0, 0, 0]) if abs(d[0]) < 0.9 else np.array([0, 1.0, 0])
+    e1 = ref - (ref @ d) * d
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(d, e1)
+    az = np.arctan2(out @ e2, out @ e1) % (2 * np.pi)
+    ok = np.abs(mus) < 0.999
+    assert stats.kstest(az[ok] / (2 * np.pi), "uniform").pvalue > 1e-3
+    # a fixed phi gives a fixed azimuth offset (rotation is rigid in phi)
+    a1 = O.rotate(d, 0.3, 0.4)
+    a2 = O.rotate(d, 0.3, 0.4 + np.pi / 2)
+    assert abs(((a1 - (a1 @ d) * d) @ (a2 - (a2 @ d) * d))) < max(tol, 1e-12)
