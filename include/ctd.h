@@ -1,0 +1,274 @@
+/*
+ * ctd.h -- C ABI of the MI355X (gfx950) Monte Carlo CT/CBCT imaging-dose
+ * transport library (libctd.so).
+ *
+ * Method: Jia, Yan, Gu & Jiang, "Fast Monte Carlo Simulation for
+ * Patient-specific CT/CBCT Imaging Dose Calculation" (arXiv 1109.3266):
+ * photons from a cone-beam or pencil source (Sec. 2.2.5 spectrum
+ * stratification, Sec. 2.2.6 source trajectory) are transported through a
+ * voxel phantom by Woodcock tracking (Sec. 2.1), interacting by photoelectric
+ * absorption, Compton and Rayleigh scattering with angles drawn from
+ * inverse-CDF "C/R surfaces" (Sec. 2.2.2-2.2.3), depositing electron energy
+ * locally; histories run in batches whose spread gives the per-voxel
+ * statistical uncertainty (Sec. 2.2.1).
+ *
+ * Conventions
+ *   - Every call returns an int32 status (CTD_OK or a negative CTD_E* code);
+ *     ctd_last_error() gives a message for the last failing call on a ctx.
+ *   - Handles are opaque and owned by the library; release them with the
+ *     matching *_release / *_destroy call.  One ctx per host thread, or
+ *     external locking.  No C++ exception crosses this interface.
+ *   - Device work is enqueued on the ctx's stream (ctd_set_stream), in order;
+ *     ctd_run* return once the work is enqueued unless stated otherwise.
+ *   - Arrays are C order.  Voxel arrays are [nz][ny][nx] (x fastest).
+ *   - Energies in keV, lengths in cm, densities in g/cm^3, mass attenuation
+ *     coefficients in cm^2/g.
+ *   - Deposited energy is tallied exactly in int64 fixed point with unit
+ *     q = 2^-24 keV.  Transport arithmetic is float32, so every deposit and
+ *     escape is an exact multiple of q and incident = deposited + escaped
+ *     holds exactly in q units.
+ *   - Determinism: tallies are a pure function of (inputs, seed, the sequence
+ *     of batch sizes); they do not depend on the stream, tuning, thread
+ *     count or work co-scheduled in a batched launch.
+ */
+#ifndef CTD_H
+#define CTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define CTD_OK 0
+#define CTD_EINVAL (-1)     /* invalid argument or input data */
+#define CTD_ENOMEM (-2)     /* device or host allocation failed */
+#define CTD_EDEVICE (-3)    /* HIP runtime error (message in ctd_last_error) */
+#define CTD_EOVERFLOW (-4)  /* fixed-point headroom: N * E_max * 2^24 >= 2^63 */
+#define CTD_EBUSY (-5)      /* object still referenced by a live case/request */
+#define CTD_ENOTFOUND (-6)  /* unknown ticket */
+#define CTD_ECANCELLED (-7) /* request was cancelled */
+#define CTD_ESTEPS (-8)     /* a history exceeded the step guard (majorant 0?) */
+
+#define CTD_MEM_HOST 0   /* pointer is host memory; the library copies it */
+#define CTD_MEM_DEVICE 1 /* pointer is device memory on the ctx's GPU */
+
+#define CTD_GEOM_PENCIL 0
+#define CTD_GEOM_CONE 1
+
+#define CTD_SIGMA_LOCAL 0 /* mean of s/D over voxels with D > f * D_max */
+#define CTD_SIGMA_PAPER 1 /* mean of s/D_max over voxels with D > f * D_max (Sec. 3.1) */
+
+typedef struct ctd_ctx ctd_ctx;
+typedef struct ctd_phantom ctd_phantom;
+typedef struct ctd_matset ctd_matset;
+typedef struct ctd_spectrum ctd_spectrum;
+typedef struct ctd_geometry ctd_geometry;
+typedef struct ctd_case ctd_case;
+typedef struct ctd_server ctd_server;
+
+/* Voxel grid: nx*ny*nz voxels of dx*dy*dz cm; origin = corner of voxel 0. */
+typedef struct {
+  int32_t nx, ny, nz, reserved;
+  double dx, dy, dz;
+  double origin[3];
+} ctd_grid;
+
+/* Uniform energy grid of the attenuation tables and surfaces:
+ * E_j = e0 + j*de, j = 0..ne-1 (keV).  Must cover [e_cut, E_max]. */
+typedef struct {
+  double e0, de;
+  int32_t ne, reserved;
+} ctd_egrid;
+
+/* Scan geometry (Sec. 2.2.6).  PENCIL: a fixed point src and direction dir.
+ * CONE: point source on the circle iso + sad*(sin phi, cos phi, 0), aimed at
+ * the field rectangle [a0,a1] x [b0,b1] (cm) spanned at the isocentre by
+ * e_lat = (cos phi, -sin phi, 0) and e_z; phi = phi0 + p*arc/n_proj for a
+ * projection p drawn uniformly (n_proj > 0), or phi0 + u*arc (n_proj = 0,
+ * continuous t). */
+typedef struct {
+  int32_t kind, n_proj;
+  double src[3], dir[3];
+  double sad, iso[3];
+  double a0, a1, b0, b1;
+  double phi0_deg, arc_deg;
+} ctd_geom;
+
+typedef struct {
+  double e_cut_kev;      /* photon absorption energy (Sec. 3.1 uses 1 keV) */
+  uint64_t seed;         /* Philox key */
+  int32_t n_batches;     /* batches per ctd_run (Sec. 2.2.1 uses 10), >= 2 */
+  int32_t rayleigh;      /* 1 = Rayleigh scattering on */
+  double sigma_rho_min;  /* voxels with rho >= this count as "inside" for sigma-bar */
+} ctd_params;
+
+typedef struct {
+  int64_t q_incident, q_deposited, q_escaped; /* units of 2^-24 keV */
+  uint64_t n_histories, n_missed, n_unscattered, n_cutoff;
+} ctd_balance;
+
+typedef struct {
+  double sigma_local;    /* CTD_SIGMA_LOCAL with f = 0.5 after the last run */
+  double sigma_paper;    /* CTD_SIGMA_PAPER with f = 0.2 after the last run */
+  uint64_t n_steps, n_real, n_photo, n_compton, n_rayleigh, n_deposits,
+      n_escapes, n_refills;
+  double transport_ms;   /* GPU time of the transport launches (HIP events) */
+  double fold_ms;        /* GPU time of the batch folds */
+  uint32_t n_batches;    /* batches folded so far */
+  uint32_t reserved;
+  uint64_t n_histories;  /* histories run so far */
+} ctd_stats;
+
+/* Launch configuration of the persistent transport kernel. */
+typedef struct {
+  int32_t block;         /* threads per workgroup: 64, 128, 256, 512 */
+  int32_t waves_per_simd;/* resident waves per SIMD to size the grid (1..8) */
+  int32_t refill_min;    /* refill a wave when >= this many lanes idle (1..64) */
+  int32_t chunk;         /* histories a wave claims per counter atomic (64..4096) */
+} ctd_tuning;
+
+/* Deposit/event record of the debug log (test use). type: 0 source, 1
+ * photoelectric, 2 Compton, 3 Rayleigh, 4 cutoff deposit, 5 escape, 6 miss. */
+typedef struct {
+  uint64_t h;
+  uint32_t seq, k;
+  int32_t type, reserved;
+  int64_t vox;
+  float e;   /* deposited (1,2,4), escaping (5,6) or source (0) energy, keV */
+  float E;   /* photon energy after the event */
+} ctd_event;
+
+/* ---------------- context ---------------- */
+
+/* Create a context on HIP device `device`.  CTD_EDEVICE if it does not exist. */
+int32_t ctd_create(ctd_ctx **out, int32_t device);
+/* Destroy the context (waits for its stream, frees what it owns). */
+int32_t ctd_destroy(ctd_ctx *ctx);
+/* Message of the last failing call on ctx (valid until the next call). */
+const char *ctd_last_error(const ctd_ctx *ctx);
+/* Enqueue all further work on the caller's hipStream_t (borrowed, never
+ * destroyed); NULL restores the context's own stream. */
+int32_t ctd_set_stream(ctd_ctx *ctx, void *hip_stream);
+
+/* ---------------- inputs ----------------
+ * Inverse-CDF surface construction (Sec. 2.2.2): pdf [n_e][n_mu] tabulated
+ * at n_mu equally spaced mu in [-1, 1] for each energy node.  Host FP64:
+ * cumulative distribution by the trapezoid rule, normalised, inverted at
+ * zeta_i = i/(n_zeta-1) by linear interpolation; out [n_e][n_zeta] float,
+ * caller-allocated.  CTD_EINVAL on sizes < 2 or a negative/zero-mass pdf. */
+int32_t ctd_surface_build(int32_t n_e, int32_t n_mu, const double *pdf, int32_t n_zeta,
+                          float *out);
+
+/* Voxel phantom (Sec. 2.2.1 inputs): material id mat[] and density rho[].
+ * mem = CTD_MEM_HOST or CTD_MEM_DEVICE; both arrays are read during the call
+ * only (the library keeps its own packed copy).  CTD_EINVAL on dims <= 0,
+ * spacing <= 0, rho not finite or < 0. */
+int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8_t *mat, const float *rho,
+                         int32_t mem, ctd_phantom **out);
+/* CTD_EBUSY while a case refers to it. */
+int32_t ctd_phantom_release(ctd_ctx *ctx, ctd_phantom *ph);
+
+/* Material tables (host memory, copied):
+ *   mu_rho   [M][ne][3]  photoelectric, Compton, Rayleigh mass attenuation;
+ *   comp     [1 or M][ne][n_zeta_c] Compton surface (one shared, or per
+ *            material when comp_per_mat = 1);
+ *   rayl     [M][ne][n_zeta_r] Rayleigh surfaces, or NULL.
+ * CTD_EINVAL if a surface is not non-decreasing in zeta or leaves [-1, 1],
+ * or a coefficient is negative / not finite. */
+int32_t ctd_materials_load(ctd_ctx *ctx, const ctd_egrid *eg, int32_t M, const float *mu_rho,
+                           const float *comp, int32_t comp_per_mat, int32_t n_zeta_c,
+                           const float *rayl, int32_t n_zeta_r, ctd_matset **out);
+int32_t ctd_materials_release(ctd_ctx *ctx, ctd_matset *ms);
+
+/* Stratified spectrum (Sec. 2.2.5): nbins bins [e_lo[j], e_lo[j]+width)
+ * with relative weights; width = 0 gives monoenergetic lines.  Copied.
+ * CTD_EINVAL on a negative weight or zero total. */
+int32_t ctd_spectrum_set(ctd_ctx *ctx, int32_t nbins, const double *e_lo, double width,
+                         const double *weight, ctd_spectrum **out);
+int32_t ctd_spectrum_release(ctd_ctx *ctx, ctd_spectrum *sp);
+
+/* Scan geometry (copied).  CTD_EINVAL on a zero direction, sad <= 0, an
+ * empty field, or n_proj < 0. */
+int32_t ctd_geometry_set(ctd_ctx *ctx, const ctd_geom *g, ctd_geometry **out);
+int32_t ctd_geometry_release(ctd_ctx *ctx, ctd_geometry *geo);
+
+/* ---------------- cases ----------------
+ * Bind one dose problem; computes the Woodcock majorant mu_max(E) (Sec. 2.1)
+ * from the phantom's per-material maximum density and allocates the batch
+ * tally T_b, S1 = sum_b T_b and S2 = sum_b T_b^2 (128-bit).
+ * CTD_EINVAL if a material id >= M, the energy grid does not cover
+ * [e_cut, E_max] or n_batches < 2; CTD_ENOMEM. */
+int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms, ctd_spectrum *sp,
+                        ctd_geometry *geo, const ctd_params *p, ctd_case **out);
+int32_t ctd_case_destroy(ctd_ctx *ctx, ctd_case *cs);
+/* Clear all tallies and counters; the next history id is 0 again. */
+int32_t ctd_case_reset(ctd_ctx *ctx, ctd_case *cs);
+/* Launch configuration for this case (defaults are chosen at creation). */
+int32_t ctd_set_tuning(ctd_ctx *ctx, ctd_case *cs, const ctd_tuning *t);
+int32_t ctd_get_tuning(ctd_ctx *ctx, const ctd_case *cs, ctd_tuning *t);
+/* Time a few launch configurations on `trial_histories` histories of this
+ * case (run on a scratch copy of the tallies; the case is left unchanged)
+ * and keep the fastest.  Synchronous. */
+int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histories, ctd_tuning *best);
+
+/* Run n_histories as n_batches equal batches (the first n mod n_batches
+ * one larger), continuing the case's history ids.  Each batch: transport
+ * launch, then fold S1 += T_b, S2 += T_b^2, T_b = 0 (Sec. 2.2.1).  Async.
+ * CTD_EOVERFLOW if the case's cumulative histories * E_max * 2^24 >= 2^63. */
+int32_t ctd_run(ctd_ctx *ctx, ctd_case *cs, uint64_t n_histories);
+
+/* Add batches of batch_histories until sigma-bar (sigma_kind, threshold
+ * dose_frac * D_max) <= target with >= n_batches batches, or max_histories
+ * is reached: a pilot of n_batches batches, then the estimated remainder
+ * (sigma ~ batches^-1/2), re-checked.  Synchronous; *achieved receives the
+ * final sigma-bar (may be NULL). */
+int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, double dose_frac,
+                         int32_t sigma_kind, uint64_t batch_histories, uint64_t max_histories,
+                         double *achieved);
+
+/* Batched engine: run n[i] histories of each case i in ONE persistent launch
+ * per batch round over a (case, history-chunk) task queue.  Per-case
+ * results equal ctd_run(cs[i], n[i]) bit for bit.  Async. */
+int32_t ctd_run_many(ctd_ctx *ctx, ctd_case *const *cs, const uint64_t *n, int32_t count);
+
+/* Wait until all work enqueued for the case (its stream) is complete. */
+int32_t ctd_sync(ctd_ctx *ctx, ctd_case *cs);
+
+/* Compute sigma-bar on the device over the folded batches.  Synchronous. */
+int32_t ctd_sigma(ctd_ctx *ctx, ctd_case *cs, int32_t sigma_kind, double dose_frac,
+                  double *out);
+
+/* ---------------- readout ----------------
+ * Exact integer sums (V-sized caller arrays, host): s1[v] = sum_b T_b[v];
+ * s2 as 128-bit (s2_hi:s2_lo) = sum_b T_b[v]^2; *n_batches batches folded.
+ * Synchronous. */
+int32_t ctd_read_tally(ctd_ctx *ctx, ctd_case *cs, int64_t *s1, uint64_t *s2_hi,
+                       uint64_t *s2_lo, uint32_t *n_batches);
+/* Dose per history [Gy] and the variance of that mean [Gy^2] per voxel, from
+ * the exact sums (batch means; numerator formed in 192-bit integers).  Voxels
+ * of zero density report 0.  Synchronous; needs >= 2 equal-size batches. */
+int32_t ctd_read_dose(ctd_ctx *ctx, ctd_case *cs, double *dose, double *var_of_mean);
+/* Device pointers of the case's S1 (int64 [V]) and S2 (uint64 [V][2], lo
+ * then hi), valid until the case is destroyed. */
+int32_t ctd_tally_device(ctd_ctx *ctx, ctd_case *cs, void **s1, void **s2);
+int32_t ctd_read_balance(ctd_ctx *ctx, ctd_case *cs, ctd_balance *out);
+int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out);
+/* Copy the case's majorant nodes mu_max[ne] (float, cm^-1). */
+int32_t ctd_read_majorant(ctd_ctx *ctx, ctd_case *cs, float *out);
+
+/* ---------------- debug log (tests) ----------------
+ * Arm event logging of histories [h0, h0+nh) for the following runs, with
+ * room for `capacity` events (0 disarms).  Read them back with
+ * ctd_read_event_log (*n = events recorded; may exceed capacity, in which
+ * case only `capacity` were kept). */
+int32_t ctd_debug_deposit_log(ctd_ctx *ctx, ctd_case *cs, uint64_t h0, uint64_t nh,
+                              uint64_t capacity);
+int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out, uint64_t capacity,
+                           uint64_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTD_H */

@@ -1,0 +1,1142 @@
+// C ABI of the MI355X imaging-dose transport library: handles, input
+// validation, device buffers, batch driver (Jia et al., Sec. 2.2.1: histories
+// split into N_b batches, one transport launch per batch, per-voxel mean and
+// uncertainty from the batches), run-to-sigma controller, batched engine,
+// readout and the launch-configuration tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctd_api_internal.h"
+#include "ctd_tables.h"
+
+using namespace ctd;
+
+// ------------------------------------------------------------ error helpers
+
+int ctd::set_err(ctd_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+int ctd::hip_err(ctd_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipSuccess) return CTD_OK;
+  if (e == hipErrorOutOfMemory)
+    return set_err(ctx, CTD_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return set_err(ctx, CTD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                        \
+  do {                                                           \
+    hipError_t e_ = (call);                                      \
+    if (e_ != hipSuccess) return ctd::hip_err((ctx), e_, #call); \
+  } while (0)
+
+#define NEED(ctx, cond, ...)                                   \
+  do {                                                         \
+    if (!(cond)) return ctd::set_err((ctx), CTD_EINVAL, __VA_ARGS__); \
+  } while (0)
+
+static void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+// --------------------------------------------------------------- context
+
+extern "C" int32_t ctd_create(ctd_ctx **out, int32_t device) {
+  if (!out) return CTD_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return CTD_EDEVICE;
+  }
+  ctd_ctx *ctx = new (std::nothrow) ctd_ctx();
+  if (!ctx) return CTD_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) {
+    delete ctx;
+    return CTD_EDEVICE;
+  }
+  ctx->stream = ctx->own;
+  ctx->n_cu = device_cu_count(device);
+  if (ctx->n_cu <= 0) ctx->n_cu = 256;
+  ctx->slots.resize(64);
+  if (hipMalloc(&ctx->sigma_scratch, sizeof(double) * (3 * kSigmaBlocks + 4)) != hipSuccess ||
+      hipHostMalloc(&ctx->sigma_host, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
+    ctd_destroy(ctx);
+    return CTD_ENOMEM;
+  }
+  *out = ctx;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_destroy(ctd_ctx *ctx) {
+  if (!ctx) return CTD_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->own) (void)hipStreamSynchronize(ctx->own);
+  for (auto &s : ctx->slots) {
+    if (s.ev) (void)hipEventDestroy(s.ev);
+    if (s.host) (void)hipHostFree(s.host);
+    dfree(s.dev);
+  }
+  dfree(ctx->sigma_scratch);
+  if (ctx->sigma_host) (void)hipHostFree(ctx->sigma_host);
+  if (ctx->own) (void)hipStreamDestroy(ctx->own);
+  delete ctx;
+  return CTD_OK;
+}
+
+extern "C" const char *ctd_last_error(const ctd_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+extern "C" int32_t ctd_set_stream(ctd_ctx *ctx, void *hip_stream) {
+  if (!ctx) return CTD_EINVAL;
+  ctx->stream = hip_stream ? (hipStream_t)hip_stream : ctx->own;
+  return CTD_OK;
+}
+
+// --------------------------------------------------------------- phantom
+
+extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8_t *mat,
+                                    const float *rho, int32_t mem, ctd_phantom **out) {
+  if (!ctx || !out) return CTD_EINVAL;
+  *out = nullptr;
+  NEED(ctx, g && mat && rho, "null argument");
+  NEED(ctx, g->nx > 0 && g->ny > 0 && g->nz > 0, "grid dimensions must be positive");
+  NEED(ctx, g->dx > 0 && g->dy > 0 && g->dz > 0, "voxel spacing must be positive");
+  NEED(ctx, mem == CTD_MEM_HOST || mem == CTD_MEM_DEVICE, "mem must be HOST or DEVICE");
+  const int64_t V = (int64_t)g->nx * g->ny * g->nz;
+  NEED(ctx, V < ((int64_t)1 << 31), "at most 2^31 - 1 voxels");
+  NEED(ctx, g->nx < (1 << 24) && g->ny < (1 << 24) && g->nz < (1 << 24), "axis too long");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctd_phantom *ph = new (std::nothrow) ctd_phantom();
+  if (!ph) return CTD_ENOMEM;
+  ph->ctx = ctx;
+  ph->g = *g;
+  ph->V = V;
+  uint8_t *dmat = nullptr;
+  float *drho = nullptr;
+  unsigned int *dstat = nullptr;
+  int rc = CTD_OK;
+  auto fail = [&](int code) {
+    dfree(dmat);
+    dfree(drho);
+    dfree(dstat);
+    dfree(ph->vox);
+    delete ph;
+    return code;
+  };
+  hipError_t e = hipMalloc(&ph->vox, sizeof(uint2) * V);
+  if (e != hipSuccess) return fail(hip_err(ctx, e, "phantom alloc"));
+  e = hipMalloc(&dstat, sizeof(unsigned int) * 514);
+  if (e != hipSuccess) return fail(hip_err(ctx, e, "phantom stats alloc"));
+  const uint8_t *pm = mat;
+  const float *pr = rho;
+  if (mem == CTD_MEM_HOST) {
+    if ((e = hipMalloc(&dmat, V)) != hipSuccess || (e = hipMalloc(&drho, 4 * V)) != hipSuccess)
+      return fail(hip_err(ctx, e, "phantom staging alloc"));
+    if ((e = hipMemcpyAsync(dmat, mat, V, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(drho, rho, 4 * V, hipMemcpyHostToDevice, ctx->stream)) != hipSuccess)
+      return fail(hip_err(ctx, e, "phantom upload"));
+    pm = dmat;
+    pr = drho;
+  }
+  if ((e = hipMemsetAsync(dstat, 0, sizeof(unsigned int) * 514, ctx->stream)) != hipSuccess)
+    return fail(hip_err(ctx, e, "phantom stats clear"));
+  if (launch_pack(pm, pr, ph->vox, V, dstat, ctx->stream) != 0)
+    return fail(hip_err(ctx, hipGetLastError(), "pack kernel"));
+  unsigned int hstat[514];
+  if ((e = hipMemcpyAsync(hstat, dstat, sizeof hstat, hipMemcpyDeviceToHost, ctx->stream)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+    return fail(hip_err(ctx, e, "phantom stats readback"));
+  if (hstat[513] != 0) {
+    rc = set_err(ctx, CTD_EINVAL, "%u voxels with a negative or non-finite density", hstat[513]);
+    return fail(rc);
+  }
+  ph->max_mat = (int)hstat[512];
+  for (int m = 0; m < 256; ++m) {
+    float f;
+    std::memcpy(&f, &hstat[m], 4);
+    ph->rho_max[m] = (double)f;
+    ph->present[m] = hstat[256 + m] != 0;
+  }
+  dfree(dmat);
+  dfree(drho);
+  dmat = nullptr;
+  drho = nullptr;
+  dfree(dstat);
+  *out = ph;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_phantom_release(ctd_ctx *ctx, ctd_phantom *ph) {
+  if (!ctx || !ph) return CTD_EINVAL;
+  if (ph->refs > 0) return set_err(ctx, CTD_EBUSY, "phantom is used by %d case(s)", ph->refs);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  dfree(ph->vox);
+  delete ph;
+  return CTD_OK;
+}
+
+// ------------------------------------------------------------- materials
+
+static int upload(ctd_ctx *ctx, void **dst, const void *src, size_t bytes) {
+  HIPCHK(ctx, hipMalloc(dst, bytes));
+  HIPCHK(ctx, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return CTD_OK;
+}
+
+static bool surface_ok(const float *S, int ne, int nz) {
+  for (int j = 0; j < ne; ++j) {
+    const float *r = S + (size_t)j * nz;
+    for (int i = 0; i < nz; ++i) {
+      if (!(r[i] >= -1.0f && r[i] <= 1.0f)) return false;
+      if (i > 0 && r[i] < r[i - 1]) return false;
+    }
+  }
+  return true;
+}
+
+// [ns][ne][nz] rows -> [ns][ne-1][nz-1] bilinear cells
+static std::vector<float4> quad_cells(const float *S, int ns, int ne, int nz) {
+  std::vector<float4> q((size_t)ns * (ne - 1) * (nz - 1));
+  for (int s = 0; s < ns; ++s)
+    for (int j = 0; j + 1 < ne; ++j) {
+      const float *r0 = S + ((size_t)s * ne + j) * nz;
+      const float *r1 = r0 + nz;
+      for (int i = 0; i + 1 < nz; ++i)
+        q[((size_t)s * (ne - 1) + j) * (nz - 1) + i] =
+            make_float4(r0[i], r0[i + 1], r1[i], r1[i + 1]);
+    }
+  return q;
+}
+
+extern "C" int32_t ctd_materials_load(ctd_ctx *ctx, const ctd_egrid *eg, int32_t M,
+                                      const float *mu_rho, const float *comp,
+                                      int32_t comp_per_mat, int32_t n_zeta_c, const float *rayl,
+                                      int32_t n_zeta_r, ctd_matset **out) {
+  if (!ctx || !out) return CTD_EINVAL;
+  *out = nullptr;
+  NEED(ctx, eg && mu_rho && comp, "null argument");
+  NEED(ctx, M >= 1 && M <= 255, "1 <= M <= 255 materials");
+  NEED(ctx, eg->ne >= 2 && eg->de > 0 && std::isfinite(eg->e0), "bad energy grid");
+  NEED(ctx, n_zeta_c >= 2 && (!rayl || n_zeta_r >= 2), "surfaces need >= 2 zeta nodes");
+  const int ne = eg->ne;
+  for (size_t i = 0; i < (size_t)M * ne * 3; ++i)
+    NEED(ctx, mu_rho[i] >= 0.0f && std::isfinite(mu_rho[i]),
+         "attenuation coefficient %zu is negative or not finite", i);
+  const int ncomp = comp_per_mat ? M : 1;
+  NEED(ctx, surface_ok(comp, ncomp * ne, n_zeta_c),
+       "Compton surface leaves [-1,1] or decreases in zeta");
+  if (rayl)
+    NEED(ctx, surface_ok(rayl, M * ne, n_zeta_r),
+         "Rayleigh surface leaves [-1,1] or decreases in zeta");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctd_matset *ms = new (std::nothrow) ctd_matset();
+  if (!ms) return CTD_ENOMEM;
+  ms->eg = *eg;
+  ms->M = M;
+  ms->ncomp = ncomp;
+  ms->nzc = n_zeta_c;
+  ms->nzr = rayl ? n_zeta_r : 0;
+  ms->mu_rho.assign(mu_rho, mu_rho + (size_t)M * ne * 3);
+  std::vector<float4> mu4((size_t)M * ne);
+  for (size_t i = 0; i < mu4.size(); ++i)
+    mu4[i] = make_float4(mu_rho[3 * i], mu_rho[3 * i + 1], mu_rho[3 * i + 2], 0.0f);
+  int rc = upload(ctx, (void **)&ms->d_mu, mu4.data(), sizeof(float4) * mu4.size());
+  if (rc == CTD_OK) {
+    auto q = quad_cells(comp, ncomp, ne, n_zeta_c);
+    rc = upload(ctx, (void **)&ms->d_comp, q.data(), sizeof(float4) * q.size());
+  }
+  if (rc == CTD_OK && rayl) {
+    auto q = quad_cells(rayl, M, ne, n_zeta_r);
+    rc = upload(ctx, (void **)&ms->d_rayl, q.data(), sizeof(float4) * q.size());
+  }
+  if (rc != CTD_OK) {
+    dfree(ms->d_mu);
+    dfree(ms->d_comp);
+    dfree(ms->d_rayl);
+    delete ms;
+    return rc;
+  }
+  *out = ms;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_materials_release(ctd_ctx *ctx, ctd_matset *ms) {
+  if (!ctx || !ms) return CTD_EINVAL;
+  if (ms->refs > 0) return set_err(ctx, CTD_EBUSY, "material set is used by %d case(s)", ms->refs);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  dfree(ms->d_mu);
+  dfree(ms->d_comp);
+  dfree(ms->d_rayl);
+  delete ms;
+  return CTD_OK;
+}
+
+// ------------------------------------------------------ spectrum, geometry
+
+extern "C" int32_t ctd_spectrum_set(ctd_ctx *ctx, int32_t nbins, const double *e_lo, double width,
+                                    const double *weight, ctd_spectrum **out) {
+  if (!ctx || !out) return CTD_EINVAL;
+  *out = nullptr;
+  NEED(ctx, nbins >= 1 && nbins <= 4096 && e_lo && weight, "1..4096 bins required");
+  NEED(ctx, width >= 0.0 && std::isfinite(width), "bin width must be >= 0");
+  double W = 0.0;
+  for (int j = 0; j < nbins; ++j) {
+    NEED(ctx, weight[j] >= 0.0 && std::isfinite(weight[j]), "weight %d is negative", j);
+    NEED(ctx, e_lo[j] > 0.0 && std::isfinite(e_lo[j]), "bin energy %d must be positive", j);
+    W += weight[j];
+  }
+  NEED(ctx, W > 0.0, "spectrum weights sum to zero");
+  ctd_spectrum *sp = new (std::nothrow) ctd_spectrum();
+  if (!sp) return CTD_ENOMEM;
+  sp->lo.assign(e_lo, e_lo + nbins);
+  sp->w.assign(weight, weight + nbins);
+  sp->width = width;
+  *out = sp;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_spectrum_release(ctd_ctx *ctx, ctd_spectrum *sp) {
+  if (!ctx || !sp) return CTD_EINVAL;
+  if (sp->refs > 0) return set_err(ctx, CTD_EBUSY, "spectrum is used by %d case(s)", sp->refs);
+  delete sp;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_geometry_set(ctd_ctx *ctx, const ctd_geom *g, ctd_geometry **out) {
+  if (!ctx || !out) return CTD_EINVAL;
+  *out = nullptr;
+  NEED(ctx, g, "null geometry");
+  NEED(ctx, g->kind == CTD_GEOM_PENCIL || g->kind == CTD_GEOM_CONE, "unknown geometry kind");
+  if (g->kind == CTD_GEOM_PENCIL) {
+    const double n = std::sqrt(g->dir[0] * g->dir[0] + g->dir[1] * g->dir[1] +
+                               g->dir[2] * g->dir[2]);
+    NEED(ctx, n > 0 && std::isfinite(n), "pencil direction is zero");
+  } else {
+    NEED(ctx, g->sad > 0 && std::isfinite(g->sad), "sad must be positive");
+    NEED(ctx, g->a1 > g->a0 && g->b1 > g->b0, "empty field rectangle");
+    NEED(ctx, g->n_proj >= 0 && g->n_proj <= (1 << 20), "0 <= n_proj <= 2^20");
+  }
+  ctd_geometry *geo = new (std::nothrow) ctd_geometry();
+  if (!geo) return CTD_ENOMEM;
+  geo->g = *g;
+  if (g->kind == CTD_GEOM_CONE && g->n_proj > 0) {
+    geo->proj_sc.resize((size_t)g->n_proj);
+    const double d2r = 0.017453292519943295769236907684886;
+    for (int p = 0; p < g->n_proj; ++p) {
+      const double phi = (g->phi0_deg + (double)p * g->arc_deg / (double)g->n_proj) * d2r;
+      geo->proj_sc[p] = make_float2((float)std::sin(phi), (float)std::cos(phi));
+    }
+  }
+  *out = geo;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_geometry_release(ctd_ctx *ctx, ctd_geometry *geo) {
+  if (!ctx || !geo) return CTD_EINVAL;
+  if (geo->refs > 0) return set_err(ctx, CTD_EBUSY, "geometry is used by %d case(s)", geo->refs);
+  delete geo;
+  return CTD_OK;
+}
+
+// ------------------------------------------------------------------ cases
+
+static double e_max_of(const ctd_spectrum *sp) {
+  double m = 0.0;
+  for (double lo : sp->lo) m = std::max(m, lo + sp->width);
+  return m;
+}
+
+int ctd::upload_desc(ctd_ctx *ctx, ctd_case *cs) {
+  HIPCHK(ctx, hipMemcpyAsync(cs->d_desc, &cs->desc, sizeof(CaseDev), hipMemcpyHostToDevice,
+                             ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms,
+                                   ctd_spectrum *sp, ctd_geometry *geo, const ctd_params *p,
+                                   ctd_case **out) {
+  if (!ctx || !out) return CTD_EINVAL;
+  *out = nullptr;
+  NEED(ctx, ph && ms && sp && geo && p, "null argument");
+  NEED(ctx, p->n_batches >= 2, "n_batches must be >= 2");
+  NEED(ctx, ph->max_mat < ms->M, "phantom uses material %d but only %d are loaded", ph->max_mat,
+       ms->M);
+  const double emax = e_max_of(sp);
+  const ctd_egrid &eg = ms->eg;
+  const double etop = eg.e0 + (eg.ne - 1) * eg.de;
+  NEED(ctx, p->e_cut_kev >= eg.e0 && p->e_cut_kev > 0.0, "e_cut %.6g below the energy grid",
+       p->e_cut_kev);
+  NEED(ctx, emax <= etop, "spectrum reaches %.6g keV beyond the energy grid (%.6g)", emax, etop);
+  NEED(ctx, emax < 255.0, "spectrum energies must stay below 255 keV");
+  NEED(ctx, !p->rayleigh || ms->d_rayl, "Rayleigh on but no Rayleigh surfaces loaded");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  ctd_case *cs = new (std::nothrow) ctd_case();
+  if (!cs) return CTD_ENOMEM;
+  cs->ctx = ctx;
+  cs->ph = ph;
+  cs->ms = ms;
+  cs->sp = sp;
+  cs->geo = geo;
+  cs->p = *p;
+  cs->e_max = emax;
+  cs->tune = default_tuning();
+  // majorant from per-material maximum density (Sec. 2.1)
+  std::vector<double> rmax((size_t)ms->M, 0.0);
+  bool pres[256];
+  for (int m = 0; m < ms->M; ++m) {
+    rmax[m] = ph->rho_max[m];
+    pres[m] = ph->present[m];
+  }
+  int rc = CTD_OK;
+  cs->mu_max.resize((size_t)eg.ne);
+  majorant_fp64(eg.ne, ms->M, ms->mu_rho.data(), rmax.data(), pres, p->rayleigh != 0,
+                cs->mu_max.data());
+  bool any = false;
+  for (float v : cs->mu_max) any |= v > 0.0f;
+  if (!any) {
+    delete cs;
+    return set_err(ctx, CTD_EINVAL, "majorant is zero: empty phantom");
+  }
+  const int64_t V = ph->V;
+  auto cleanup = [&](int code) {
+    free_case_buffers(cs);
+    delete cs;
+    return code;
+  };
+  hipError_t e;
+  std::vector<float> blo(sp->lo.begin(), sp->lo.end());
+  if ((e = hipMalloc(&cs->d_tally, 8 * V)) != hipSuccess ||
+      (e = hipMalloc(&cs->d_s1, 8 * V)) != hipSuccess ||
+      (e = hipMalloc(&cs->d_s2, 16 * V)) != hipSuccess ||
+      (e = hipMalloc(&cs->d_acc, 8 * ACC_COUNT)) != hipSuccess ||
+      (e = hipMalloc(&cs->d_desc, sizeof(CaseDev))) != hipSuccess ||
+      (e = hipMalloc(&cs->d_mu_max, 4 * eg.ne)) != hipSuccess ||
+      (e = hipMalloc(&cs->d_bin_lo, 4 * blo.size())) != hipSuccess)
+    return cleanup(hip_err(ctx, e, "case alloc"));
+  if (!geo->proj_sc.empty() &&
+      (e = hipMalloc(&cs->d_proj, sizeof(float2) * geo->proj_sc.size())) != hipSuccess)
+    return cleanup(hip_err(ctx, e, "case alloc"));
+  if ((e = hipMemcpy(cs->d_mu_max, cs->mu_max.data(), 4 * eg.ne, hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(cs->d_bin_lo, blo.data(), 4 * blo.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (cs->d_proj && (e = hipMemcpy(cs->d_proj, geo->proj_sc.data(),
+                                    sizeof(float2) * geo->proj_sc.size(),
+                                    hipMemcpyHostToDevice)) != hipSuccess))
+    return cleanup(hip_err(ctx, e, "case upload"));
+  if (launch_zero(cs->d_tally, 8 * V, ctx->stream) || launch_zero(cs->d_s1, 8 * V, ctx->stream) ||
+      launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
+      launch_zero(cs->d_acc, 8 * ACC_COUNT, ctx->stream))
+    return cleanup(hip_err(ctx, hipGetLastError(), "case clear"));
+  fill_desc(cs);
+  if ((rc = upload_desc(ctx, cs)) != CTD_OK) return cleanup(rc);
+  ph->refs++;
+  ms->refs++;
+  sp->refs++;
+  geo->refs++;
+  *out = cs;
+  return CTD_OK;
+}
+
+void ctd::fill_desc(ctd_case *cs) {
+  CaseDev &d = cs->desc;
+  std::memset(&d, 0, sizeof d);
+  const ctd_grid &g = cs->ph->g;
+  d.nx = g.nx;
+  d.ny = g.ny;
+  d.nz = g.nz;
+  d.nmat = cs->ms->M;
+  d.fnx = (float)g.nx;
+  d.fny = (float)g.ny;
+  d.fnz = (float)g.nz;
+  d.inv_dx = (float)(1.0 / g.dx);
+  d.inv_dy = (float)(1.0 / g.dy);
+  d.inv_dz = (float)(1.0 / g.dz);
+  d.ox = (float)g.origin[0];
+  d.oy = (float)g.origin[1];
+  d.oz = (float)g.origin[2];
+  d.vox = cs->ph->vox;
+  d.V = cs->ph->V;
+  const ctd_matset *ms = cs->ms;
+  d.ne = ms->eg.ne;
+  d.nzc = ms->nzc;
+  d.nzr = ms->nzr;
+  d.rayleigh = cs->p.rayleigh ? 1 : 0;
+  d.e0 = (float)ms->eg.e0;
+  d.inv_de = (float)(1.0 / ms->eg.de);
+  d.e_cut = (float)cs->p.e_cut_kev;
+  d.mu_rho = ms->d_mu;
+  d.mu_max = cs->d_mu_max;
+  d.comp_quad = ms->d_comp;
+  d.rayl_quad = ms->d_rayl;
+  d.comp_per_mat = ms->ncomp > 1 ? 1 : 0;
+  d.nbins = (int)cs->sp->lo.size();
+  d.bin_width = (float)cs->sp->width;
+  d.bin_lo = cs->d_bin_lo;
+  const ctd_geom &G = cs->geo->g;
+  d.kind = G.kind;
+  d.nproj = G.kind == CTD_GEOM_CONE ? G.n_proj : 0;
+  d.sad = (float)G.sad;
+  if (G.kind == CTD_GEOM_PENCIL) {
+    const double n = std::sqrt(G.dir[0] * G.dir[0] + G.dir[1] * G.dir[1] + G.dir[2] * G.dir[2]);
+    for (int a = 0; a < 3; ++a) {
+      d.src[a] = (float)G.src[a];
+      d.dir[a] = (float)(G.dir[a] / n);
+    }
+  }
+  for (int a = 0; a < 3; ++a) d.iso[a] = (float)G.iso[a];
+  d.a0 = (float)G.a0;
+  d.a1 = (float)G.a1;
+  d.b0 = (float)G.b0;
+  d.b1 = (float)G.b1;
+  d.phi0_turns = (float)(G.phi0_deg / 360.0);
+  d.arc_turns = (float)(G.arc_deg / 360.0);
+  d.proj_sc = cs->d_proj;
+  d.key0 = (uint32_t)cs->p.seed;
+  d.key1 = (uint32_t)(cs->p.seed >> 32);
+  d.tally = cs->d_tally;
+  d.s1 = cs->d_s1;
+  d.s2 = cs->d_s2;
+  d.acc = cs->d_acc;
+  d.log = cs->d_log;
+  d.log_n = cs->d_log_n;
+  d.log_h0 = cs->log_h0;
+  d.log_h1 = cs->log_h1;
+  d.log_cap = cs->log_cap;
+}
+
+void ctd::free_case_buffers(ctd_case *cs) {
+  dfree(cs->d_tally);
+  dfree(cs->d_s1);
+  dfree(cs->d_s2);
+  dfree(cs->d_acc);
+  dfree(cs->d_desc);
+  dfree(cs->d_mu_max);
+  dfree(cs->d_bin_lo);
+  dfree(cs->d_proj);
+  dfree(cs->d_log);
+  dfree(cs->d_log_n);
+  for (auto &t : cs->timing) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.c);
+  }
+  cs->timing.clear();
+}
+
+extern "C" int32_t ctd_case_destroy(ctd_ctx *ctx, ctd_case *cs) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  if (cs->in_server) return set_err(ctx, CTD_EBUSY, "case is queued in a server");
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_case_buffers(cs);
+  cs->ph->refs--;
+  cs->ms->refs--;
+  cs->sp->refs--;
+  cs->geo->refs--;
+  delete cs;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_case_reset(ctd_ctx *ctx, ctd_case *cs) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const int64_t V = cs->ph->V;
+  if (launch_zero(cs->d_tally, 8 * V, ctx->stream) || launch_zero(cs->d_s1, 8 * V, ctx->stream) ||
+      launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
+      launch_zero(cs->d_acc, 8 * ACC_COUNT, ctx->stream))
+    return hip_err(ctx, hipGetLastError(), "case reset");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  cs->h_next = 0;
+  cs->batches = 0;
+  cs->batch_sizes.clear();
+  cs->sigma_local = cs->sigma_paper = NAN;
+  for (auto &t : cs->timing) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.c);
+  }
+  cs->timing.clear();
+  cs->transport_ms = cs->fold_ms = 0.0;
+  return CTD_OK;
+}
+
+ctd_tuning ctd::default_tuning() {
+  ctd_tuning t;
+  t.block = 256;
+  t.waves_per_simd = 4;
+  t.refill_min = 16;
+  t.chunk = 256;
+  return t;
+}
+
+static bool tuning_ok(const ctd_tuning &t) {
+  return (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
+         t.waves_per_simd >= 1 && t.waves_per_simd <= 8 && t.refill_min >= 1 &&
+         t.refill_min <= 64 && t.chunk >= 64 && t.chunk <= 65536;
+}
+
+extern "C" int32_t ctd_set_tuning(ctd_ctx *ctx, ctd_case *cs, const ctd_tuning *t) {
+  if (!ctx || !cs || !t) return CTD_EINVAL;
+  NEED(ctx, tuning_ok(*t), "tuning out of range");
+  cs->tune = *t;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_get_tuning(ctd_ctx *ctx, const ctd_case *cs, ctd_tuning *t) {
+  if (!ctx || !cs || !t) return CTD_EINVAL;
+  *t = cs->tune;
+  return CTD_OK;
+}
+
+// ------------------------------------------------------------- launching
+
+// Stage one round (RoundCase table, bin prefixes, chunk counter) through a
+// pinned slot and launch the transport kernel on the ctx stream.
+int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const ctd_tuning &t,
+                      bool with_log) {
+  const int nrc = (int)items.size();
+  if (nrc == 0) return CTD_OK;
+  size_t bytes = sizeof(RoundCase) * nrc;
+  std::vector<size_t> poff((size_t)nrc);
+  for (int i = 0; i < nrc; ++i) {
+    poff[i] = bytes;
+    bytes += 8 * (items[i].prefix.size());
+  }
+  const size_t ctr_off = (bytes + 255) & ~(size_t)255;
+  bytes = ctr_off + 256;
+  ctd_ctx::Slot &s = ctx->slots[ctx->next_slot];
+  ctx->next_slot = (ctx->next_slot + 1) % ctx->slots.size();
+  if (s.ev) HIPCHK(ctx, hipEventSynchronize(s.ev));
+  else HIPCHK(ctx, hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+  if (s.cap < bytes) {
+    if (s.host) (void)hipHostFree(s.host);
+    dfree(s.dev);
+    s.host = nullptr;
+    s.dev = nullptr;
+    s.cap = 0;
+    const size_t cap = std::max(bytes * 2, (size_t)65536);
+    HIPCHK(ctx, hipHostMalloc(&s.host, cap, hipHostMallocDefault));
+    HIPCHK(ctx, hipMalloc(&s.dev, cap));
+    s.cap = cap;
+  }
+  char *h = (char *)s.host;
+  char *d = (char *)s.dev;
+  RoundCase *rc = (RoundCase *)h;
+  uint64_t chunks = 0;
+  for (int i = 0; i < nrc; ++i) {
+    rc[i].cd = items[i].cd;
+    rc[i].prefix = (const unsigned long long *)(d + poff[i]);
+    rc[i].h_begin = items[i].h_begin;
+    rc[i].n = items[i].n;
+    rc[i].chunk_begin = chunks;
+    rc[i].pad = 0;
+    chunks += (items[i].n + (uint64_t)t.chunk - 1) / (uint64_t)t.chunk;
+    std::memcpy(h + poff[i], items[i].prefix.data(), 8 * items[i].prefix.size());
+  }
+  std::memset(h + ctr_off, 0, 256);
+  HIPCHK(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
+  LaunchCfg cfg;
+  cfg.block = t.block;
+  const int waves_per_wg = t.block / 64;
+  cfg.grid = std::max(1, ctx->n_cu * 4 * t.waves_per_simd / waves_per_wg);
+  cfg.refill_min = t.refill_min;
+  cfg.chunk = t.chunk;
+  if (chunks > 0 &&
+      launch_transport((const RoundCase *)d, nrc, chunks, (unsigned long long *)(d + ctr_off),
+                       cfg, with_log, ctx->stream) != 0)
+    return hip_err(ctx, hipGetLastError(), "transport launch");
+  HIPCHK(ctx, hipEventRecord(s.ev, ctx->stream));
+  return CTD_OK;
+}
+
+int ctd::batch_prefix(ctd_ctx *ctx, const ctd_case *cs, uint64_t n,
+                      std::vector<unsigned long long> &prefix) {
+  const int nb = (int)cs->sp->w.size();
+  std::vector<uint64_t> cnt((size_t)nb);
+  if (alloc_bins(n, nb, cs->sp->w.data(), cnt.data()) != CTD_OK)
+    return set_err(ctx, CTD_EINVAL, "bin allocation failed");
+  prefix.resize((size_t)nb + 1);
+  prefix[0] = 0;
+  for (int j = 0; j < nb; ++j) prefix[j + 1] = prefix[j] + cnt[j];
+  return CTD_OK;
+}
+
+static int check_headroom(ctd_ctx *ctx, const ctd_case *cs, uint64_t more) {
+  const double total = (double)cs->h_next + (double)more;
+  if (total * cs->e_max * 16777216.0 >= 9.2e18)
+    return set_err(ctx, CTD_EOVERFLOW,
+                   "%.3g histories at %.4g keV exceed the int64 fixed-point range", total,
+                   cs->e_max);
+  return CTD_OK;
+}
+
+// Enqueue one round over several cases (each with its own batch size), then
+// fold every participating case.
+int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vector<uint64_t> &n,
+                   const ctd_tuning &t) {
+  std::vector<RoundItem> items;
+  bool with_log = false;
+  for (size_t i = 0; i < cases.size(); ++i) {
+    if (n[i] == 0) continue;
+    RoundItem it;
+    it.cd = cases[i]->d_desc;
+    it.h_begin = cases[i]->h_next;
+    it.n = n[i];
+    int rc = batch_prefix(ctx, cases[i], n[i], it.prefix);
+    if (rc != CTD_OK) return rc;
+    items.push_back(std::move(it));
+    with_log |= cases[i]->log_cap > 0;
+  }
+  if (items.empty()) return CTD_OK;
+  ctd_case *first = cases[0];
+  ctd_case::Timing tm{};
+  const bool timed = cases.size() == 1;
+  if (timed) {
+    HIPCHK(ctx, hipEventCreate(&tm.a));
+    HIPCHK(ctx, hipEventCreate(&tm.b));
+    HIPCHK(ctx, hipEventCreate(&tm.c));
+    HIPCHK(ctx, hipEventRecord(tm.a, ctx->stream));
+  }
+  int rc = submit_round(ctx, items, t, with_log);
+  if (rc != CTD_OK) return rc;
+  if (timed) HIPCHK(ctx, hipEventRecord(tm.b, ctx->stream));
+  for (size_t i = 0; i < cases.size(); ++i) {
+    if (n[i] == 0) continue;
+    ctd_case *cs = cases[i];
+    if (launch_fold(cs->d_tally, cs->d_s1, cs->d_s2, cs->ph->V, ctx->stream) != 0)
+      return hip_err(ctx, hipGetLastError(), "fold launch");
+    cs->h_next += n[i];
+    cs->batches += 1;
+    cs->batch_sizes.push_back(n[i]);
+  }
+  if (timed) {
+    HIPCHK(ctx, hipEventRecord(tm.c, ctx->stream));
+    first->timing.push_back(tm);
+  }
+  return CTD_OK;
+}
+
+std::vector<uint64_t> ctd::split_batches(uint64_t n, int nb) {
+  std::vector<uint64_t> v((size_t)nb, n / (uint64_t)nb);
+  for (uint64_t b = 0; b < n % (uint64_t)nb; ++b) v[b] += 1;
+  return v;
+}
+
+extern "C" int32_t ctd_run(ctd_ctx *ctx, ctd_case *cs, uint64_t n_histories) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  int rc = check_headroom(ctx, cs, n_histories);
+  if (rc != CTD_OK) return rc;
+  if (n_histories == 0) return CTD_OK;
+  const auto sizes = split_batches(n_histories, cs->p.n_batches);
+  std::vector<ctd_case *> one{cs};
+  for (uint64_t nb : sizes) {
+    if (nb == 0) continue;
+    rc = run_round(ctx, one, std::vector<uint64_t>{nb}, cs->tune);
+    if (rc != CTD_OK) return rc;
+  }
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_run_many(ctd_ctx *ctx, ctd_case *const *cs, const uint64_t *n,
+                                int32_t count) {
+  if (!ctx || !cs || !n || count < 1) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  std::vector<std::vector<uint64_t>> sizes((size_t)count);
+  size_t rounds = 0;
+  for (int i = 0; i < count; ++i) {
+    NEED(ctx, cs[i], "null case %d", i);
+    for (int j = 0; j < i; ++j) NEED(ctx, cs[j] != cs[i], "case %d listed twice", i);
+    int rc = check_headroom(ctx, cs[i], n[i]);
+    if (rc != CTD_OK) return rc;
+    if (n[i]) sizes[i] = split_batches(n[i], cs[i]->p.n_batches);
+    rounds = std::max(rounds, sizes[i].size());
+  }
+  const ctd_tuning t = cs[0]->tune;
+  std::vector<ctd_case *> cases(cs, cs + count);
+  for (size_t r = 0; r < rounds; ++r) {
+    std::vector<uint64_t> nr((size_t)count, 0);
+    for (int i = 0; i < count; ++i)
+      if (r < sizes[i].size()) nr[i] = sizes[i][r];
+    int rc = run_round(ctx, cases, nr, t);
+    if (rc != CTD_OK) return rc;
+  }
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_sync(ctd_ctx *ctx, ctd_case *cs) {
+  (void)cs;
+  if (!ctx) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return CTD_OK;
+}
+
+int ctd::sigma_now(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *out) {
+  if (cs->batches < 2) return set_err(ctx, CTD_EINVAL, "sigma needs >= 2 folded batches");
+  double rho_min = cs->p.sigma_rho_min;
+  double *out_dev = ctx->sigma_scratch + 3 * kSigmaBlocks;
+  if (launch_sigma(cs->d_s1, cs->d_s2, cs->ph->vox, cs->ph->V, cs->batches, rho_min, frac, kind,
+                   ctx->sigma_scratch, kSigmaBlocks, out_dev, ctx->stream) != 0)
+    return hip_err(ctx, hipGetLastError(), "sigma launch");
+  HIPCHK(ctx, hipMemcpyAsync(ctx->sigma_host, out_dev, 3 * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  *out = ctx->sigma_host[0];
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_sigma(ctd_ctx *ctx, ctd_case *cs, int32_t sigma_kind, double dose_frac,
+                             double *out) {
+  if (!ctx || !cs || !out) return CTD_EINVAL;
+  NEED(ctx, sigma_kind == CTD_SIGMA_LOCAL || sigma_kind == CTD_SIGMA_PAPER, "bad sigma kind");
+  NEED(ctx, dose_frac >= 0.0 && dose_frac < 1.0, "dose_frac must be in [0,1)");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  return sigma_now(ctx, cs, sigma_kind, dose_frac, out);
+}
+
+int ctd::run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count) {
+  int rc = check_headroom(ctx, cs, batch * count);
+  if (rc != CTD_OK) return rc;
+  std::vector<ctd_case *> one{cs};
+  for (uint64_t b = 0; b < count; ++b) {
+    rc = run_round(ctx, one, std::vector<uint64_t>{batch}, cs->tune);
+    if (rc != CTD_OK) return rc;
+  }
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, double dose_frac,
+                                    int32_t sigma_kind, uint64_t batch_histories,
+                                    uint64_t max_histories, double *achieved) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  NEED(ctx, target > 0.0, "target must be positive");
+  NEED(ctx, batch_histories > 0, "batch_histories must be positive");
+  NEED(ctx, sigma_kind == CTD_SIGMA_LOCAL || sigma_kind == CTD_SIGMA_PAPER, "bad sigma kind");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const uint64_t max_b = std::max<uint64_t>(max_histories / batch_histories, 2);
+  uint64_t have = cs->batches;
+  const uint64_t pilot = (uint64_t)cs->p.n_batches;
+  int rc = CTD_OK;
+  if (have < pilot) {
+    rc = run_batches(ctx, cs, batch_histories, std::min(pilot - have, max_b - std::min(max_b, have)));
+    if (rc != CTD_OK) return rc;
+  }
+  double sig = INFINITY;
+  for (;;) {
+    rc = sigma_now(ctx, cs, sigma_kind, dose_frac, &sig);
+    if (rc != CTD_OK) return rc;
+    have = cs->batches;
+    if (sig <= target || have >= max_b) break;
+    // sigma ~ batches^-1/2 at fixed batch size
+    const double want = std::ceil((double)have * (sig / target) * (sig / target) * 1.02);
+    uint64_t more = (uint64_t)std::max(1.0, want - (double)have);
+    more = std::min(more, max_b - have);
+    rc = run_batches(ctx, cs, batch_histories, more);
+    if (rc != CTD_OK) return rc;
+  }
+  if (sigma_kind == CTD_SIGMA_LOCAL) cs->sigma_local = sig; else cs->sigma_paper = sig;
+  if (achieved) *achieved = sig;
+  return CTD_OK;
+}
+
+// ---------------------------------------------------------------- readout
+
+extern "C" int32_t ctd_tally_device(ctd_ctx *ctx, ctd_case *cs, void **s1, void **s2) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  if (s1) *s1 = cs->d_s1;
+  if (s2) *s2 = cs->d_s2;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_read_tally(ctd_ctx *ctx, ctd_case *cs, int64_t *s1, uint64_t *s2_hi,
+                                  uint64_t *s2_lo, uint32_t *n_batches) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const int64_t V = cs->ph->V;
+  if (s1) HIPCHK(ctx, hipMemcpy(s1, cs->d_s1, 8 * V, hipMemcpyDeviceToHost));
+  if (s2_hi || s2_lo) {
+    std::vector<uint64_t> s2((size_t)V * 2);
+    HIPCHK(ctx, hipMemcpy(s2.data(), cs->d_s2, 16 * V, hipMemcpyDeviceToHost));
+    for (int64_t v = 0; v < V; ++v) {
+      if (s2_lo) s2_lo[v] = s2[2 * v];
+      if (s2_hi) s2_hi[v] = s2[2 * v + 1];
+    }
+  }
+  if (n_batches) *n_batches = cs->batches;
+  return CTD_OK;
+}
+
+// (nb*S2 - S1^2) exactly in 192-bit unsigned arithmetic, returned as double.
+static double var_numerator(int64_t s1, uint64_t hi, uint64_t lo, uint32_t nb) {
+  const unsigned __int128 plo = (unsigned __int128)lo * nb;
+  const unsigned __int128 pmid = (unsigned __int128)hi * nb + (uint64_t)(plo >> 64);
+  const uint64_t a0 = (uint64_t)plo, a1 = (uint64_t)pmid, a2 = (uint64_t)(pmid >> 64);
+  const unsigned __int128 B = (unsigned __int128)(uint64_t)s1 * (uint64_t)s1;
+  const uint64_t b0 = (uint64_t)B, b1 = (uint64_t)(B >> 64);
+  const uint64_t r0 = a0 - b0;
+  const uint64_t br0 = a0 < b0 ? 1 : 0;
+  const uint64_t r1 = a1 - b1 - br0;
+  const uint64_t br1 = (a1 < b1 || (a1 - b1) < br0) ? 1 : 0;
+  if (a2 < br1) return 0.0;  // cannot happen for consistent sums
+  const uint64_t r2 = a2 - br1;
+  return (double)r2 * 0x1p128 + (double)r1 * 0x1p64 + (double)r0;
+}
+
+extern "C" int32_t ctd_read_dose(ctd_ctx *ctx, ctd_case *cs, double *dose, double *var_of_mean) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  NEED(ctx, cs->batches >= 2, "dose needs >= 2 folded batches");
+  const int64_t V = cs->ph->V;
+  std::vector<int64_t> s1((size_t)V);
+  std::vector<uint64_t> hi((size_t)V), lo((size_t)V);
+  uint32_t nb = 0;
+  int rc = ctd_read_tally(ctx, cs, s1.data(), hi.data(), lo.data(), &nb);
+  if (rc != CTD_OK) return rc;
+  std::vector<uint2> rec((size_t)V);
+  HIPCHK(ctx, hipMemcpy(rec.data(), cs->ph->vox, 8 * V, hipMemcpyDeviceToHost));
+  const ctd_grid &g = cs->ph->g;
+  const double vol = g.dx * g.dy * g.dz;
+  const double N = (double)cs->h_next;
+  const double per_batch = N / (double)nb;
+  for (int64_t v = 0; v < V; ++v) {
+    float r;
+    std::memcpy(&r, &rec[v].x, 4);
+    const double mass_kg = (double)r * vol * 1e-3;
+    if (!(mass_kg > 0.0)) {
+      if (dose) dose[v] = 0.0;
+      if (var_of_mean) var_of_mean[v] = 0.0;
+      continue;
+    }
+    const double conv = 1.602176634e-16 / (16777216.0 * mass_kg);  // q -> Gy
+    if (dose) dose[v] = (double)s1[v] / N * conv;
+    if (var_of_mean) {
+      const double num = var_numerator(s1[v], hi[v], lo[v], nb);
+      const double var_t = num / ((double)nb * nb * (double)(nb - 1));
+      var_of_mean[v] = var_t / (per_batch * per_batch) * conv * conv;
+    }
+  }
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_read_balance(ctd_ctx *ctx, ctd_case *cs, ctd_balance *out) {
+  if (!ctx || !cs || !out) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  uint64_t a[ACC_COUNT];
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(a, cs->d_acc, sizeof a, hipMemcpyDeviceToHost));
+  out->q_incident = (int64_t)a[ACC_Q_INC];
+  out->q_deposited = (int64_t)a[ACC_Q_DEP];
+  out->q_escaped = (int64_t)a[ACC_Q_ESC];
+  out->n_histories = a[ACC_N_HIST];
+  out->n_missed = a[ACC_N_MISS];
+  out->n_unscattered = a[ACC_N_UNSCATTERED];
+  out->n_cutoff = a[ACC_N_CUTOFF];
+  if (a[ACC_STEP_GUARD])
+    return set_err(ctx, CTD_ESTEPS, "%llu histories hit the step guard",
+                   (unsigned long long)a[ACC_STEP_GUARD]);
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out) {
+  if (!ctx || !cs || !out) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  uint64_t a[ACC_COUNT];
+  HIPCHK(ctx, hipMemcpy(a, cs->d_acc, sizeof a, hipMemcpyDeviceToHost));
+  for (auto &t : cs->timing) {
+    float ms1 = 0.f, ms2 = 0.f;
+    if (hipEventElapsedTime(&ms1, t.a, t.b) == hipSuccess) cs->transport_ms += ms1;
+    if (hipEventElapsedTime(&ms2, t.b, t.c) == hipSuccess) cs->fold_ms += ms2;
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.c);
+  }
+  cs->timing.clear();
+  if (cs->batches >= 2) {
+    double s;
+    if (sigma_now(ctx, cs, CTD_SIGMA_LOCAL, 0.5, &s) == CTD_OK) cs->sigma_local = s;
+    if (sigma_now(ctx, cs, CTD_SIGMA_PAPER, 0.2, &s) == CTD_OK) cs->sigma_paper = s;
+  }
+  out->sigma_local = cs->sigma_local;
+  out->sigma_paper = cs->sigma_paper;
+  out->n_steps = a[ACC_N_STEPS];
+  out->n_photo = a[ACC_N_PHOTO];
+  out->n_compton = a[ACC_N_COMPTON];
+  out->n_rayleigh = a[ACC_N_RAYLEIGH];
+  out->n_real = a[ACC_N_PHOTO] + a[ACC_N_COMPTON] + a[ACC_N_RAYLEIGH];
+  out->n_deposits = a[ACC_N_DEPOSITS];
+  out->n_escapes = a[ACC_N_ESCAPES];
+  out->n_refills = a[ACC_N_REFILLS];
+  out->transport_ms = cs->transport_ms;
+  out->fold_ms = cs->fold_ms;
+  out->n_batches = cs->batches;
+  out->reserved = 0;
+  out->n_histories = cs->h_next;
+  return CTD_OK;
+}
+
+extern "C" int32_t ctd_read_majorant(ctd_ctx *ctx, ctd_case *cs, float *out) {
+  if (!ctx || !cs || !out) return CTD_EINVAL;
+  std::memcpy(out, cs->mu_max.data(), 4 * cs->mu_max.size());
+  return CTD_OK;
+}
+
+// -------------------------------------------------------------- debug log
+
+extern "C" int32_t ctd_debug_deposit_log(ctd_ctx *ctx, ctd_case *cs, uint64_t h0, uint64_t nh,
+                                         uint64_t capacity) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  dfree(cs->d_log);
+  dfree(cs->d_log_n);
+  cs->d_log = nullptr;
+  cs->d_log_n = nullptr;
+  cs->log_cap = 0;
+  cs->log_h0 = cs->log_h1 = 0;
+  if (capacity > 0 && nh > 0) {
+    HIPCHK(ctx, hipMalloc(&cs->d_log, sizeof(ctd_event) * capacity));
+    HIPCHK(ctx, hipMalloc(&cs->d_log_n, 256));
+    HIPCHK(ctx, hipMemset(cs->d_log_n, 0, 256));
+    cs->log_cap = capacity;
+    cs->log_h0 = h0;
+    cs->log_h1 = h0 + nh;
+  }
+  fill_desc(cs);
+  return upload_desc(ctx, cs);
+}
+
+extern "C" int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out,
+                                      uint64_t capacity, uint64_t *n) {
+  if (!ctx || !cs || !n) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  *n = 0;
+  if (!cs->d_log_n) return CTD_OK;
+  unsigned long long cnt = 0;
+  HIPCHK(ctx, hipMemcpy(&cnt, cs->d_log_n, 8, hipMemcpyDeviceToHost));
+  *n = cnt;
+  const uint64_t k = std::min<uint64_t>({cnt, capacity, cs->log_cap});
+  if (k && out) HIPCHK(ctx, hipMemcpy(out, cs->d_log, sizeof(ctd_event) * k, hipMemcpyDeviceToHost));
+  return CTD_OK;
+}
+
+// ------------------------------------------------------------------ tuner
+
+extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histories,
+                                ctd_tuning *best) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  NEED(ctx, trial_histories > 0, "trial_histories must be positive");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  // scratch twin of the case: same inputs, private tallies
+  ctd_case tw = *cs;
+  tw.timing.clear();
+  tw.d_tally = nullptr;
+  tw.d_s1 = nullptr;
+  tw.d_s2 = nullptr;
+  tw.d_acc = nullptr;
+  tw.d_desc = nullptr;
+  tw.d_log = nullptr;
+  tw.d_log_n = nullptr;
+  tw.log_cap = 0;
+  const int64_t V = cs->ph->V;
+  auto release = [&]() {
+    dfree(tw.d_tally);
+    dfree(tw.d_s1);
+    dfree(tw.d_s2);
+    dfree(tw.d_acc);
+    dfree(tw.d_desc);
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&tw.d_tally, 8 * V)) != hipSuccess ||
+      (e = hipMalloc(&tw.d_s1, 8 * V)) != hipSuccess ||
+      (e = hipMalloc(&tw.d_s2, 16 * V)) != hipSuccess ||
+      (e = hipMalloc(&tw.d_acc, 8 * ACC_COUNT)) != hipSuccess ||
+      (e = hipMalloc(&tw.d_desc, sizeof(CaseDev))) != hipSuccess) {
+    release();
+    return hip_err(ctx, e, "autotune alloc");
+  }
+  launch_zero(tw.d_tally, 8 * V, ctx->stream);
+  launch_zero(tw.d_s1, 8 * V, ctx->stream);
+  launch_zero(tw.d_s2, 16 * V, ctx->stream);
+  launch_zero(tw.d_acc, 8 * ACC_COUNT, ctx->stream);
+  fill_desc(&tw);
+  int rc = upload_desc(ctx, &tw);
+  if (rc != CTD_OK) {
+    release();
+    return rc;
+  }
+  std::vector<ctd_tuning> cand;
+  for (int wps : {2, 4, 8})
+    for (int rm : {8, 16, 32})
+      for (int ch : {256, 1024}) {
+        ctd_tuning t;
+        t.block = 256;
+        t.waves_per_simd = wps;
+        t.refill_min = rm;
+        t.chunk = ch;
+        cand.push_back(t);
+      }
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  double best_ms = INFINITY;
+  ctd_tuning best_t = cs->tune;
+  std::vector<ctd_case *> one{&tw};
+  for (size_t i = 0; i <= cand.size(); ++i) {
+    const ctd_tuning t = i == 0 ? cand[0] : cand[i - 1];  // first run warms up
+    (void)hipEventRecord(a, ctx->stream);
+    rc = run_round(ctx, one, std::vector<uint64_t>{trial_histories}, t);
+    if (rc != CTD_OK) break;
+    (void)hipEventRecord(b, ctx->stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (i > 0 && ms < best_ms) {
+      best_ms = ms;
+      best_t = t;
+    }
+  }
+  for (auto &t : tw.timing) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.c);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamSynchronize(ctx->stream);
+  release();
+  if (rc != CTD_OK) return rc;
+  cs->tune = best_t;
+  if (best) *best = best_t;
+  return CTD_OK;
+}

@@ -1,0 +1,128 @@
+// Host-side object layouts behind the opaque C handles, and runtime helpers
+// shared by the C-ABI translation units (ctd_api.cpp, ctd_server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ctd.h"
+#include "ctd_internal.h"
+
+namespace ctd {
+
+constexpr int kSigmaBlocks = 1024;
+
+struct RoundItem {
+  const CaseDev *cd;
+  uint64_t h_begin, n;
+  std::vector<unsigned long long> prefix;
+};
+
+}  // namespace ctd
+
+struct ctd_ctx {
+  int device = 0;
+  hipStream_t own = nullptr;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  std::string err;
+  struct Slot {
+    void *host = nullptr;
+    void *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+  };
+  std::vector<Slot> slots;  // staging ring for per-round launch tables
+  size_t next_slot = 0;
+  double *sigma_scratch = nullptr;
+  double *sigma_host = nullptr;
+};
+
+struct ctd_phantom {
+  ctd_ctx *ctx = nullptr;
+  ctd_grid g{};
+  int64_t V = 0;
+  uint2 *vox = nullptr;   // packed (rho bits, material) records
+  double rho_max[256] = {};
+  bool present[256] = {};
+  int max_mat = 0;
+  int refs = 0;
+};
+
+struct ctd_matset {
+  ctd_egrid eg{};
+  int M = 0, ncomp = 1, nzc = 0, nzr = 0;
+  std::vector<float> mu_rho;  // host copy [M][ne][3]
+  float4 *d_mu = nullptr;
+  float4 *d_comp = nullptr;
+  float4 *d_rayl = nullptr;
+  int refs = 0;
+};
+
+struct ctd_spectrum {
+  std::vector<double> lo, w;
+  double width = 0.0;
+  int refs = 0;
+};
+
+struct ctd_geometry {
+  ctd_geom g{};
+  std::vector<float2> proj_sc;
+  int refs = 0;
+};
+
+struct ctd_case {
+  ctd_ctx *ctx = nullptr;
+  ctd_phantom *ph = nullptr;
+  ctd_matset *ms = nullptr;
+  ctd_spectrum *sp = nullptr;
+  ctd_geometry *geo = nullptr;
+  ctd_params p{};
+  double e_max = 0.0;
+  ctd_tuning tune{};
+  std::vector<float> mu_max;
+  ctd::CaseDev desc{};
+  ctd::CaseDev *d_desc = nullptr;
+  float *d_mu_max = nullptr;
+  float *d_bin_lo = nullptr;
+  float2 *d_proj = nullptr;
+  unsigned long long *d_tally = nullptr;
+  long long *d_s1 = nullptr;
+  unsigned long long *d_s2 = nullptr;
+  unsigned long long *d_acc = nullptr;
+  ctd_event *d_log = nullptr;
+  unsigned long long *d_log_n = nullptr;
+  uint64_t log_h0 = 0, log_h1 = 0, log_cap = 0;
+  uint64_t h_next = 0;      // next history id
+  uint32_t batches = 0;     // batches folded
+  std::vector<uint64_t> batch_sizes;
+  struct Timing {
+    hipEvent_t a, b, c;
+  };
+  std::vector<Timing> timing;
+  double transport_ms = 0.0, fold_ms = 0.0;
+  double sigma_local = NAN, sigma_paper = NAN;
+  bool in_server = false;
+};
+
+namespace ctd {
+
+int set_err(ctd_ctx *ctx, int code, const char *fmt, ...);
+int hip_err(ctd_ctx *ctx, hipError_t e, const char *what);
+int upload_desc(ctd_ctx *ctx, ctd_case *cs);
+void fill_desc(ctd_case *cs);
+void free_case_buffers(ctd_case *cs);
+ctd_tuning default_tuning();
+int submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const ctd_tuning &t,
+                 bool with_log);
+int batch_prefix(ctd_ctx *ctx, const ctd_case *cs, uint64_t n,
+                 std::vector<unsigned long long> &prefix);
+int run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vector<uint64_t> &n,
+              const ctd_tuning &t);
+std::vector<uint64_t> split_batches(uint64_t n, int nb);
+int sigma_now(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *out);
+int run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count);
+
+}  // namespace ctd

@@ -1,0 +1,112 @@
+// Plain-old-data structures shared by the host runtime (ctd_api.cpp) and the
+// HIP kernels (ctd_kernels.hip).  Everything a kernel reads about a case lives
+// in one CaseDev record in device memory; a launch covers one "round": for
+// each participating case, one batch of histories, consumed in chunks.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ctd.h"
+
+namespace ctd {
+
+// Per-case accumulators (device, uint64 each).
+enum Acc : int {
+  ACC_Q_INC = 0,     // incident energy, q units
+  ACC_Q_DEP,         // deposited energy, q units
+  ACC_Q_ESC,         // escaped energy (including misses), q units
+  ACC_N_HIST,
+  ACC_N_STEPS,
+  ACC_N_REAL,
+  ACC_N_PHOTO,
+  ACC_N_COMPTON,
+  ACC_N_RAYLEIGH,
+  ACC_N_DEPOSITS,
+  ACC_N_ESCAPES,
+  ACC_N_MISS,
+  ACC_N_UNSCATTERED,
+  ACC_N_CUTOFF,
+  ACC_N_REFILLS,
+  ACC_STEP_GUARD,    // histories killed by the step guard (must stay 0)
+  ACC_COUNT
+};
+
+constexpr float kQScale = 16777216.0f;  // 2^24: tally unit q = 2^-24 keV
+constexpr uint32_t kStepGuard = 1000000u;
+constexpr float kInvMeC2 = (float)(1.0 / 510.99895);
+
+struct CaseDev {
+  // voxel grid; positions are tracked in voxel units
+  int32_t nx, ny, nz, nmat;
+  float fnx, fny, fnz, pad0;
+  float inv_dx, inv_dy, inv_dz, pad1;
+  float ox, oy, oz, pad2;
+  const uint2 *vox;            // [V] (float bits of rho, material id)
+  int64_t V;
+  // energy grid and tables
+  int32_t ne, nzc, nzr, rayleigh;
+  float e0, inv_de, e_cut, pad3;
+  const float4 *mu_rho;        // [nmat][ne] (pe, Compton, Rayleigh, 0) cm^2/g
+  const float *mu_max;         // [ne] cm^-1
+  const float4 *comp_quad;     // [ncomp][ne-1][nzc-1] bilinear cells
+  const float4 *rayl_quad;     // [nmat][ne-1][nzr-1] or null
+  int32_t comp_per_mat, nbins;
+  float bin_width, pad4;
+  const float *bin_lo;         // [nbins]
+  // geometry
+  int32_t kind, nproj;
+  float sad, pad5;
+  float src[3], dir[3];
+  float iso[3], pad6;
+  float a0, a1, b0, b1;
+  float phi0_turns, arc_turns, pad7, pad8;
+  const float2 *proj_sc;       // [nproj] (sin phi_p, cos phi_p)
+  // random stream key
+  uint32_t key0, key1;
+  // tallies
+  unsigned long long *tally;   // T_b [V]
+  long long *s1;               // [V]
+  unsigned long long *s2;      // [V][2] (lo, hi)
+  unsigned long long *acc;     // [ACC_COUNT]
+  // event log (debug)
+  ctd_event *log;
+  unsigned long long *log_n;
+  uint64_t log_h0, log_h1, log_cap;
+};
+
+// One case's share of a launch: batch histories [h_begin, h_begin + n) laid
+// out bin-major by prefix[0..nbins]; chunks [chunk_begin, chunk_begin +
+// ceil(n/chunk)) of the launch-wide chunk counter belong to it.
+struct RoundCase {
+  const CaseDev *cd;
+  const unsigned long long *prefix;
+  uint64_t h_begin, n, chunk_begin, pad;
+};
+
+struct LaunchCfg {
+  int block;
+  int grid;
+  int refill_min;
+  int chunk;
+};
+
+// Kernel launchers (ctd_kernels.hip).  All enqueue on `stream`.
+int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
+                     unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
+                     void *stream);
+int launch_fold(unsigned long long *tally, long long *s1, unsigned long long *s2, int64_t V,
+                void *stream);
+// stats[514]: [0,256) max density bits per material, [256,512) presence,
+// [512] largest material id, [513] voxels with a bad density.
+int launch_pack(const uint8_t *mat, const float *rho, uint2 *vox, int64_t V, unsigned int *stats,
+                void *stream);
+int launch_zero(void *ptr, size_t bytes, void *stream);
+// sigma-bar over one case: out[0] = sigma, out[1] = voxel count, out[2] =
+// max dose (S1/rho); scratch holds 3 * nblocks doubles.
+int launch_sigma(const long long *s1, const unsigned long long *s2, const uint2 *vox, int64_t V,
+                 uint32_t nb, double rho_min, double frac, int kind, double *scratch,
+                 int nblocks, double *out, void *stream);
+int device_cu_count(int device);
+
+}  // namespace ctd

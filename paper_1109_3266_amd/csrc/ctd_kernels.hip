@@ -1,0 +1,685 @@
+// HIP kernels for gfx950 (MI355X): Woodcock photon transport (Jia et al.,
+// arXiv 1109.3266, Sec. 2.1-2.2), batch fold and sigma-bar reduction.
+//
+// Execution model.  One persistent launch per round.  A round is, for each
+// participating case, one batch of histories laid out bin-major over the
+// spectrum (Sec. 2.2.5), split into chunks of consecutive history ids.  Each
+// 64-lane wave owns one case at a time and a pool of history ids claimed one
+// chunk per atomic; lanes are one photon each (Sec. 2.2, one thread per
+// photon).  When at least `refill_min` lanes of a wave are idle the wave
+// refills them from its pool in one step, so a wave keeps ~all lanes busy and
+// its lanes hold photons of neighbouring ids, i.e. similar energies.  A wave
+// that claims a chunk of a different case finishes its live photons first.
+//
+// Numerics.  Transport is float32.  Every deposit (E - E' of a Compton event,
+// E of a photoelectric or cutoff event) and every escape is an exact
+// multiple of q = 2^-24 keV for E < 256 keV, so deposits enter the int64 tally
+// exactly and incident = deposited + escaped holds exactly in q units.
+// Random numbers: Philox4x32-10 keyed by the case seed, counter (step k,
+// history id lo, hi, 0); k = 0 draws the source, step k >= 1 draws
+// (free path, interaction type, polar zeta, azimuth).
+#include <hip/hip_runtime.h>
+
+#include "ctd_internal.h"
+
+namespace ctd {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0,
+                                          uint32_t k1) {
+  uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = 0u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(x0, x1, x2, x3);
+}
+
+// (2 (r >> 9) + 1) 2^-24 exactly: [1,2) mantissa trick minus (1 - 2^-24).
+__device__ __forceinline__ float unif(uint32_t r) {
+  return __uint_as_float((r >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
+}
+
+__device__ __forceinline__ float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
+
+// sin / cos of a phase given in turns (revolutions), hardware transcendental.
+__device__ __forceinline__ float sin_turns(float t) { return __builtin_amdgcn_sinf(t); }
+__device__ __forceinline__ float cos_turns(float t) { return __builtin_amdgcn_cosf(t); }
+
+// Inverse-CDF surface mu(zeta, E): one 16-byte cell gives both zeta
+// neighbours at both energy neighbours; bilinear, clamped to [-1, 1].
+__device__ __forceinline__ float surface(const float4 *__restrict__ Q, int nz, int je, float we,
+                                         float zeta) {
+  const float f = zeta * (float)(nz - 1);
+  const int i = min((int)f, nz - 2);
+  const float wz = f - (float)i;
+  const float4 q = Q[(size_t)je * (size_t)(nz - 1) + (size_t)i];
+  const float s0 = lerpf(q.x, q.y, wz);
+  const float s1 = lerpf(q.z, q.w, wz);
+  return fminf(fmaxf(lerpf(s0, s1, we), -1.0f), 1.0f);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ lane state
+
+struct Counters {
+  unsigned long long q_inc, q_dep, q_esc;
+  uint32_t n_hist, n_steps, n_photo, n_compton, n_rayleigh, n_dep, n_esc, n_miss, n_unsc,
+      n_cut, n_guard;
+  __device__ void clear() {
+    q_inc = q_dep = q_esc = 0ull;
+    n_hist = n_steps = n_photo = n_compton = n_rayleigh = n_dep = n_esc = n_miss = n_unsc =
+        n_cut = n_guard = 0u;
+  }
+};
+
+__device__ void flush(Counters &c, const CaseDev *cd, int lane, uint32_t refills) {
+  const unsigned long long q_inc = wave_sum(c.q_inc);
+  const unsigned long long q_dep = wave_sum(c.q_dep);
+  const unsigned long long q_esc = wave_sum(c.q_esc);
+  const uint32_t v[11] = {wave_sum(c.n_hist),  wave_sum(c.n_steps), wave_sum(c.n_photo),
+                          wave_sum(c.n_compton), wave_sum(c.n_rayleigh), wave_sum(c.n_dep),
+                          wave_sum(c.n_esc),   wave_sum(c.n_miss),  wave_sum(c.n_unsc),
+                          wave_sum(c.n_cut),   wave_sum(c.n_guard)};
+  if (lane == 0) {
+    unsigned long long *a = cd->acc;
+    if (q_inc) atomic_add_u64(a + ACC_Q_INC, q_inc);
+    if (q_dep) atomic_add_u64(a + ACC_Q_DEP, q_dep);
+    if (q_esc) atomic_add_u64(a + ACC_Q_ESC, q_esc);
+    const int idx[11] = {ACC_N_HIST,    ACC_N_STEPS, ACC_N_PHOTO, ACC_N_COMPTON,
+                         ACC_N_RAYLEIGH, ACC_N_DEPOSITS, ACC_N_ESCAPES, ACC_N_MISS,
+                         ACC_N_UNSCATTERED, ACC_N_CUTOFF, ACC_STEP_GUARD};
+#pragma unroll
+    for (int i = 0; i < 11; ++i)
+      if (v[i]) atomic_add_u64(a + idx[i], v[i]);
+    if (refills) atomic_add_u64(a + ACC_N_REFILLS, refills);
+  }
+  c.clear();
+}
+
+struct Photon {
+  float px, py, pz;   // position, voxel units
+  float ux, uy, uz;   // unit direction
+  float vx, vy, vz;   // direction in voxel units per cm
+  float E;            // keV
+  float mumax;        // majorant at E, cm^-1
+  float sc;           // ln2 / mumax
+  float we;           // energy-grid weight
+  int je;             // energy-grid cell
+  uint32_t hlo, hhi, k, seq;
+  bool scattered;
+};
+
+__device__ __forceinline__ void set_energy(Photon &p, const CaseDev *cd, float E) {
+  p.E = E;
+  const float f = (E - cd->e0) * cd->inv_de;
+  const int j = min(max((int)f, 0), cd->ne - 2);
+  p.je = j;
+  p.we = f - (float)j;
+  p.mumax = lerpf(cd->mu_max[j], cd->mu_max[j + 1], p.we);
+  p.sc = 0.69314718055994531f / p.mumax;
+}
+
+__device__ __forceinline__ void set_dir(Photon &p, const CaseDev *cd) {
+  p.vx = p.ux * cd->inv_dx;
+  p.vy = p.uy * cd->inv_dy;
+  p.vz = p.uz * cd->inv_dz;
+}
+
+// Direction after deflection cos(theta) = mu and azimuth 2 pi t (t in turns).
+__device__ __forceinline__ void rotate(Photon &p, float mu, float t) {
+  const float st = sqrtf(fmaxf(0.0f, (1.0f - mu) * (1.0f + mu)));
+  const float sp = sin_turns(t), cp = cos_turns(t);
+  const float u = p.ux, v = p.uy, w = p.uz;
+  float nu, nv, nw;
+  if (fabsf(w) < 1.0f - 1e-5f) {
+    const float r = sqrtf((1.0f - w) * (1.0f + w));
+    const float g = st / r;
+    nu = fmaf(u, mu, g * (u * w * cp - v * sp));
+    nv = fmaf(v, mu, g * (v * w * cp + u * sp));
+    nw = fmaf(w, mu, -st * cp * r);
+  } else {
+    nu = st * cp;
+    nv = st * sp;
+    nw = w >= 0.0f ? mu : -mu;
+  }
+  const float n = rsqrtf(nu * nu + nv * nv + nw * nw);
+  p.ux = nu * n;
+  p.uy = nv * n;
+  p.uz = nw * n;
+}
+
+template <bool LOG>
+__device__ __forceinline__ void log_event(const CaseDev *cd, Photon &p, int type, int64_t vox,
+                                          float e, float Eafter) {
+  if (!LOG) return;
+  const uint64_t h = ((uint64_t)p.hhi << 32) | p.hlo;
+  if (h < cd->log_h0 || h >= cd->log_h1) return;
+  const unsigned long long idx = atomicAdd(cd->log_n, 1ull);
+  if (idx < cd->log_cap) {
+    ctd_event ev;
+    ev.h = h;
+    ev.seq = p.seq;
+    ev.k = p.k;
+    ev.type = type;
+    ev.reserved = 0;
+    ev.vox = vox;
+    ev.e = e;
+    ev.E = Eafter;
+    cd->log[idx] = ev;
+  }
+  p.seq += 1;
+}
+
+template <bool LOG>
+__device__ __forceinline__ void deposit(const CaseDev *cd, Photon &p, Counters &c, int32_t vox,
+                                        float e, int type, float Eafter) {
+  const uint32_t q = (uint32_t)(e * kQScale);  // exact: e is a multiple of 2^-24 keV
+  if (q) atomic_add_u64(cd->tally + vox, (unsigned long long)q);
+  c.q_dep += q;
+  c.n_dep += 1;
+  log_event<LOG>(cd, p, type, vox, e, Eafter);
+}
+
+// Source photon of history h from spectrum bin j (Sec. 2.2.5-2.2.6); returns
+// false when the ray misses the voxel box (the photon escapes at once).
+template <bool LOG>
+__device__ bool source(Photon &p, const CaseDev *cd, uint64_t h, int j, Counters &c) {
+  p.hlo = (uint32_t)h;
+  p.hhi = (uint32_t)(h >> 32);
+  p.k = 0;
+  p.seq = 0;
+  p.scattered = false;
+  const uint4 r = philox10(0u, p.hlo, p.hhi, cd->key0, cd->key1);
+  const float E = fmaf(unif(r.x), cd->bin_width, cd->bin_lo[j]);
+  float sx, sy, sz, dx, dy, dz;
+  if (cd->kind == CTD_GEOM_PENCIL) {
+    sx = cd->src[0]; sy = cd->src[1]; sz = cd->src[2];
+    dx = cd->dir[0]; dy = cd->dir[1]; dz = cd->dir[2];
+  } else {
+    float sp, cp;
+    if (cd->nproj > 0) {
+      // exact in double: 24-bit uniform times an integer < 2^31
+      int pi = (int)((double)unif(r.y) * (double)cd->nproj);
+      pi = min(pi, cd->nproj - 1);
+      const float2 sc = cd->proj_sc[pi];
+      sp = sc.x;
+      cp = sc.y;
+    } else {
+      const float t = fmaf(unif(r.y), cd->arc_turns, cd->phi0_turns);
+      sp = sin_turns(t);
+      cp = cos_turns(t);
+    }
+    sx = fmaf(cd->sad, sp, cd->iso[0]);
+    sy = fmaf(cd->sad, cp, cd->iso[1]);
+    sz = cd->iso[2];
+    const float a = fmaf(unif(r.z), cd->a1 - cd->a0, cd->a0);
+    const float b = fmaf(unif(r.w), cd->b1 - cd->b0, cd->b0);
+    const float Px = fmaf(a, cp, cd->iso[0]);
+    const float Py = fmaf(-a, sp, cd->iso[1]);
+    const float Pz = cd->iso[2] + b;
+    const float vx = Px - sx, vy = Py - sy, vz = Pz - sz;
+    const float inv = rsqrtf(vx * vx + vy * vy + vz * vz);
+    dx = vx * inv; dy = vy * inv; dz = vz * inv;
+  }
+  c.n_hist += 1;
+  c.q_inc += (uint32_t)(E * kQScale);
+  p.E = E;
+  log_event<LOG>(cd, p, 0, -1, E, E);
+  // slab entry into the box [0, n) in voxel units
+  const float S[3] = {(sx - cd->ox) * cd->inv_dx, (sy - cd->oy) * cd->inv_dy,
+                      (sz - cd->oz) * cd->inv_dz};
+  const float D[3] = {dx * cd->inv_dx, dy * cd->inv_dy, dz * cd->inv_dz};
+  const float N[3] = {cd->fnx, cd->fny, cd->fnz};
+  float tn = -INFINITY, tf = INFINITY;
+  bool miss = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (D[a] == 0.0f) {
+      miss |= (S[a] < 0.0f) | (S[a] > N[a]);
+    } else {
+      const float inv = 1.0f / D[a];
+      const float t1 = (0.0f - S[a]) * inv, t2 = (N[a] - S[a]) * inv;
+      tn = fmaxf(tn, fminf(t1, t2));
+      tf = fminf(tf, fmaxf(t1, t2));
+    }
+  }
+  const float tin = fmaxf(tn, 0.0f);
+  if (miss || !(tin < tf)) {
+    c.n_miss += 1;
+    c.q_esc += (uint32_t)(E * kQScale);
+    log_event<LOG>(cd, p, 6, -1, E, E);
+    return false;
+  }
+  // entry point, kept inside [0, n) against rounding
+  const float top[3] = {__int_as_float(__float_as_int(N[0]) - 1),
+                        __int_as_float(__float_as_int(N[1]) - 1),
+                        __int_as_float(__float_as_int(N[2]) - 1)};
+  p.px = fminf(fmaxf(fmaf(tin, D[0], S[0]), 0.0f), top[0]);
+  p.py = fminf(fmaxf(fmaf(tin, D[1], S[1]), 0.0f), top[1]);
+  p.pz = fminf(fmaxf(fmaf(tin, D[2], S[2]), 0.0f), top[2]);
+  p.ux = dx; p.uy = dy; p.uz = dz;
+  set_dir(p, cd);
+  set_energy(p, cd, E);
+  return true;
+}
+
+// One Woodcock step (Sec. 2.1); returns false when the photon is done.
+template <bool LOG>
+__device__ __forceinline__ bool step(Photon &p, const CaseDev *cd, Counters &c) {
+  p.k += 1;
+  c.n_steps += 1;
+  if (p.k > kStepGuard) {
+    c.n_guard += 1;
+    return false;
+  }
+  const uint4 r = philox10(p.k, p.hlo, p.hhi, cd->key0, cd->key1);
+  const float s = -__log2f(unif(r.x)) * p.sc;  // -ln(u) / mu_max
+  p.px = fmaf(s, p.vx, p.px);
+  p.py = fmaf(s, p.vy, p.py);
+  p.pz = fmaf(s, p.vz, p.pz);
+  const bool inside = (p.px >= 0.0f) & (p.px < cd->fnx) & (p.py >= 0.0f) & (p.py < cd->fny) &
+                      (p.pz >= 0.0f) & (p.pz < cd->fnz);
+  if (!inside) {
+    c.n_esc += 1;
+    c.n_unsc += p.scattered ? 0u : 1u;
+    c.q_esc += (uint32_t)(p.E * kQScale);
+    log_event<LOG>(cd, p, 5, -1, p.E, p.E);
+    return false;
+  }
+  const int32_t vox = ((int32_t)p.pz * cd->ny + (int32_t)p.py) * cd->nx + (int32_t)p.px;
+  const uint2 rec = cd->vox[vox];
+  const float rho = __uint_as_float(rec.x);
+  const int m = (int)rec.y;
+  const float4 *t = cd->mu_rho + (size_t)m * (size_t)cd->ne + (size_t)p.je;
+  const float4 t0 = t[0], t1 = t[1];
+  const float mpe = rho * lerpf(t0.x, t1.x, p.we);
+  const float c1 = mpe + rho * lerpf(t0.y, t1.y, p.we);
+  const float xi = unif(r.y) * p.mumax;
+  if (xi < mpe) {  // photoelectric: absorb, deposit E locally
+    c.n_photo += 1;
+    deposit<LOG>(cd, p, c, vox, p.E, 1, 0.0f);
+    return false;
+  }
+  if (xi < c1) {  // Compton (Sec. 2.2.3): angle from the C surface
+    c.n_compton += 1;
+    p.scattered = true;
+    const float4 *Q = cd->comp_quad;
+    if (cd->comp_per_mat) Q += (size_t)m * (size_t)(cd->ne - 1) * (size_t)(cd->nzc - 1);
+    const float mu = surface(Q, cd->nzc, p.je, p.we, unif(r.z));
+    const float E = p.E;
+    const float Ep = E / fmaf(E * kInvMeC2, 1.0f - mu, 1.0f);
+    deposit<LOG>(cd, p, c, vox, E - Ep, 2, Ep);  // exact: Ep > E/2 (Sterbenz)
+    rotate(p, mu, unif(r.w));
+    set_dir(p, cd);
+    set_energy(p, cd, Ep);
+    if (Ep < cd->e_cut) {
+      c.n_cut += 1;
+      deposit<LOG>(cd, p, c, vox, Ep, 4, 0.0f);
+      return false;
+    }
+    return true;
+  }
+  if (cd->rayleigh) {
+    const float c2 = c1 + rho * lerpf(t0.z, t1.z, p.we);
+    if (xi < c2) {  // Rayleigh (Sec. 2.2.2): angle from the R surface, E unchanged
+      c.n_rayleigh += 1;
+      p.scattered = true;
+      const float4 *Q = cd->rayl_quad + (size_t)m * (size_t)(cd->ne - 1) * (size_t)(cd->nzr - 1);
+      const float mu = surface(Q, cd->nzr, p.je, p.we, unif(r.z));
+      rotate(p, mu, unif(r.w));
+      set_dir(p, cd);
+      log_event<LOG>(cd, p, 3, vox, 0.0f, p.E);
+    }
+  }
+  return true;  // fictitious or scattered: keep going
+}
+
+// ------------------------------------------------------- transport kernel
+
+__device__ __forceinline__ int find_round_case(const RoundCase *__restrict__ rcs, int nrc,
+                                               uint64_t t) {
+  int lo = 0, hi = nrc - 1;
+  while (lo < hi) {  // last index with chunk_begin <= t
+    const int mid = (lo + hi + 1) >> 1;
+    if (rcs[mid].chunk_begin <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int find_bin(const unsigned long long *__restrict__ prefix, int nbins,
+                                        uint64_t local) {
+  int lo = 0, hi = nbins - 1;
+  while (lo < hi) {  // last bin with prefix[bin] <= local
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= local) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool LOG>
+__global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__ rcs, int nrc,
+                                                   uint64_t total_chunks,
+                                                   unsigned long long *chunk_ctr, int refill_min,
+                                                   int chunk) {
+  const int lane = __lane_id();
+  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  // wave-uniform state
+  int cur = -1;                         // round-case index of the wave's case
+  uint64_t pool_next = 0, pool_end = 0; // local history indices of `cur`
+  int wbin = 0;                         // bin of pool_next
+  int pend = -1;                        // claimed chunk of another case
+  uint64_t pend_lo = 0, pend_hi = 0;
+  bool queue_done = false;
+  uint32_t refills = 0;
+
+  Counters cnt;
+  cnt.clear();
+  Photon p;
+  bool alive = false;
+
+  for (;;) {
+    const unsigned long long dead = __ballot(!alive);
+    const int ndead = __popcll(dead);
+    if (ndead == 64 || ndead >= refill_min) {
+      // switch to the pending case once the wave has drained
+      if (pend >= 0 && ndead == 64 && pool_next >= pool_end) {
+        if (cur >= 0) flush(cnt, rcs[cur].cd, lane, refills);
+        refills = 0;
+        cur = pend;
+        pend = -1;
+        pool_next = pend_lo;
+        pool_end = pend_hi;
+        wbin = find_bin(rcs[cur].prefix, rcs[cur].cd->nbins, pool_next);
+      }
+      // claim chunks until the pool has work or the queue is empty
+      while (pool_next >= pool_end && pend < 0 && !queue_done) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(chunk_ctr, 1ull);
+        t = __shfl(t, 0, 64);
+        if (t >= total_chunks) {
+          queue_done = true;
+          break;
+        }
+        const int rc = find_round_case(rcs, nrc, t);
+        const uint64_t lo = (t - rcs[rc].chunk_begin) * (uint64_t)chunk;
+        const uint64_t hi = min(lo + (uint64_t)chunk, rcs[rc].n);
+        if (rc == cur || cur < 0 || ndead == 64) {
+          if (rc != cur) {
+            if (cur >= 0) flush(cnt, rcs[cur].cd, lane, refills);
+            refills = 0;
+            cur = rc;
+            wbin = find_bin(rcs[cur].prefix, rcs[cur].cd->nbins, lo);
+          }
+          pool_next = lo;
+          pool_end = hi;
+        } else {
+          pend = rc;
+          pend_lo = lo;
+          pend_hi = hi;
+        }
+      }
+      // hand out pool ids to idle lanes, lowest lanes first
+      if (pool_next < pool_end && ndead > 0) {
+        const RoundCase &R = rcs[cur];
+        const CaseDev *cd = R.cd;
+        const uint64_t avail = pool_end - pool_next;
+        const uint32_t m = (uint32_t)min((uint64_t)ndead, avail);
+        const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
+        if (!alive && rank < m) {
+          const uint64_t local = pool_next + rank;
+          int j = wbin;
+          while (j + 1 < cd->nbins && local >= R.prefix[j + 1]) ++j;
+          alive = source<LOG>(p, cd, R.h_begin + local, j, cnt);
+        }
+        pool_next += m;
+        refills += 1;
+        if (pool_next < pool_end) {
+          while (wbin + 1 < cd->nbins && pool_next >= R.prefix[wbin + 1]) ++wbin;
+        }
+      }
+    }
+    if (__ballot(alive) == 0ull) {
+      if (queue_done && pend < 0 && pool_next >= pool_end) break;
+      continue;
+    }
+    if (alive) alive = step<LOG>(p, rcs[cur].cd, cnt);
+  }
+  if (cur >= 0) flush(cnt, rcs[cur].cd, lane, refills);
+}
+
+// --------------------------------------------------------------- fold etc.
+
+// S1 += T_b, S2 += T_b^2 (128-bit), T_b = 0 (Sec. 2.2.1 batch statistics).
+__global__ void __launch_bounds__(256) k_fold(unsigned long long *__restrict__ T,
+                                              long long *__restrict__ S1,
+                                              unsigned long long *__restrict__ S2, int64_t V) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
+    const unsigned long long t = T[i];
+    if (t == 0ull) continue;
+    S1[i] += (long long)t;
+    const unsigned long long lo = S2[2 * i], hi = S2[2 * i + 1];
+    const unsigned long long plo = t * t, phi = __umul64hi(t, t);
+    const unsigned long long nlo = lo + plo;
+    S2[2 * i] = nlo;
+    S2[2 * i + 1] = hi + phi + (nlo < lo ? 1ull : 0ull);
+    T[i] = 0ull;
+  }
+}
+
+// Pack (mat, rho) into 8-byte voxel records; per-material max density (as
+// float bits, valid for rho >= 0) and presence flag, max material id and a
+// count of bad densities.  stats: [0,256) rho max bits, [256,512) presence,
+// [512] max material id, [513] bad count.
+__global__ void __launch_bounds__(256) k_pack(const uint8_t *__restrict__ mat,
+                                              const float *__restrict__ rho,
+                                              uint2 *__restrict__ vox, int64_t V,
+                                              unsigned int *stats) {
+  __shared__ unsigned int lmax[256], lpres[256];
+  __shared__ unsigned int lmat, lbad;
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) { lmax[i] = 0u; lpres[i] = 0u; }
+  if (threadIdx.x == 0) { lmat = 0u; lbad = 0u; }
+  __syncthreads();
+  unsigned int mymat = 0u, mybad = 0u;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
+    const unsigned int m = mat[i];
+    const float r = rho[i];
+    const bool ok = (r >= 0.0f) && (r <= 3.4e38f);
+    vox[i] = make_uint2(__float_as_uint(r), m);
+    mymat = max(mymat, m);
+    if (lpres[m] == 0u) lpres[m] = 1u;  // benign race: every writer stores 1
+    if (ok) atomicMax(&lmax[m], __float_as_uint(r)); else mybad += 1u;
+  }
+  atomicMax(&lmat, mymat);
+  if (mybad) atomicAdd(&lbad, mybad);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+    if (lmax[i]) atomicMax(&stats[i], lmax[i]);
+    if (lpres[i]) atomicMax(&stats[256 + i], 1u);
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(&stats[512], lmat);
+    if (lbad) atomicAdd(&stats[513], lbad);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_zero(unsigned long long *p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
+// sigma-bar, deterministic two-level reductions (fixed grid and block).
+__device__ __forceinline__ bool voxel_dose(const long long *s1, const uint2 *vox, int64_t i,
+                                           double rho_min, double &d, double &rho) {
+  rho = (double)__uint_as_float(vox[i].x);
+  if (!(rho >= rho_min) || rho <= 0.0) return false;
+  d = (double)s1[i] / rho;
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_sigma_max(const long long *s1, const uint2 *vox,
+                                                   int64_t V, double rho_min, double *part) {
+  __shared__ double sm[256];
+  double m = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
+    double d, r;
+    if (voxel_dose(s1, vox, i, rho_min, d, r)) m = fmax(m, d);
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void __launch_bounds__(256) k_sigma_sum(const long long *s1,
+                                                   const unsigned long long *s2,
+                                                   const uint2 *vox, int64_t V, uint32_t nb,
+                                                   double rho_min, double frac, int kind,
+                                                   const double *part_max, int nparts,
+                                                   double *part) {
+  __shared__ double ss[256], sc[256];
+  __shared__ double dmax_s;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int b = 0; b < nparts; ++b) m = fmax(m, part_max[b]);
+    dmax_s = m;
+  }
+  __syncthreads();
+  const double dmax = dmax_s;
+  const double nbd = (double)nb;
+  double sum = 0.0, count = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
+    double d, rho;
+    if (!voxel_dose(s1, vox, i, rho_min, d, rho)) continue;
+    if (!(d > frac * dmax) || dmax <= 0.0) continue;
+    const double S1 = (double)s1[i];
+    const double S2 = (double)s2[2 * i + 1] * 18446744073709551616.0 + (double)s2[2 * i];
+    const double var_t = fmax(nbd * S2 - S1 * S1, 0.0) / (nbd * nbd * (nbd - 1.0));
+    const double s = sqrt(var_t) * nbd / rho;  // same scale as d = S1 / rho
+    sum += (kind == CTD_SIGMA_PAPER) ? s / dmax : s / d;
+    count += 1.0;
+  }
+  ss[threadIdx.x] = sum;
+  sc[threadIdx.x] = count;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      ss[threadIdx.x] += ss[threadIdx.x + o];
+      sc[threadIdx.x] += sc[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ss[0];
+    part[2 * blockIdx.x + 1] = sc[0];
+  }
+}
+
+__global__ void k_sigma_final(const double *part, int nparts, const double *part_max,
+                              double *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0, c = 0.0, m = 0.0;
+  for (int b = 0; b < nparts; ++b) {
+    s += part[2 * b];
+    c += part[2 * b + 1];
+    m = fmax(m, part_max[b]);
+  }
+  out[0] = c > 0.0 ? s / c : INFINITY;
+  out[1] = c;
+  out[2] = m;
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
+
+int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
+                     unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
+                     void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (with_log)
+    hipLaunchKernelGGL(k_transport<true>, dim3(cfg.grid), dim3(cfg.block), 0, s, rc_dev, nrc,
+                       total_chunks, chunk_ctr, cfg.refill_min, cfg.chunk);
+  else
+    hipLaunchKernelGGL(k_transport<false>, dim3(cfg.grid), dim3(cfg.block), 0, s, rc_dev, nrc,
+                       total_chunks, chunk_ctr, cfg.refill_min, cfg.chunk);
+  return check_launch();
+}
+
+static int grid_for(int64_t n, int block, int cap) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+int launch_fold(unsigned long long *tally, long long *s1, unsigned long long *s2, int64_t V,
+                void *stream) {
+  hipLaunchKernelGGL(k_fold, dim3(grid_for(V, 256, 4096)), dim3(256), 0, (hipStream_t)stream,
+                     tally, s1, s2, V);
+  return check_launch();
+}
+
+int launch_pack(const uint8_t *mat, const float *rho, uint2 *vox, int64_t V,
+                unsigned int *stats, void *stream) {
+  hipLaunchKernelGGL(k_pack, dim3(grid_for(V, 256, 2048)), dim3(256), 0, (hipStream_t)stream,
+                     mat, rho, vox, V, stats);
+  return check_launch();
+}
+
+int launch_zero(void *ptr, size_t bytes, void *stream) {
+  const size_t n = bytes / 8;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for((int64_t)n, 256, 4096)), dim3(256), 0,
+                     (hipStream_t)stream, (unsigned long long *)ptr, n);
+  return check_launch();
+}
+
+int launch_sigma(const long long *s1, const unsigned long long *s2, const uint2 *vox, int64_t V,
+                 uint32_t nb, double rho_min, double frac, int kind, double *scratch,
+                 int nblocks, double *out, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  double *pmax = scratch;
+  double *psum = scratch + nblocks;
+  hipLaunchKernelGGL(k_sigma_max, dim3(nblocks), dim3(256), 0, s, s1, vox, V, rho_min, pmax);
+  hipLaunchKernelGGL(k_sigma_sum, dim3(nblocks), dim3(256), 0, s, s1, s2, vox, V, nb, rho_min,
+                     frac, kind, pmax, nblocks, psum);
+  hipLaunchKernelGGL(k_sigma_final, dim3(1), dim3(64), 0, s, psum, nblocks, pmax, out);
+  return check_launch();
+}
+
+int device_cu_count(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
+  return prop.multiProcessorCount;
+}
+
+}  // namespace ctd

@@ -1,0 +1,121 @@
+"""Marshalling helpers: hand a workload description to the C ABI.
+
+A workload is any object with the attributes used below (grid dict, mat and
+rho arrays, material names, mu_rho(), compton_pdf(), rayleigh_pdf(m),
+spectrum_lo/width/w, geometry dict, seed, n_batches, e_cut, rayleigh, e0, de,
+ne, n_zeta).  Inverse-CDF surfaces are built by the library's own FP64
+routine (ctd_surface_build); nothing here computes a step of the transport.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ctd as L
+
+_surface_cache: dict = {}
+
+
+def _grid(g: dict) -> L.ctd_grid:
+    out = L.ctd_grid()
+    out.nx, out.ny, out.nz = g["nx"], g["ny"], g["nz"]
+    out.dx, out.dy, out.dz = g["dx"], g["dy"], g["dz"]
+    out.origin[:] = (g["ox"], g["oy"], g["oz"])
+    return out
+
+
+def _geom(geo: dict) -> L.ctd_geom:
+    g = L.ctd_geom()
+    if geo["kind"] == "pencil":
+        g.kind = L.CTD_GEOM_PENCIL
+        g.src[:] = geo["src"]
+        g.dir[:] = geo["dir"]
+    else:
+        g.kind = L.CTD_GEOM_CONE
+        g.n_proj = geo["nproj"]
+        g.sad = geo["sad"]
+        g.iso[:] = geo["iso"]
+        g.a0, g.a1, g.b0, g.b1 = geo["a0"], geo["a1"], geo["b0"], geo["b1"]
+        g.phi0_deg, g.arc_deg = geo["phi0_deg"], geo["arc_deg"]
+    return g
+
+
+def surfaces(wl):
+    """(Compton surface [ne][nz], Rayleigh surfaces [M][ne][nz] or None),
+    cached by material and grid."""
+    key_c = ("compton", wl.e0, wl.de, wl.ne, wl.n_mu_c, wl.n_zeta)
+    if key_c not in _surface_cache:
+        _surface_cache[key_c] = L.ctd_surface_build(wl.compton_pdf(), wl.n_zeta)
+    comp = _surface_cache[key_c]
+    rayl = None
+    if wl.rayleigh:
+        rows = []
+        for m, name in enumerate(wl.materials):
+            key = ("rayleigh", name, wl.e0, wl.de, wl.ne, wl.n_mu_r, wl.n_zeta)
+            if key not in _surface_cache:
+                _surface_cache[key] = L.ctd_surface_build(wl.rayleigh_pdf(m), wl.n_zeta)
+            rows.append(_surface_cache[key])
+        rayl = np.stack(rows)
+    return comp, rayl
+
+
+class Case:
+    """One dose problem bound in the library (phantom, tables, spectrum,
+    geometry, case).  ``close()`` releases everything."""
+
+    def __init__(self, ctx, wl, mu_rho=None, seed=None, n_batches=None, rho_min=0.05,
+                 mat=None, rho=None, mem=L.CTD_MEM_HOST):
+        self.ctx = ctx
+        self.wl = wl
+        self.V = int(wl.grid["nx"] * wl.grid["ny"] * wl.grid["nz"])
+        m = np.ascontiguousarray(wl.mat if mat is None else mat)
+        r = np.ascontiguousarray(wl.rho if rho is None else rho)
+        if mem == L.CTD_MEM_HOST:
+            m = np.ascontiguousarray(m, dtype=np.uint8)
+            r = np.ascontiguousarray(r, dtype=np.float32)
+        self.ph = L.ctd_phantom_load(ctx, _grid(wl.grid), m, r, mem)
+        eg = L.ctd_egrid()
+        eg.e0, eg.de, eg.ne = wl.e0, wl.de, wl.ne
+        comp, rayl = surfaces(wl)
+        mu = wl.mu_rho() if mu_rho is None else mu_rho
+        self.ms = L.ctd_materials_load(ctx, eg, mu, comp, 0, rayl)
+        self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
+        self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
+        p = L.ctd_params()
+        p.e_cut_kev = wl.e_cut
+        p.seed = wl.seed if seed is None else seed
+        p.n_batches = wl.n_batches if n_batches is None else n_batches
+        p.rayleigh = int(wl.rayleigh)
+        p.sigma_rho_min = rho_min
+        self.params = p
+        self.cs = L.ctd_case_create(ctx, self.ph, self.ms, self.sp, self.geo, p)
+
+    # convenience pass-throughs
+    def run(self, n):
+        L.ctd_run(self.ctx, self.cs, n)
+
+    def tally(self):
+        return L.ctd_read_tally(self.ctx, self.cs, self.V)
+
+    def dose(self):
+        return L.ctd_read_dose(self.ctx, self.cs, self.V)
+
+    def balance(self):
+        return L.ctd_read_balance(self.ctx, self.cs)
+
+    def stats(self):
+        return L.ctd_read_stats(self.ctx, self.cs)
+
+    def close(self):
+        if self.cs is not None:
+            L.ctd_case_destroy(self.ctx, self.cs)
+            L.ctd_geometry_release(self.ctx, self.geo)
+            L.ctd_spectrum_release(self.ctx, self.sp)
+            L.ctd_materials_release(self.ctx, self.ms)
+            L.ctd_phantom_release(self.ctx, self.ph)
+            self.cs = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,315 @@
+"""GPU (libctd.so through the C ABI) against the FP64 CPU oracle.
+
+Paired streams: both sides draw the same Philox numbers for each history id,
+so trajectories coincide except at float32/float64 near-ties; the checks are
+the per-voxel 3-sigma criterion on >= 99 % of voxels above 10 % of the
+maximum dose and 1e-3 relative agreement of the total deposited energy, the
+exact integer energy balance of the GPU, bit-exact replay of the GPU deposit
+log through the oracle's tally routine, and per-history event pairing.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1109_3266_amd import ctd as L
+from paper_1109_3266_amd.session import Case
+from synth import workloads as W
+from tests._helpers import random_phantom
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    h = L.ctd_create(0)
+    yield h
+    L.ctd_destroy(h)
+
+
+def gpu_run(ctx, wl, n=None, log=None, tuning=None, **kw):
+    """Run wl on the GPU; returns dict of tally, balance, stats (and events)."""
+    n = wl.n_histories if n is None else n
+    with Case(ctx, wl, **kw) as c:
+        if tuning is not None:
+            L.ctd_set_tuning(ctx, c.cs, tuning)
+        if log is not None:
+            h0, nh, cap = log
+            L.ctd_debug_deposit_log(ctx, c.cs, h0, nh, cap)
+        c.run(n)
+        s1, hi, lo, nb = c.tally()
+        out = dict(s1=s1, s2_hi=hi, s2_lo=lo, nb=nb, bal=c.balance(), st=c.stats(),
+                   mu_max=L.ctd_read_majorant(ctx, c.cs, wl.ne))
+        if log is not None:
+            ev = L.ctd_read_event_log(ctx, c.cs, log[2])
+            out["log"] = ev[np.lexsort((ev["seq"], ev["h"]))]
+    return out
+
+
+def check_balance(g, n):
+    b = g["bal"]
+    assert b.n_histories == n
+    assert b.q_incident == b.q_deposited + b.q_escaped, "exact energy balance"
+    assert int(g["s1"].sum()) == b.q_deposited
+
+
+def paired_compare(g, r, min_frac=0.99):
+    m_g, v_g = O.batch_stats(g["s1"], g["s2_hi"], g["s2_lo"], g["nb"])
+    m_o, v_o = O.batch_stats(r["s1"], r["s2_hi"], r["s2_lo"], r["n_batches"])
+    mask = m_o > 0.1 * m_o.max()
+    ok = np.abs(m_g - m_o)[mask] <= 3.0 * np.sqrt(v_g + v_o)[mask]
+    frac = float(ok.mean())
+    rel = abs(g["bal"].q_deposited - r["q_dep"]) / r["q_dep"]
+    say(f"3-sigma {frac:.4f} over {mask.sum()} voxels, dE/E {rel:.2e}")
+    assert frac >= min_frac
+    assert rel <= 1e-3
+    return frac, rel
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("tiny", dict(n_histories=100_000)),
+    ("water_cbct", dict(n_histories=200_000, scale=4)),
+    ("head", dict(n_histories=200_000, scale=4)),
+])
+def test_paired_parity(ctx, name, kw):
+    say(f"paired parity {name} {kw}")
+    wl = W.by_name(name, **kw)
+    g = gpu_run(ctx, wl)
+    check_balance(g, wl.n_histories)
+    oc = O.OracleCase(wl)
+    assert np.array_equal(g["mu_max"], oc.mu_max), "majorant rule"
+    r = O.run(oc, threads=8)
+    paired_compare(g, r)
+    st = g["st"]
+    assert abs(st.n_steps - r["n_steps"]) <= 1e-3 * r["n_steps"]
+    assert abs(st.n_compton - r["n_compton"]) <= 2e-3 * r["n_compton"] + 5
+
+
+@pytest.mark.parametrize("shape,seed", [((2, 2, 2), 3), ((4, 4, 4), 5), ((3, 5, 7), 8)])
+def test_deposit_log_replay_bit_exact(ctx, shape, seed):
+    say(f"log replay {shape}")
+    wl = random_phantom(shape, 3, seed=seed, n_hist=10_000)
+    g = gpu_run(ctx, wl, n_batches=2, log=(0, 10_000, 200_000))
+    ev = g["log"]
+    dep = ev[np.isin(ev["type"], [1, 2, 4])]
+    T = O.tally_replay(dep["vox"], dep["e"], int(wl.mat.size))
+    assert np.array_equal(T, g["s1"])
+    check_balance(g, 10_000)
+    # every history ends exactly once
+    ends = ev[np.isin(ev["type"], [1, 4, 5, 6])]
+    assert np.array_equal(np.sort(ends["h"]), np.arange(10_000))
+
+
+def _pair_histories(gev, oev_by_h, hs):
+    same = 0
+    for h in hs:
+        a = gev[gev["h"] == h]
+        b = oev_by_h[h]
+        if len(a) == len(b) and np.array_equal(a["type"], b["type"]) and \
+                np.array_equal(a["vox"], b["vox"]) and np.array_equal(a["k"], b["k"]):
+            np.testing.assert_allclose(a["e"], b["e"], rtol=1e-4, atol=1e-4)
+            np.testing.assert_allclose(a["E"], b["E"], rtol=1e-4, atol=1e-4)
+            same += 1
+    return same / len(hs)
+
+
+def test_per_history_event_pairing(ctx):
+    say("per-history pairing water_cbct/4")
+    wl = W.water_cbct(scale=4, n_histories=20_000)
+    g = gpu_run(ctx, wl, log=(0, 5000, 200_000))
+    oc = O.OracleCase(wl)
+    r = O.run(oc, threads=8, log_range=(0, 5000), log_cap=200_000)
+    oev = r["log"]
+    by_h = {h: oev[oev["h"] == h] for h in range(5000)}
+    frac = _pair_histories(g["log"], by_h, range(5000))
+    say(f"identical histories {frac:.4f}")
+    assert frac >= 0.99
+
+
+def test_independent_seeds(ctx):
+    say("independent seeds head/4")
+    wl = W.head(scale=4, n_histories=400_000)
+    wl.n_batches = 40
+    g = gpu_run(ctx, wl, seed=101)
+    r = O.run(O.OracleCase(wl), threads=8)
+    m_g, v_g = O.batch_stats(g["s1"], g["s2_hi"], g["s2_lo"], g["nb"])
+    m_o, v_o = O.batch_stats(r["s1"], r["s2_hi"], r["s2_lo"], r["n_batches"])
+    mask = m_o > 0.1 * m_o.max()
+    ok = np.abs(m_g - m_o)[mask] <= 3.0 * np.sqrt(v_g + v_o)[mask]
+    say(f"independent 3-sigma {ok.mean():.4f}")
+    assert ok.mean() >= 0.99
+    tot_g, tot_o = g["bal"].q_deposited, r["q_dep"]
+    assert abs(tot_g - tot_o) / tot_o < 0.01
+
+
+def test_tuning_and_repeat_bit_identity(ctx):
+    say("bit identity across tunings")
+    wl = W.water_cbct(scale=4, n_histories=100_000)
+    outs = []
+    for blk, wps, rm, ch in [(256, 4, 16, 256), (256, 8, 1, 64), (512, 2, 64, 4096),
+                             (64, 1, 32, 1024), (256, 4, 16, 256)]:
+        t = L.ctd_tuning(blk, wps, rm, ch)
+        outs.append(gpu_run(ctx, wl, tuning=t))
+    for o in outs[1:]:
+        assert np.array_equal(o["s1"], outs[0]["s1"])
+        assert np.array_equal(o["s2_hi"], outs[0]["s2_hi"])
+        assert np.array_equal(o["s2_lo"], outs[0]["s2_lo"])
+        assert o["bal"].q_escaped == outs[0]["bal"].q_escaped
+        assert o["st"].n_steps == outs[0]["st"].n_steps
+
+
+def test_run_many_matches_solo(ctx):
+    say("batched engine vs solo")
+    cases = W.batched(n_cases=5, size_scale=0.2, hist_scale=1e-3)
+    solo = [gpu_run(ctx, wl) for wl in cases]
+    objs = [Case(ctx, wl) for wl in cases]
+    try:
+        L.ctd_run_many(ctx, [o.cs for o in objs], [wl.n_histories for wl in cases])
+        for o, s, wl in zip(objs, solo, cases):
+            s1, hi, lo, nb = o.tally()
+            assert nb == s["nb"]
+            assert np.array_equal(s1, s["s1"])
+            assert np.array_equal(hi, s["s2_hi"]) and np.array_equal(lo, s["s2_lo"])
+            b = o.balance()
+            assert b.q_incident == s["bal"].q_incident
+            assert b.q_incident == b.q_deposited + b.q_escaped
+    finally:
+        for o in objs:
+            o.close()
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 63, 64, 65, 100_003])
+def test_ragged_and_tiny_runs(ctx, n):
+    say(f"ragged n={n}")
+    wl = random_phantom((5, 6, 7), 4, seed=13, n_hist=max(n, 1))
+    g = gpu_run(ctx, wl, n=n, log=(0, max(n, 1), 40 * max(n, 1) + 100))
+    b = g["bal"]
+    assert b.n_histories == n
+    assert b.q_incident == b.q_deposited + b.q_escaped
+    ev = g["log"]
+    dep = ev[np.isin(ev["type"], [1, 2, 4])]
+    assert np.array_equal(O.tally_replay(dep["vox"], dep["e"], int(wl.mat.size)), g["s1"])
+    if n:
+        oc = O.OracleCase(wl)
+        bs = O.batch_sizes(n, wl.n_batches)
+        hs = range(min(n, 500))
+        by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
+        assert _pair_histories(ev, by_h, hs) >= 0.99
+
+
+def test_all_histories_miss(ctx):
+    say("pencil missing the box")
+    wl = W.tiny(n_histories=1000)
+    wl.geometry = dict(kind="pencil", src=(8.0, 8.0, -5.0), dir=(0.0, 0.0, -1.0))
+    g = gpu_run(ctx, wl)
+    b = g["bal"]
+    assert b.n_missed == 1000 and b.q_deposited == 0 and np.all(g["s1"] == 0)
+    assert b.q_escaped == b.q_incident == 1000 * 60 * 2**24
+
+
+def test_error_paths(ctx):
+    say("error paths")
+    wl = W.tiny(n_histories=10)
+    bad = W.tiny()
+    bad.mat = bad.mat.copy()
+    bad.mat[0, 0, 0] = 3
+    with pytest.raises(L.CtdError) as e:
+        Case(ctx, bad)
+    assert e.value.code == L.CTD_EINVAL
+    neg = W.tiny()
+    neg.rho = neg.rho.copy()
+    neg.rho[1, 2, 3] = -1.0
+    with pytest.raises(L.CtdError) as e:
+        Case(ctx, neg)
+    assert e.value.code == L.CTD_EINVAL
+    nan = W.tiny()
+    nan.rho = nan.rho.copy()
+    nan.rho[0, 0, 1] = np.nan
+    with pytest.raises(L.CtdError):
+        Case(ctx, nan)
+    with pytest.raises(L.CtdError):
+        Case(ctx, wl, n_batches=1)
+    hi = W.tiny()
+    hi.spectrum_lo = np.array([200.0])
+    with pytest.raises(L.CtdError):
+        Case(ctx, hi)
+    with Case(ctx, wl) as c:
+        with pytest.raises(L.CtdError) as e:
+            L.ctd_run(ctx, c.cs, 10**18)
+        assert e.value.code == L.CTD_EOVERFLOW
+        with pytest.raises(L.CtdError):
+            L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(100, 4, 16, 256))
+        with pytest.raises(L.CtdError):
+            L.ctd_read_dose(ctx, c.cs, c.V)      # no batches folded yet
+        c.run(1000)
+        assert c.balance().n_histories == 1000
+
+
+def test_run_to_sigma_and_host_sigma(ctx):
+    say("run to sigma water_cbct/4")
+    wl = W.water_cbct(scale=4)
+    with Case(ctx, wl) as c:
+        sig = L.ctd_run_to_sigma(ctx, c.cs, 0.03, 0.5, L.CTD_SIGMA_LOCAL, 20_000, 10_000_000)
+        assert sig <= 0.03
+        st = c.stats()
+        assert st.n_batches >= 10 and st.n_histories == st.n_batches * 20_000
+        dose, var = c.dose()
+        rho = wl.rho.reshape(-1)
+        inside = rho >= 0.05
+        d = np.where(inside, dose, 0)
+        m = d > 0.5 * d.max()
+        host = float(np.mean(np.sqrt(var[m]) / dose[m]))
+        assert host == pytest.approx(sig, rel=1e-9)
+        paper = L.ctd_sigma(ctx, c.cs, L.CTD_SIGMA_PAPER, 0.2)
+        m2 = d > 0.2 * d.max()
+        assert float(np.mean(np.sqrt(var[m2]) / d.max())) == pytest.approx(paper, rel=1e-9)
+        # dose against the oracle's readout formula on the same exact sums
+        s1, hi, lo, nb = c.tally()
+        res = dict(s1=s1, s2_hi=hi, s2_lo=lo, n_batches=nb)
+        d_o, sd_o = O.dose_and_sigma(res, O.OracleCase(wl), int(st.n_histories))
+        np.testing.assert_allclose(dose, d_o, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(np.sqrt(var), sd_o, rtol=1e-9, atol=1e-30)
+
+
+def test_full_size_water_cbct_sampled(ctx):
+    """The benchmark workload at full size (1e9 histories, 10 batches) in the
+    default launch configuration: exact balance, incident energy against its
+    expectation, and 2000 logged histories paired one by one with the oracle."""
+    wl = W.water_cbct()
+    h0, nh = 500_000_000, 2000
+    say("full-size water_cbct 1e9")
+    g = gpu_run(ctx, wl, log=(h0, nh, 100_000))
+    check_balance(g, wl.n_histories)
+    oc = O.OracleCase(wl)
+    bs = O.batch_sizes(wl.n_histories, 10)
+    cnt = O.alloc_bins(bs[0], oc.bin_w).astype(np.float64)
+    expect = 10 * np.sum(cnt * (oc.bin_lo + 0.5)) * 2**24
+    sd = np.sqrt(wl.n_histories / 12.0) * 2**24
+    assert abs(g["bal"].q_incident - expect) < 6 * sd
+    hs = range(h0, h0 + nh)
+    by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
+    frac = _pair_histories(g["log"], by_h, hs)
+    say(f"full-size pairing {frac:.4f}")
+    assert frac >= 0.99
+
+
+def test_full_size_head_grid_sampled(ctx):
+    wl = W.head(n_histories=200_000_000)
+    h0, nh = 123_456_789, 1000
+    say("full-grid head 2e8")
+    g = gpu_run(ctx, wl, log=(h0, nh, 100_000))
+    check_balance(g, wl.n_histories)
+    oc = O.OracleCase(wl)
+    assert np.array_equal(g["mu_max"], oc.mu_max)
+    bs = O.batch_sizes(wl.n_histories, 10)
+    hs = range(h0, h0 + nh)
+    by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
+    frac = _pair_histories(g["log"], by_h, hs)
+    say(f"head pairing {frac:.4f}")
+    assert frac >= 0.99
