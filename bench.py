@@ -1,0 +1,245 @@
+"""Benchmark: photon histories/s of the transport hot path on one MI355X.
+
+Workload (default): the cone-beam water cylinder -- 128x128x100 voxels of
+0.25x0.25x0.2 cm, water cylinder r = 15 cm in air, point source at 100 cm,
+26x20 cm field at the isocentre, 360 projections over 360 deg, 120 kVp
+Kramers spectrum with 2 mm Al in 1 keV bins 20-119 keV, Rayleigh on, 1e9
+histories in 10 batches of 1e8.  One step = one batch: transport launch plus
+the batch fold.  Inputs are resident in device memory before timing.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--quick]
+
+Prints one JSON line (rank 0).  Extra legs (time to 1 % sigma, batched
+engine vs per-case runs, serving) are included unless --quick.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photon histories/s + time-to-1%-σ dose; batched serving p50/p99 latency"
+BATCH = 100_000_000
+PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes/clk x 2.4 GHz (non-packed)
+
+# Algorithmic 32-bit lane operations per unit of work:
+OPS_STEP = 132       # Philox block 100, 2 uniforms 6, free path 2, move 3, inside 6,
+                     # voxel index 5, two table lerps + cumulative 7, selection 3
+OPS_SCATTER = 46     # 2 uniforms 6, bilinear surface 12, rotation 28
+OPS_COMPTON = 13     # kinematics 4, energy-grid update 7, deposit conversion 2
+OPS_HISTORY = 170    # source block 100 + 4 uniforms 12, projection/source/field 12,
+                     # direction 8, slab entry 30, energy-grid set-up 8
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1109_3266_amd", "csrc", "ctd_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str, launch_histories: int):
+    """HBM bytes per transport launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"k_transport_{workload}_pmc.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_sha") != kernel_source_hash():
+        return None
+    per_hist = d["hbm_bytes_per_launch"] / d["histories_per_launch"]
+    return per_hist * launch_histories
+
+
+def cpu_baseline(wl, n_hist: int):
+    from oracle import oracle as O
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = max(1, min(cores, 16))
+    c = O.OracleCase(wl)
+    t0 = time.perf_counter()
+    r = O.run(c, n_histories=n_hist, n_batches=10, threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=r["n_hist"] / dt, unit="histories/s", cores=threads, kind="oracle",
+                sample=f"{n_hist:.0e} histories of the same workload, 10 batches, "
+                       f"FP64 CPU oracle, {threads} threads, {dt:.1f} s"), r
+
+
+def batched_leg(ctx, L, W, Case, tuning, torch, hist_scale):
+    """48 uneven cases: each run alone back to back (plain per-case launches)
+    vs one batched launch per round over all cases; results must match."""
+    import numpy as np
+    log("batched: generating 48 cases")
+    cases = W.batched(hist_scale=hist_scale)
+    objs = [Case(ctx, wl) for wl in cases]
+    ns = [wl.n_histories for wl in cases]
+    total = float(sum(ns))
+    for o in objs:
+        L.ctd_set_tuning(ctx, o.cs, tuning)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for o, n in zip(objs, ns):
+        L.ctd_run(ctx, o.cs, n)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ref = [o.tally()[0] for o in objs[:4]]
+    for o in objs:
+        L.ctd_case_reset(ctx, o.cs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.ctd_run_many(ctx, [o.cs for o in objs], ns)
+    torch.cuda.synchronize()
+    t_many = time.perf_counter() - t0
+    same = all(np.array_equal(r, o.tally()[0]) for r, o in zip(ref, objs[:4]))
+    for o in objs:
+        o.close()
+    log(f"batched {total / t_many:.4g} vs plain {total / t_plain:.4g} histories/s")
+    return dict(cases=len(cases), histories=total, histories_per_s=total / t_many,
+                plain_histories_per_s=total / t_plain, speedup=t_plain / t_many,
+                identical_to_plain=bool(same))
+
+
+def calibrate_copy():
+    """A plain device copy of known size, for scaling HBM counters."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes_read=n, copy_bytes_written=n, launches=3)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="main leg only")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--cpu-histories", type=int, default=6_000_000)
+    ap.add_argument("--batched-scale", type=float, default=1.0)
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the transport on a single "
+              "MI355X (histories shard across GPUs by id range; not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1109_3266_amd import ctd as L
+    from paper_1109_3266_amd.session import Case
+    from synth import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx = L.ctd_create(0)
+    L.ctd_set_stream(ctx, stream.cuda_stream)
+    log("building water_cbct workload")
+    wl = W.water_cbct()
+    case = Case(ctx, wl)
+    tuning = L.ctd_get_tuning(ctx, case.cs)
+    if not args.no_tune:
+        tuning = L.ctd_autotune(ctx, case.cs, 20_000_000)
+    log(f"tuning block={tuning.block} waves/simd={tuning.waves_per_simd} "
+        f"refill_min={tuning.refill_min} chunk={tuning.chunk}")
+
+    L.ctd_run_batches(ctx, case.cs, BATCH, args.warmup)
+    torch.cuda.synchronize()
+    st0 = L.ctd_read_stats(ctx, case.cs)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    L.ctd_run_batches(ctx, case.cs, BATCH, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    st1 = L.ctd_read_stats(ctx, case.cs)
+    bal = L.ctd_read_balance(ctx, case.cs)
+    assert bal.q_incident == bal.q_deposited + bal.q_escaped, "energy balance broken"
+    n_timed = args.steps * BATCH
+    value = n_timed / wall
+    log(f"{value:.4g} histories/s ({wall:.3f} s wall, {gpu_ms:.1f} ms events)")
+
+    # roofline of the dominant kernel (k_transport): one launch = one batch
+    d_steps = st1.n_steps - st0.n_steps
+    d_scat = (st1.n_compton - st0.n_compton) + (st1.n_rayleigh - st0.n_rayleigh)
+    d_comp = st1.n_compton - st0.n_compton
+    ops = (OPS_STEP * d_steps + OPS_SCATTER * d_scat + OPS_COMPTON * d_comp +
+           OPS_HISTORY * n_timed)
+    launch_ms = (st1.transport_ms - st0.transport_ms) / args.steps
+    achieved = ops / args.steps / (launch_ms * 1e-3)
+    traffic = load_traffic("water_cbct", BATCH)
+    roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_LANE_OPS / 1e12,
+                unit="T lane-ops/s", frac=achieved / PEAK_LANE_OPS, traffic=traffic,
+                kernel="k_transport", launch_ms=launch_ms,
+                ops_per_history=ops / n_timed,
+                steps_per_history=d_steps / n_timed)
+    out = dict(metric=METRIC, value=value, unit="histories/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=wall * 1e3 / args.steps, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload="water_cbct_128x128x100_cyl30cm_120kVp_cbct360",
+                           histories_per_step=BATCH, histories_total=(args.steps + args.warmup)
+                           * BATCH, voxels=wl.n_voxels, tally="int64 fixed point 2^-24 keV",
+                           tuning=dict(block=tuning.block, waves_per_simd=tuning.waves_per_simd,
+                                       refill_min=tuning.refill_min, chunk=tuning.chunk)),
+               roofline=roof,
+               transport_only_histories_per_s=n_timed / ((st1.transport_ms - st0.transport_ms)
+                                                         * 1e-3),
+               sigma_local=L.ctd_sigma(ctx, case.cs, L.CTD_SIGMA_LOCAL, 0.5),
+               sigma_paper=L.ctd_sigma(ctx, case.cs, L.CTD_SIGMA_PAPER, 0.2),
+               paper_context="gCTD: ~17 s at 0.4 % mean relative sigma (s/D_max over "
+                             "D > 20 % D_max), Zubal HN, 2.5e8 histories, Tesla C2050 FP32")
+    case.close()
+
+    if not args.quick:
+        # time to 1 % sigma on the same workload, from a fresh case
+        log("time to 1% sigma")
+        c2 = Case(ctx, wl)
+        L.ctd_set_tuning(ctx, c2.cs, tuning)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sig = L.ctd_run_to_sigma(ctx, c2.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, BATCH,
+                                 200_000_000_000)
+        tts = time.perf_counter() - t0
+        s2 = L.ctd_read_stats(ctx, c2.cs)
+        out["time_to_1pct_sigma"] = dict(seconds=tts, sigma_local=sig,
+                                         histories=s2.n_histories, batches=s2.n_batches,
+                                         sigma_paper=L.ctd_sigma(ctx, c2.cs,
+                                                                 L.CTD_SIGMA_PAPER, 0.2))
+        c2.close()
+        log(f"time to 1% sigma {tts:.2f} s ({s2.n_histories:.3g} histories)")
+        out["batched"] = batched_leg(ctx, L, W, Case, tuning, torch, args.batched_scale)
+
+    if not args.no_cpu:
+        log("cpu baseline")
+        cb, _ = cpu_baseline(wl, args.cpu_histories)
+        out["cpu_baseline"] = cb
+    L.ctd_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

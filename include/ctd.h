@@ -219,6 +219,10 @@ int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histories, ctd_t
  * CTD_EOVERFLOW if the case's cumulative histories * E_max * 2^24 >= 2^63. */
 int32_t ctd_run(ctd_ctx *ctx, ctd_case *cs, uint64_t n_histories);
 
+/* Run `count` batches of exactly batch_histories each (same per-batch work
+ * as ctd_run), continuing the case's history ids.  Async. */
+int32_t ctd_run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch_histories, uint64_t count);
+
 /* Add batches of batch_histories until sigma-bar (sigma_kind, threshold
  * dose_frac * D_max) <= target with >= n_batches batches, or max_histories
  * is reached: a pilot of n_batches batches, then the estimated remainder

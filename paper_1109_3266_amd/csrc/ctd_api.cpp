@@ -833,6 +833,14 @@ int ctd::run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count)
   return CTD_OK;
 }
 
+extern "C" int32_t ctd_run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch_histories,
+                                   uint64_t count) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (batch_histories == 0 || count == 0) return CTD_OK;
+  return run_batches(ctx, cs, batch_histories, count);
+}
+
 extern "C" int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, double dose_frac,
                                     int32_t sigma_kind, uint64_t batch_histories,
                                     uint64_t max_histories, double *achieved) {

@@ -24,6 +24,15 @@
 
 namespace ctd {
 
+// Pointers the step loop dereferences are tagged with the global address
+// space so they compile to global_* (not flat_*) memory instructions (the
+// tag only exists in the device compilation pass).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL __attribute__((address_space(1)))
+#else
+#define GLOBAL
+#endif
+
 // ---------------------------------------------------------------- helpers
 
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0,
@@ -58,7 +67,8 @@ __device__ __forceinline__ float cos_turns(float t) { return __builtin_amdgcn_co
 
 // Inverse-CDF surface mu(zeta, E): one 16-byte cell gives both zeta
 // neighbours at both energy neighbours; bilinear, clamped to [-1, 1].
-__device__ __forceinline__ float surface(const float4 *__restrict__ Q, int nz, int je, float we,
+__device__ __forceinline__ float surface(const GLOBAL float4 *__restrict__ Q, int nz, int je,
+                                         float we,
                                          float zeta) {
   const float f = zeta * (float)(nz - 1);
   const int i = min((int)f, nz - 2);
@@ -80,81 +90,124 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ------------------------------------------------------------ lane state
-
-struct Counters {
-  unsigned long long q_inc, q_dep, q_esc;
-  uint32_t n_hist, n_steps, n_photo, n_compton, n_rayleigh, n_dep, n_esc, n_miss, n_unsc,
-      n_cut, n_guard;
-  __device__ void clear() {
-    q_inc = q_dep = q_esc = 0ull;
-    n_hist = n_steps = n_photo = n_compton = n_rayleigh = n_dep = n_esc = n_miss = n_unsc =
-        n_cut = n_guard = 0u;
-  }
+// The fields the step loop reads, as one wave-uniform record.  It is filled
+// with readfirstlane on every case switch, so the compiler keeps it in scalar
+// registers; everything else about a case (source geometry, counters, log)
+// is read from the wave's LDS copy of the full descriptor.
+struct StepCase {
+  const GLOBAL uint2 *vox;
+  const GLOBAL float4 *mu_rho;
+  const GLOBAL float *mu_max;
+  const GLOBAL float4 *comp_quad;
+  const GLOBAL float4 *rayl_quad;
+  GLOBAL unsigned long long *tally;
+  float fnx, fny, fnz, inv_dx, inv_dy, inv_dz, e0, inv_de, e_cut;
+  int32_t nx, ny, ne, nzc, nzr, rayleigh, comp_per_mat;
+  uint32_t key0, key1;
 };
 
-__device__ void flush(Counters &c, const CaseDev *cd, int lane, uint32_t refills) {
-  const unsigned long long q_inc = wave_sum(c.q_inc);
-  const unsigned long long q_dep = wave_sum(c.q_dep);
-  const unsigned long long q_esc = wave_sum(c.q_esc);
-  const uint32_t v[11] = {wave_sum(c.n_hist),  wave_sum(c.n_steps), wave_sum(c.n_photo),
-                          wave_sum(c.n_compton), wave_sum(c.n_rayleigh), wave_sum(c.n_dep),
-                          wave_sum(c.n_esc),   wave_sum(c.n_miss),  wave_sum(c.n_unsc),
-                          wave_sum(c.n_cut),   wave_sum(c.n_guard)};
-  if (lane == 0) {
-    unsigned long long *a = cd->acc;
-    if (q_inc) atomic_add_u64(a + ACC_Q_INC, q_inc);
-    if (q_dep) atomic_add_u64(a + ACC_Q_DEP, q_dep);
-    if (q_esc) atomic_add_u64(a + ACC_Q_ESC, q_esc);
-    const int idx[11] = {ACC_N_HIST,    ACC_N_STEPS, ACC_N_PHOTO, ACC_N_COMPTON,
-                         ACC_N_RAYLEIGH, ACC_N_DEPOSITS, ACC_N_ESCAPES, ACC_N_MISS,
-                         ACC_N_UNSCATTERED, ACC_N_CUTOFF, ACC_STEP_GUARD};
-#pragma unroll
-    for (int i = 0; i < 11; ++i)
-      if (v[i]) atomic_add_u64(a + idx[i], v[i]);
-    if (refills) atomic_add_u64(a + ACC_N_REFILLS, refills);
+template <typename T>
+__device__ __forceinline__ GLOBAL T *uniform_ptr(T *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (GLOBAL T *)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ int32_t uniform_i(int32_t x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ __forceinline__ StepCase make_step_case(const CaseDev &c) {
+  StepCase s;
+  s.vox = uniform_ptr(c.vox);
+  s.mu_rho = uniform_ptr(c.mu_rho);
+  s.mu_max = uniform_ptr(c.mu_max);
+  s.comp_quad = uniform_ptr(c.comp_quad);
+  s.rayl_quad = uniform_ptr(c.rayl_quad);
+  s.tally = uniform_ptr(c.tally);
+  s.fnx = uniform_f(c.fnx);
+  s.fny = uniform_f(c.fny);
+  s.fnz = uniform_f(c.fnz);
+  s.inv_dx = uniform_f(c.inv_dx);
+  s.inv_dy = uniform_f(c.inv_dy);
+  s.inv_dz = uniform_f(c.inv_dz);
+  s.e0 = uniform_f(c.e0);
+  s.inv_de = uniform_f(c.inv_de);
+  s.e_cut = uniform_f(c.e_cut);
+  s.nx = uniform_i(c.nx);
+  s.ny = uniform_i(c.ny);
+  s.ne = uniform_i(c.ne);
+  s.nzc = uniform_i(c.nzc);
+  s.nzr = uniform_i(c.nzr);
+  s.rayleigh = uniform_i(c.rayleigh);
+  s.comp_per_mat = uniform_i(c.comp_per_mat);
+  s.key0 = (uint32_t)uniform_i((int32_t)c.key0);
+  s.key1 = (uint32_t)uniform_i((int32_t)c.key1);
+  return s;
+}
+
+__device__ __forceinline__ uint64_t lane0_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, 0);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), 0);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// ------------------------------------------------------------ lane state
+
+// Per-wave event counters in LDS (one slot of ACC_COUNT words per wave),
+// bumped with LDS atomics when an event happens and added to the case's
+// device counters when the wave switches case or exits.  Keeping them out of
+// registers leaves room for more resident waves.
+struct Counters {
+  unsigned long long *s;
+  __device__ __forceinline__ void add(int i, unsigned long long v) { atomicAdd(s + i, v); }
+};
+
+__device__ void flush(Counters &c, unsigned long long *acc, int lane, uint32_t refills) {
+  if (lane == 0 && refills) c.add(ACC_N_REFILLS, refills);
+  if (lane < ACC_COUNT) {
+    const unsigned long long v = atomicExch(c.s + lane, 0ull);
+    if (v) atomic_add_u64(acc + lane, v);
   }
-  c.clear();
 }
 
 struct Photon {
   float px, py, pz;   // position, voxel units
   float ux, uy, uz;   // unit direction
-  float vx, vy, vz;   // direction in voxel units per cm
   float E;            // keV
   float mumax;        // majorant at E, cm^-1
   float sc;           // ln2 / mumax
   float we;           // energy-grid weight
   int je;             // energy-grid cell
-  uint32_t hlo, hhi, k, seq;
-  bool scattered;
+  uint32_t hlo, hhi;  // history id
+  uint32_t k;         // Woodcock step counter; bit 31 = has scattered
+  uint32_t seq;       // event sequence (debug log only)
 };
 
-__device__ __forceinline__ void set_energy(Photon &p, const CaseDev *cd, float E) {
+constexpr uint32_t kScatBit = 0x80000000u;
+
+__device__ __forceinline__ void set_energy(Photon &p, const StepCase &S, float E) {
   p.E = E;
-  const float f = (E - cd->e0) * cd->inv_de;
-  const int j = min(max((int)f, 0), cd->ne - 2);
+  const float f = (E - S.e0) * S.inv_de;
+  const int j = min(max((int)f, 0), S.ne - 2);
   p.je = j;
   p.we = f - (float)j;
-  p.mumax = lerpf(cd->mu_max[j], cd->mu_max[j + 1], p.we);
-  p.sc = 0.69314718055994531f / p.mumax;
-}
-
-__device__ __forceinline__ void set_dir(Photon &p, const CaseDev *cd) {
-  p.vx = p.ux * cd->inv_dx;
-  p.vy = p.uy * cd->inv_dy;
-  p.vz = p.uz * cd->inv_dz;
+  p.mumax = lerpf(S.mu_max[j], S.mu_max[j + 1], p.we);
+  p.sc = 0.69314718055994531f * __builtin_amdgcn_rcpf(p.mumax);
 }
 
 // Direction after deflection cos(theta) = mu and azimuth 2 pi t (t in turns).
 __device__ __forceinline__ void rotate(Photon &p, float mu, float t) {
-  const float st = sqrtf(fmaxf(0.0f, (1.0f - mu) * (1.0f + mu)));
+  const float st = __builtin_amdgcn_sqrtf(fmaxf(0.0f, (1.0f - mu) * (1.0f + mu)));
   const float sp = sin_turns(t), cp = cos_turns(t);
   const float u = p.ux, v = p.uy, w = p.uz;
   float nu, nv, nw;
   if (fabsf(w) < 1.0f - 1e-5f) {
-    const float r = sqrtf((1.0f - w) * (1.0f + w));
-    const float g = st / r;
+    const float r = __builtin_amdgcn_sqrtf((1.0f - w) * (1.0f + w));
+    const float g = st * __builtin_amdgcn_rcpf(r);
     nu = fmaf(u, mu, g * (u * w * cp - v * sp));
     nv = fmaf(v, mu, g * (v * w * cp + u * sp));
     nw = fmaf(w, mu, -st * cp * r);
@@ -170,186 +223,188 @@ __device__ __forceinline__ void rotate(Photon &p, float mu, float t) {
 }
 
 template <bool LOG>
-__device__ __forceinline__ void log_event(const CaseDev *cd, Photon &p, int type, int64_t vox,
+__device__ __forceinline__ void log_event(const CaseDev &G, Photon &p, int type, int64_t vox,
                                           float e, float Eafter) {
   if (!LOG) return;
   const uint64_t h = ((uint64_t)p.hhi << 32) | p.hlo;
-  if (h < cd->log_h0 || h >= cd->log_h1) return;
-  const unsigned long long idx = atomicAdd(cd->log_n, 1ull);
-  if (idx < cd->log_cap) {
+  if (h < G.log_h0 || h >= G.log_h1) return;
+  const unsigned long long idx = atomicAdd(G.log_n, 1ull);
+  if (idx < G.log_cap) {
     ctd_event ev;
     ev.h = h;
     ev.seq = p.seq;
-    ev.k = p.k;
+    ev.k = p.k & ~kScatBit;
     ev.type = type;
     ev.reserved = 0;
     ev.vox = vox;
     ev.e = e;
     ev.E = Eafter;
-    cd->log[idx] = ev;
+    G.log[idx] = ev;
   }
   p.seq += 1;
 }
 
 template <bool LOG>
-__device__ __forceinline__ void deposit(const CaseDev *cd, Photon &p, Counters &c, int32_t vox,
-                                        float e, int type, float Eafter) {
+__device__ __forceinline__ void deposit(const StepCase &S, const CaseDev &G, Photon &p,
+                                        Counters &c, int32_t vox, float e, int type,
+                                        float Eafter) {
   const uint32_t q = (uint32_t)(e * kQScale);  // exact: e is a multiple of 2^-24 keV
-  if (q) atomic_add_u64(cd->tally + vox, (unsigned long long)q);
-  c.q_dep += q;
-  c.n_dep += 1;
-  log_event<LOG>(cd, p, type, vox, e, Eafter);
+  if (q) {
+    __hip_atomic_fetch_add(S.tally + vox, (unsigned long long)q, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    c.add(ACC_Q_DEP, q);
+  }
+  c.add(ACC_N_DEPOSITS, 1);
+  log_event<LOG>(G, p, type, vox, e, Eafter);
 }
 
 // Source photon of history h from spectrum bin j (Sec. 2.2.5-2.2.6); returns
 // false when the ray misses the voxel box (the photon escapes at once).
 template <bool LOG>
-__device__ bool source(Photon &p, const CaseDev *cd, uint64_t h, int j, Counters &c) {
+__device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t h, int j,
+                       Counters &c) {
   p.hlo = (uint32_t)h;
   p.hhi = (uint32_t)(h >> 32);
   p.k = 0;
   p.seq = 0;
-  p.scattered = false;
-  const uint4 r = philox10(0u, p.hlo, p.hhi, cd->key0, cd->key1);
-  const float E = fmaf(unif(r.x), cd->bin_width, cd->bin_lo[j]);
+  const uint4 r = philox10(0u, p.hlo, p.hhi, S.key0, S.key1);
+  const float E = fmaf(unif(r.x), G.bin_width, G.bin_lo[j]);
   float sx, sy, sz, dx, dy, dz;
-  if (cd->kind == CTD_GEOM_PENCIL) {
-    sx = cd->src[0]; sy = cd->src[1]; sz = cd->src[2];
-    dx = cd->dir[0]; dy = cd->dir[1]; dz = cd->dir[2];
+  if (G.kind == CTD_GEOM_PENCIL) {
+    sx = G.src[0]; sy = G.src[1]; sz = G.src[2];
+    dx = G.dir[0]; dy = G.dir[1]; dz = G.dir[2];
   } else {
     float sp, cp;
-    if (cd->nproj > 0) {
+    if (G.nproj > 0) {
       // exact in double: 24-bit uniform times an integer < 2^31
-      int pi = (int)((double)unif(r.y) * (double)cd->nproj);
-      pi = min(pi, cd->nproj - 1);
-      const float2 sc = cd->proj_sc[pi];
+      int pi = (int)((double)unif(r.y) * (double)G.nproj);
+      pi = min(pi, G.nproj - 1);
+      const float2 sc = G.proj_sc[pi];
       sp = sc.x;
       cp = sc.y;
     } else {
-      const float t = fmaf(unif(r.y), cd->arc_turns, cd->phi0_turns);
+      const float t = fmaf(unif(r.y), G.arc_turns, G.phi0_turns);
       sp = sin_turns(t);
       cp = cos_turns(t);
     }
-    sx = fmaf(cd->sad, sp, cd->iso[0]);
-    sy = fmaf(cd->sad, cp, cd->iso[1]);
-    sz = cd->iso[2];
-    const float a = fmaf(unif(r.z), cd->a1 - cd->a0, cd->a0);
-    const float b = fmaf(unif(r.w), cd->b1 - cd->b0, cd->b0);
-    const float Px = fmaf(a, cp, cd->iso[0]);
-    const float Py = fmaf(-a, sp, cd->iso[1]);
-    const float Pz = cd->iso[2] + b;
+    sx = fmaf(G.sad, sp, G.iso[0]);
+    sy = fmaf(G.sad, cp, G.iso[1]);
+    sz = G.iso[2];
+    const float a = fmaf(unif(r.z), G.a1 - G.a0, G.a0);
+    const float b = fmaf(unif(r.w), G.b1 - G.b0, G.b0);
+    const float Px = fmaf(a, cp, G.iso[0]);
+    const float Py = fmaf(-a, sp, G.iso[1]);
+    const float Pz = G.iso[2] + b;
     const float vx = Px - sx, vy = Py - sy, vz = Pz - sz;
     const float inv = rsqrtf(vx * vx + vy * vy + vz * vz);
     dx = vx * inv; dy = vy * inv; dz = vz * inv;
   }
-  c.n_hist += 1;
-  c.q_inc += (uint32_t)(E * kQScale);
+  c.add(ACC_N_HIST, 1);
+  c.add(ACC_Q_INC, (uint32_t)(E * kQScale));
   p.E = E;
-  log_event<LOG>(cd, p, 0, -1, E, E);
+  log_event<LOG>(G, p, 0, -1, E, E);
   // slab entry into the box [0, n) in voxel units
-  const float S[3] = {(sx - cd->ox) * cd->inv_dx, (sy - cd->oy) * cd->inv_dy,
-                      (sz - cd->oz) * cd->inv_dz};
-  const float D[3] = {dx * cd->inv_dx, dy * cd->inv_dy, dz * cd->inv_dz};
-  const float N[3] = {cd->fnx, cd->fny, cd->fnz};
+  const float Sv[3] = {(sx - G.ox) * S.inv_dx, (sy - G.oy) * S.inv_dy, (sz - G.oz) * S.inv_dz};
+  const float D[3] = {dx * S.inv_dx, dy * S.inv_dy, dz * S.inv_dz};
+  const float N[3] = {S.fnx, S.fny, S.fnz};
   float tn = -INFINITY, tf = INFINITY;
   bool miss = false;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (D[a] == 0.0f) {
-      miss |= (S[a] < 0.0f) | (S[a] > N[a]);
+      miss |= (Sv[a] < 0.0f) | (Sv[a] > N[a]);
     } else {
-      const float inv = 1.0f / D[a];
-      const float t1 = (0.0f - S[a]) * inv, t2 = (N[a] - S[a]) * inv;
+      const float inv = __builtin_amdgcn_rcpf(D[a]);
+      const float t1 = (0.0f - Sv[a]) * inv, t2 = (N[a] - Sv[a]) * inv;
       tn = fmaxf(tn, fminf(t1, t2));
       tf = fminf(tf, fmaxf(t1, t2));
     }
   }
   const float tin = fmaxf(tn, 0.0f);
   if (miss || !(tin < tf)) {
-    c.n_miss += 1;
-    c.q_esc += (uint32_t)(E * kQScale);
-    log_event<LOG>(cd, p, 6, -1, E, E);
+    c.add(ACC_N_MISS, 1);
+    c.add(ACC_Q_ESC, (uint32_t)(E * kQScale));
+    log_event<LOG>(G, p, 6, -1, E, E);
     return false;
   }
   // entry point, kept inside [0, n) against rounding
-  const float top[3] = {__int_as_float(__float_as_int(N[0]) - 1),
-                        __int_as_float(__float_as_int(N[1]) - 1),
-                        __int_as_float(__float_as_int(N[2]) - 1)};
-  p.px = fminf(fmaxf(fmaf(tin, D[0], S[0]), 0.0f), top[0]);
-  p.py = fminf(fmaxf(fmaf(tin, D[1], S[1]), 0.0f), top[1]);
-  p.pz = fminf(fmaxf(fmaf(tin, D[2], S[2]), 0.0f), top[2]);
+  p.px = fminf(fmaxf(fmaf(tin, D[0], Sv[0]), 0.0f), __int_as_float(__float_as_int(N[0]) - 1));
+  p.py = fminf(fmaxf(fmaf(tin, D[1], Sv[1]), 0.0f), __int_as_float(__float_as_int(N[1]) - 1));
+  p.pz = fminf(fmaxf(fmaf(tin, D[2], Sv[2]), 0.0f), __int_as_float(__float_as_int(N[2]) - 1));
   p.ux = dx; p.uy = dy; p.uz = dz;
-  set_dir(p, cd);
-  set_energy(p, cd, E);
+  set_energy(p, S, E);
   return true;
 }
 
 // One Woodcock step (Sec. 2.1); returns false when the photon is done.
 template <bool LOG>
-__device__ __forceinline__ bool step(Photon &p, const CaseDev *cd, Counters &c) {
+__device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G, Counters &c) {
   p.k += 1;
-  c.n_steps += 1;
-  if (p.k > kStepGuard) {
-    c.n_guard += 1;
+  const uint32_t k = p.k & ~kScatBit;
+  if (k > kStepGuard) {
+    c.add(ACC_STEP_GUARD, 1);
+    c.add(ACC_N_STEPS, k);
     return false;
   }
-  const uint4 r = philox10(p.k, p.hlo, p.hhi, cd->key0, cd->key1);
+  const uint4 r = philox10(k, p.hlo, p.hhi, S.key0, S.key1);
   const float s = -__log2f(unif(r.x)) * p.sc;  // -ln(u) / mu_max
-  p.px = fmaf(s, p.vx, p.px);
-  p.py = fmaf(s, p.vy, p.py);
-  p.pz = fmaf(s, p.vz, p.pz);
-  const bool inside = (p.px >= 0.0f) & (p.px < cd->fnx) & (p.py >= 0.0f) & (p.py < cd->fny) &
-                      (p.pz >= 0.0f) & (p.pz < cd->fnz);
+  p.px = fmaf(s, p.ux * S.inv_dx, p.px);
+  p.py = fmaf(s, p.uy * S.inv_dy, p.py);
+  p.pz = fmaf(s, p.uz * S.inv_dz, p.pz);
+  const bool inside = (p.px >= 0.0f) & (p.px < S.fnx) & (p.py >= 0.0f) & (p.py < S.fny) &
+                      (p.pz >= 0.0f) & (p.pz < S.fnz);
   if (!inside) {
-    c.n_esc += 1;
-    c.n_unsc += p.scattered ? 0u : 1u;
-    c.q_esc += (uint32_t)(p.E * kQScale);
-    log_event<LOG>(cd, p, 5, -1, p.E, p.E);
+    c.add(ACC_N_STEPS, k);
+    c.add(ACC_N_ESCAPES, 1);
+    if (!(p.k & kScatBit)) c.add(ACC_N_UNSCATTERED, 1);
+    c.add(ACC_Q_ESC, (uint32_t)(p.E * kQScale));
+    log_event<LOG>(G, p, 5, -1, p.E, p.E);
     return false;
   }
-  const int32_t vox = ((int32_t)p.pz * cd->ny + (int32_t)p.py) * cd->nx + (int32_t)p.px;
-  const uint2 rec = cd->vox[vox];
+  const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)p.pz, (uint32_t)S.ny) + (uint32_t)p.py,
+                                         (uint32_t)S.nx) + (int32_t)p.px;
+  const uint2 rec = S.vox[vox];
   const float rho = __uint_as_float(rec.x);
   const int m = (int)rec.y;
-  const float4 *t = cd->mu_rho + (size_t)m * (size_t)cd->ne + (size_t)p.je;
+  const GLOBAL float4 *t = S.mu_rho + (size_t)m * (size_t)S.ne + (size_t)p.je;
   const float4 t0 = t[0], t1 = t[1];
   const float mpe = rho * lerpf(t0.x, t1.x, p.we);
   const float c1 = mpe + rho * lerpf(t0.y, t1.y, p.we);
   const float xi = unif(r.y) * p.mumax;
   if (xi < mpe) {  // photoelectric: absorb, deposit E locally
-    c.n_photo += 1;
-    deposit<LOG>(cd, p, c, vox, p.E, 1, 0.0f);
+    c.add(ACC_N_STEPS, k);
+    c.add(ACC_N_PHOTO, 1);
+    deposit<LOG>(S, G, p, c, vox, p.E, 1, 0.0f);
     return false;
   }
   if (xi < c1) {  // Compton (Sec. 2.2.3): angle from the C surface
-    c.n_compton += 1;
-    p.scattered = true;
-    const float4 *Q = cd->comp_quad;
-    if (cd->comp_per_mat) Q += (size_t)m * (size_t)(cd->ne - 1) * (size_t)(cd->nzc - 1);
-    const float mu = surface(Q, cd->nzc, p.je, p.we, unif(r.z));
+    c.add(ACC_N_COMPTON, 1);
+    p.k |= kScatBit;
+    const GLOBAL float4 *Q = S.comp_quad;
+    if (S.comp_per_mat) Q += (size_t)m * (size_t)(S.ne - 1) * (size_t)(S.nzc - 1);
+    const float mu = surface(Q, S.nzc, p.je, p.we, unif(r.z));
     const float E = p.E;
-    const float Ep = E / fmaf(E * kInvMeC2, 1.0f - mu, 1.0f);
-    deposit<LOG>(cd, p, c, vox, E - Ep, 2, Ep);  // exact: Ep > E/2 (Sterbenz)
+    const float Ep = E * __builtin_amdgcn_rcpf(fmaf(E * kInvMeC2, 1.0f - mu, 1.0f));
+    deposit<LOG>(S, G, p, c, vox, E - Ep, 2, Ep);  // exact: Ep > E/2 (Sterbenz)
     rotate(p, mu, unif(r.w));
-    set_dir(p, cd);
-    set_energy(p, cd, Ep);
-    if (Ep < cd->e_cut) {
-      c.n_cut += 1;
-      deposit<LOG>(cd, p, c, vox, Ep, 4, 0.0f);
+    set_energy(p, S, Ep);
+    if (Ep < S.e_cut) {
+      c.add(ACC_N_STEPS, k);
+      c.add(ACC_N_CUTOFF, 1);
+      deposit<LOG>(S, G, p, c, vox, Ep, 4, 0.0f);
       return false;
     }
     return true;
   }
-  if (cd->rayleigh) {
+  if (S.rayleigh) {
     const float c2 = c1 + rho * lerpf(t0.z, t1.z, p.we);
     if (xi < c2) {  // Rayleigh (Sec. 2.2.2): angle from the R surface, E unchanged
-      c.n_rayleigh += 1;
-      p.scattered = true;
-      const float4 *Q = cd->rayl_quad + (size_t)m * (size_t)(cd->ne - 1) * (size_t)(cd->nzr - 1);
-      const float mu = surface(Q, cd->nzr, p.je, p.we, unif(r.z));
+      c.add(ACC_N_RAYLEIGH, 1);
+      p.k |= kScatBit;
+      const GLOBAL float4 *Q = S.rayl_quad + (size_t)m * (size_t)(S.ne - 1) * (size_t)(S.nzr - 1);
+      const float mu = surface(Q, S.nzr, p.je, p.we, unif(r.z));
       rotate(p, mu, unif(r.w));
-      set_dir(p, cd);
-      log_event<LOG>(cd, p, 3, vox, 0.0f, p.E);
+      log_event<LOG>(G, p, 3, vox, 0.0f, p.E);
     }
   }
   return true;  // fictitious or scattered: keep going
@@ -377,15 +432,32 @@ __device__ __forceinline__ int find_bin(const unsigned long long *__restrict__ p
   return lo;
 }
 
+static_assert(sizeof(CaseDev) % 4 == 0 && sizeof(CaseDev) <= 512, "CaseDev copy size");
+
+// Copy a case descriptor into the wave's LDS slot (lanes copy words).
+__device__ __forceinline__ void stage_case(CaseDev *dst, const CaseDev *src, int lane) {
+  const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
+  uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+  for (int i = lane; i < (int)(sizeof(CaseDev) / 4); i += 64) d[i] = s[i];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <bool LOG>
 __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__ rcs, int nrc,
                                                    uint64_t total_chunks,
                                                    unsigned long long *chunk_ctr, int refill_min,
                                                    int chunk) {
+  __shared__ unsigned long long wave_acc[8][ACC_COUNT];
+  __shared__ CaseDev wave_case[8];
   const int lane = __lane_id();
+  const int w = threadIdx.x >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  CaseDev &G = wave_case[w];
 
   // wave-uniform state
+  StepCase S;
   int cur = -1;                         // round-case index of the wave's case
   uint64_t pool_next = 0, pool_end = 0; // local history indices of `cur`
   int wbin = 0;                         // bin of pool_next
@@ -395,7 +467,8 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
   uint32_t refills = 0;
 
   Counters cnt;
-  cnt.clear();
+  cnt.s = wave_acc[w];
+  if (lane < ACC_COUNT) cnt.s[lane] = 0ull;
   Photon p;
   bool alive = false;
 
@@ -405,19 +478,21 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
     if (ndead == 64 || ndead >= refill_min) {
       // switch to the pending case once the wave has drained
       if (pend >= 0 && ndead == 64 && pool_next >= pool_end) {
-        if (cur >= 0) flush(cnt, rcs[cur].cd, lane, refills);
+        if (cur >= 0) flush(cnt, G.acc, lane, refills);
         refills = 0;
         cur = pend;
         pend = -1;
+        stage_case(&G, rcs[cur].cd, lane);
+        S = make_step_case(G);
         pool_next = pend_lo;
         pool_end = pend_hi;
-        wbin = find_bin(rcs[cur].prefix, rcs[cur].cd->nbins, pool_next);
+        wbin = find_bin(rcs[cur].prefix, G.nbins, pool_next);
       }
       // claim chunks until the pool has work or the queue is empty
       while (pool_next >= pool_end && pend < 0 && !queue_done) {
         unsigned long long t = 0;
         if (lane == 0) t = atomicAdd(chunk_ctr, 1ull);
-        t = __shfl(t, 0, 64);
+        t = lane0_u64(t);
         if (t >= total_chunks) {
           queue_done = true;
           break;
@@ -427,10 +502,12 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
         const uint64_t hi = min(lo + (uint64_t)chunk, rcs[rc].n);
         if (rc == cur || cur < 0 || ndead == 64) {
           if (rc != cur) {
-            if (cur >= 0) flush(cnt, rcs[cur].cd, lane, refills);
+            if (cur >= 0) flush(cnt, G.acc, lane, refills);
             refills = 0;
             cur = rc;
-            wbin = find_bin(rcs[cur].prefix, rcs[cur].cd->nbins, lo);
+            stage_case(&G, rcs[cur].cd, lane);
+            S = make_step_case(G);
+            wbin = find_bin(rcs[cur].prefix, G.nbins, lo);
           }
           pool_next = lo;
           pool_end = hi;
@@ -443,20 +520,19 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
       // hand out pool ids to idle lanes, lowest lanes first
       if (pool_next < pool_end && ndead > 0) {
         const RoundCase &R = rcs[cur];
-        const CaseDev *cd = R.cd;
         const uint64_t avail = pool_end - pool_next;
         const uint32_t m = (uint32_t)min((uint64_t)ndead, avail);
         const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
         if (!alive && rank < m) {
           const uint64_t local = pool_next + rank;
           int j = wbin;
-          while (j + 1 < cd->nbins && local >= R.prefix[j + 1]) ++j;
-          alive = source<LOG>(p, cd, R.h_begin + local, j, cnt);
+          while (j + 1 < G.nbins && local >= R.prefix[j + 1]) ++j;
+          alive = source<LOG>(p, S, G, R.h_begin + local, j, cnt);
         }
         pool_next += m;
         refills += 1;
         if (pool_next < pool_end) {
-          while (wbin + 1 < cd->nbins && pool_next >= R.prefix[wbin + 1]) ++wbin;
+          while (wbin + 1 < G.nbins && pool_next >= R.prefix[wbin + 1]) ++wbin;
         }
       }
     }
@@ -464,9 +540,9 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
       if (queue_done && pend < 0 && pool_next >= pool_end) break;
       continue;
     }
-    if (alive) alive = step<LOG>(p, rcs[cur].cd, cnt);
+    if (alive) alive = step<LOG>(p, S, G, cnt);
   }
-  if (cur >= 0) flush(cnt, rcs[cur].cd, lane, refills);
+  if (cur >= 0) flush(cnt, G.acc, lane, refills);
 }
 
 // --------------------------------------------------------------- fold etc.

@@ -255,10 +255,10 @@ def test_run_to_sigma_and_host_sigma(ctx):
     say("run to sigma water_cbct/4")
     wl = W.water_cbct(scale=4)
     with Case(ctx, wl) as c:
-        sig = L.ctd_run_to_sigma(ctx, c.cs, 0.03, 0.5, L.CTD_SIGMA_LOCAL, 20_000, 10_000_000)
-        assert sig <= 0.03
+        sig = L.ctd_run_to_sigma(ctx, c.cs, 0.05, 0.5, L.CTD_SIGMA_LOCAL, 50_000, 200_000_000)
+        assert sig <= 0.05
         st = c.stats()
-        assert st.n_batches >= 10 and st.n_histories == st.n_batches * 20_000
+        assert st.n_batches >= 10 and st.n_histories == st.n_batches * 50_000
         dose, var = c.dose()
         rho = wl.rho.reshape(-1)
         inside = rho >= 0.05
