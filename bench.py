@@ -59,7 +59,9 @@ def load_traffic(workload: str, launch_histories: int):
     return per_hist * launch_histories
 
 
-def cpu_baseline(wl, n_hist: int):
+def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
+    """The FP64 CPU oracle on the host's cores; with n_hist None a 1e6-history
+    pilot sizes the sample to about target_s seconds."""
     from oracle import oracle as O
     try:
         cores = len(os.sched_getaffinity(0))
@@ -67,9 +69,16 @@ def cpu_baseline(wl, n_hist: int):
         cores = os.cpu_count() or 1
     threads = max(1, min(cores, 16))
     c = O.OracleCase(wl)
-    t0 = time.perf_counter()
-    r = O.run(c, n_histories=n_hist, n_batches=10, threads=threads)
-    dt = time.perf_counter() - t0
+    adaptive = n_hist is None
+    if adaptive:  # pilot; its per-batch merge makes it underestimate the rate
+        n_hist = 2_000_000
+    for _ in range(3):
+        t0 = time.perf_counter()
+        r = O.run(c, n_histories=n_hist, n_batches=10, threads=threads)
+        dt = time.perf_counter() - t0
+        if not adaptive or dt >= 0.5 * target_s:
+            break
+        n_hist = int(min(n_hist * target_s / dt, 4e8)) // 10 * 10
     return dict(value=r["n_hist"] / dt, unit="histories/s", cores=threads, kind="oracle",
                 sample=f"{n_hist:.0e} histories of the same workload, 10 batches, "
                        f"FP64 CPU oracle, {threads} threads, {dt:.1f} s"), r
@@ -129,7 +138,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="main leg only")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--cpu-histories", type=int, default=6_000_000)
+    ap.add_argument("--cpu-histories", type=int, default=None)
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
@@ -150,7 +159,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream(dev)
+    # a dedicated stream (default priority): the library enqueues on it and
+    # the timing events below are recorded on it
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
     ctx = L.ctd_create(0)
     L.ctd_set_stream(ctx, stream.cuda_stream)
     log("building water_cbct workload")
@@ -160,7 +172,7 @@ def main():
     if not args.no_tune:
         tuning = L.ctd_autotune(ctx, case.cs, 20_000_000)
     log(f"tuning block={tuning.block} waves/simd={tuning.waves_per_simd} "
-        f"refill_min={tuning.refill_min} chunk={tuning.chunk}")
+        f"refill_min={tuning.refill_min} chunk={tuning.chunk} tally_mode={tuning.tally_mode}")
 
     L.ctd_run_batches(ctx, case.cs, BATCH, args.warmup)
     torch.cuda.synchronize()
@@ -176,6 +188,7 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     gpu_ms = ev0.elapsed_time(ev1)
+    assert gpu_ms > 0.5 * wall * 1e3, "timing events do not bracket the library's work"
     st1 = L.ctd_read_stats(ctx, case.cs)
     bal = L.ctd_read_balance(ctx, case.cs)
     assert bal.q_incident == bal.q_deposited + bal.q_escaped, "energy balance broken"
@@ -192,11 +205,25 @@ def main():
     launch_ms = (st1.transport_ms - st0.transport_ms) / args.steps
     achieved = ops / args.steps / (launch_ms * 1e-3)
     traffic = load_traffic("water_cbct", BATCH)
+    d_dep = st1.n_deposits - st0.n_deposits
+    # algorithmic bytes: 5 B voxel record per Woodcock step + 8 B per tally update
+    alg_bytes = 5.0 * d_steps + 8.0 * d_dep
+    atom_rate = d_dep / args.steps / (launch_ms * 1e-3)
+    atom_peak, _ = L.ctd_microbench(ctx, 1, wl.n_voxels * 8, 1 << 28)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_LANE_OPS / 1e12,
                 unit="T lane-ops/s", frac=achieved / PEAK_LANE_OPS, traffic=traffic,
                 kernel="k_transport", launch_ms=launch_ms,
                 ops_per_history=ops / n_timed,
-                steps_per_history=d_steps / n_timed)
+                steps_per_history=d_steps / n_timed,
+                deposits_per_history=d_dep / n_timed,
+                hbm=dict(achieved=alg_bytes / args.steps / (launch_ms * 1e-3) / 1e9,
+                         peak=8000.0, unit="GB/s",
+                         frac=alg_bytes / args.steps / (launch_ms * 1e-3) / 8e12,
+                         bytes_per_history=alg_bytes / n_timed),
+                atomic=dict(achieved=atom_rate, peak=atom_peak, unit="int64 atomics/s",
+                            frac=atom_rate / atom_peak,
+                            peak_source="ctd_microbench random 64-bit atomics into a "
+                                        "tally-sized array, measured in this run"))
     out = dict(metric=METRIC, value=value, unit="histories/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=wall * 1e3 / args.steps, higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
@@ -204,7 +231,8 @@ def main():
                            histories_per_step=BATCH, histories_total=(args.steps + args.warmup)
                            * BATCH, voxels=wl.n_voxels, tally="int64 fixed point 2^-24 keV",
                            tuning=dict(block=tuning.block, waves_per_simd=tuning.waves_per_simd,
-                                       refill_min=tuning.refill_min, chunk=tuning.chunk)),
+                                       refill_min=tuning.refill_min, chunk=tuning.chunk,
+                                       tally_mode=tuning.tally_mode)),
                roofline=roof,
                transport_only_histories_per_s=n_timed / ((st1.transport_ms - st0.transport_ms)
                                                          * 1e-3),

@@ -104,8 +104,10 @@ typedef struct {
   double sigma_rho_min;  /* voxels with rho >= this count as "inside" for sigma-bar */
 } ctd_params;
 
+/* Energy balance in units of q = 2^-24 keV as exact 128-bit sums (hi:lo). */
 typedef struct {
-  int64_t q_incident, q_deposited, q_escaped; /* units of 2^-24 keV */
+  uint64_t q_incident, q_deposited, q_escaped;          /* low 64 bits */
+  uint64_t q_incident_hi, q_deposited_hi, q_escaped_hi; /* high 64 bits */
   uint64_t n_histories, n_missed, n_unscattered, n_cutoff;
 } ctd_balance;
 
@@ -126,7 +128,11 @@ typedef struct {
   int32_t block;         /* threads per workgroup: 64, 128, 256, 512 */
   int32_t waves_per_simd;/* resident waves per SIMD to size the grid (1..8) */
   int32_t refill_min;    /* refill a wave when >= this many lanes idle (1..64) */
-  int32_t chunk;         /* histories a wave claims per counter atomic (64..4096) */
+  int32_t chunk;         /* histories a wave claims per counter atomic (64..65536) */
+  int32_t tally_mode;    /* 0: one batch tally, device-scope atomics;
+                            1: one batch tally per XCD, updated with L2-resident
+                            atomics by the waves of that XCD and summed by the
+                            fold (only where every XCD id is < 8) */
 } ctd_tuning;
 
 /* Deposit/event record of the debug log (test use). type: 0 source, 1
@@ -216,7 +222,9 @@ int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histories, ctd_t
 /* Run n_histories as n_batches equal batches (the first n mod n_batches
  * one larger), continuing the case's history ids.  Each batch: transport
  * launch, then fold S1 += T_b, S2 += T_b^2, T_b = 0 (Sec. 2.2.1).  Async.
- * CTD_EOVERFLOW if the case's cumulative histories * E_max * 2^24 >= 2^63. */
+ * CTD_EOVERFLOW if a batch could exceed 2^62 q in one voxel (histories *
+ * E_max * 2^24 >= 2^62), or if a voxel's S1 could pass 2^63 or its S2 2^128
+ * (checked against the exact per-voxel maxima the folds record). */
 int32_t ctd_run(ctd_ctx *ctx, ctd_case *cs, uint64_t n_histories);
 
 /* Run `count` batches of exactly batch_histories each (same per-batch work
@@ -261,6 +269,16 @@ int32_t ctd_read_balance(ctd_ctx *ctx, ctd_case *cs, ctd_balance *out);
 int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out);
 /* Copy the case's majorant nodes mu_max[ne] (float, cm^-1). */
 int32_t ctd_read_majorant(ctd_ctx *ctx, ctd_case *cs, float *out);
+
+/* ---------------- microbenchmarks ----------------
+ * Device peaks for roofline reporting, timed with HIP events on the ctx
+ * stream (synchronous).  kind: 0 streaming copy of `bytes` (result: GB/s of
+ * read + write), 1 random 64-bit atomic adds without return into a `bytes`
+ * array (ops/s), 2 the same into 64 hot words (ops/s), 3 random 8-byte
+ * gathers from a `bytes` array (ops/s).  `ops` is ignored for kind 0.
+ * *rate receives the measured rate, *ms the kernel time. */
+int32_t ctd_microbench(ctd_ctx *ctx, int32_t kind, uint64_t bytes, uint64_t ops, double *rate,
+                       double *ms);
 
 /* ---------------- debug log (tests) ----------------
  * Arm event logging of histories [h0, h0+nh) for the following runs, with

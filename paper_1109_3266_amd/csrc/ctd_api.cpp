@@ -83,6 +83,17 @@ extern "C" int32_t ctd_create(ctd_ctx **out, int32_t device) {
     ctd_destroy(ctx);
     return CTD_ENOMEM;
   }
+  // per-XCD tallies need every XCC id to index one of kTallyCopies copies
+  unsigned int *probe = nullptr;
+  unsigned int mx = ~0u;
+  if (hipMalloc(&probe, 4) == hipSuccess && hipMemsetAsync(probe, 0, 4, ctx->stream) == hipSuccess &&
+      launch_xcc_probe(probe, 16 * ctx->n_cu, ctx->stream) == 0 &&
+      hipMemcpyAsync(&mx, probe, 4, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess &&
+      hipStreamSynchronize(ctx->stream) == hipSuccess) {
+    ctx->max_xcc = mx;
+    ctx->xcd_tally_ok = mx < (unsigned)kTallyCopies;
+  }
+  dfree(probe);
   *out = ctx;
   return CTD_OK;
 }
@@ -115,6 +126,51 @@ extern "C" int32_t ctd_set_stream(ctd_ctx *ctx, void *hip_stream) {
 }
 
 // --------------------------------------------------------------- phantom
+
+// Piecewise-constant phantoms (at most 256 distinct (rho, material) records)
+// also get a 1-byte-per-voxel index into a 256-entry table: an 8x smaller
+// gather footprint for the same numbers.  Scanned in slices so a phantom
+// with many distinct densities is rejected after a few thousand voxels.
+static int build_palette(ctd_ctx *ctx, ctd_phantom *ph) {
+  const int64_t V = ph->V;
+  const int64_t slice = (int64_t)1 << 20;
+  std::vector<uint2> rec((size_t)std::min<int64_t>(V, slice));
+  std::vector<uint8_t> idx((size_t)V);
+  uint64_t keys[256];
+  int n = 0;
+  for (int64_t b = 0; b < V; b += slice) {
+    const int64_t m = std::min<int64_t>(slice, V - b);
+    HIPCHK(ctx, hipMemcpy(rec.data(), ph->vox + b, sizeof(uint2) * m, hipMemcpyDeviceToHost));
+    uint64_t last = ~0ull;
+    int last_i = -1;
+    for (int64_t i = 0; i < m; ++i) {
+      const uint64_t key = ((uint64_t)rec[i].y << 32) | rec[i].x;
+      int k = -1;
+      if (key == last) {
+        k = last_i;
+      } else {
+        for (int j = 0; j < n; ++j)
+          if (keys[j] == key) { k = j; break; }
+        if (k < 0) {
+          if (n == 256) return CTD_OK;  // too many distinct records: keep 8-byte layout
+          keys[n] = key;
+          k = n++;
+        }
+        last = key;
+        last_i = k;
+      }
+      idx[(size_t)(b + i)] = (uint8_t)k;
+    }
+  }
+  std::vector<uint2> pal(256, make_uint2(0u, 0u));
+  for (int j = 0; j < n; ++j) pal[j] = make_uint2((uint32_t)keys[j], (uint32_t)(keys[j] >> 32));
+  HIPCHK(ctx, hipMalloc(&ph->vox8, (size_t)V));
+  HIPCHK(ctx, hipMalloc(&ph->palette, sizeof(uint2) * 256));
+  HIPCHK(ctx, hipMemcpy(ph->vox8, idx.data(), (size_t)V, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(ph->palette, pal.data(), sizeof(uint2) * 256, hipMemcpyHostToDevice));
+  ph->npal = n;
+  return CTD_OK;
+}
 
 extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8_t *mat,
                                     const float *rho, int32_t mem, ctd_phantom **out) {
@@ -185,6 +241,8 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
   dmat = nullptr;
   drho = nullptr;
   dfree(dstat);
+  dstat = nullptr;
+  if ((rc = build_palette(ctx, ph)) != CTD_OK) return fail(rc);
   *out = ph;
   return CTD_OK;
 }
@@ -194,6 +252,8 @@ extern "C" int32_t ctd_phantom_release(ctd_ctx *ctx, ctd_phantom *ph) {
   if (ph->refs > 0) return set_err(ctx, CTD_EBUSY, "phantom is used by %d case(s)", ph->refs);
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  dfree(ph->vox8);
+  dfree(ph->palette);
   dfree(ph->vox);
   delete ph;
   return CTD_OK;
@@ -405,7 +465,7 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
   cs->geo = geo;
   cs->p = *p;
   cs->e_max = emax;
-  cs->tune = default_tuning();
+  cs->tune = default_tuning(ctx);
   // majorant from per-material maximum density (Sec. 2.1)
   std::vector<double> rmax((size_t)ms->M, 0.0);
   bool pres[256];
@@ -431,10 +491,10 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
   };
   hipError_t e;
   std::vector<float> blo(sp->lo.begin(), sp->lo.end());
-  if ((e = hipMalloc(&cs->d_tally, 8 * V)) != hipSuccess ||
+  if ((e = hipMalloc(&cs->d_tally, 8 * V * kTallyCopies)) != hipSuccess ||
       (e = hipMalloc(&cs->d_s1, 8 * V)) != hipSuccess ||
       (e = hipMalloc(&cs->d_s2, 16 * V)) != hipSuccess ||
-      (e = hipMalloc(&cs->d_acc, 8 * ACC_COUNT)) != hipSuccess ||
+      (e = hipMalloc(&cs->d_acc, 8 * kAccWords)) != hipSuccess ||
       (e = hipMalloc(&cs->d_desc, sizeof(CaseDev))) != hipSuccess ||
       (e = hipMalloc(&cs->d_mu_max, 4 * eg.ne)) != hipSuccess ||
       (e = hipMalloc(&cs->d_bin_lo, 4 * blo.size())) != hipSuccess)
@@ -450,9 +510,9 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
                                     sizeof(float2) * geo->proj_sc.size(),
                                     hipMemcpyHostToDevice)) != hipSuccess))
     return cleanup(hip_err(ctx, e, "case upload"));
-  if (launch_zero(cs->d_tally, 8 * V, ctx->stream) || launch_zero(cs->d_s1, 8 * V, ctx->stream) ||
-      launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
-      launch_zero(cs->d_acc, 8 * ACC_COUNT, ctx->stream))
+  if (launch_zero(cs->d_tally, 8 * V * kTallyCopies, ctx->stream) ||
+      launch_zero(cs->d_s1, 8 * V, ctx->stream) || launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
+      launch_zero(cs->d_acc, 8 * kAccWords, ctx->stream))
     return cleanup(hip_err(ctx, hipGetLastError(), "case clear"));
   fill_desc(cs);
   if ((rc = upload_desc(ctx, cs)) != CTD_OK) return cleanup(rc);
@@ -483,6 +543,9 @@ void ctd::fill_desc(ctd_case *cs) {
   d.oz = (float)g.origin[2];
   d.vox = cs->ph->vox;
   d.V = cs->ph->V;
+  d.vox8 = cs->ph->vox8;
+  d.palette = cs->ph->palette;
+  d.npal = cs->ph->npal;
   const ctd_matset *ms = cs->ms;
   d.ne = ms->eg.ne;
   d.nzc = ms->nzc;
@@ -568,14 +631,15 @@ extern "C" int32_t ctd_case_reset(ctd_ctx *ctx, ctd_case *cs) {
   if (!ctx || !cs) return CTD_EINVAL;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   const int64_t V = cs->ph->V;
-  if (launch_zero(cs->d_tally, 8 * V, ctx->stream) || launch_zero(cs->d_s1, 8 * V, ctx->stream) ||
-      launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
-      launch_zero(cs->d_acc, 8 * ACC_COUNT, ctx->stream))
+  if (launch_zero(cs->d_tally, 8 * V * kTallyCopies, ctx->stream) ||
+      launch_zero(cs->d_s1, 8 * V, ctx->stream) || launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
+      launch_zero(cs->d_acc, 8 * kAccWords, ctx->stream))
     return hip_err(ctx, hipGetLastError(), "case reset");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   cs->h_next = 0;
   cs->batches = 0;
   cs->batch_sizes.clear();
+  cs->s1_bound = cs->s2_bound = 0.0;
   cs->sigma_local = cs->sigma_paper = NAN;
   for (auto &t : cs->timing) {
     (void)hipEventDestroy(t.a);
@@ -587,24 +651,29 @@ extern "C" int32_t ctd_case_reset(ctd_ctx *ctx, ctd_case *cs) {
   return CTD_OK;
 }
 
-ctd_tuning ctd::default_tuning() {
+ctd_tuning ctd::default_tuning(const ctd_ctx *ctx) {
   ctd_tuning t;
   t.block = 256;
   t.waves_per_simd = 4;
   t.refill_min = 16;
-  t.chunk = 256;
+  t.chunk = 1024;
+  t.tally_mode = 0;  // per-XCD copies measured no faster on MI355X; 8x the fold traffic
+  (void)ctx;
   return t;
 }
 
 static bool tuning_ok(const ctd_tuning &t) {
   return (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
          t.waves_per_simd >= 1 && t.waves_per_simd <= 8 && t.refill_min >= 1 &&
-         t.refill_min <= 64 && t.chunk >= 64 && t.chunk <= 65536;
+         t.refill_min <= 64 && t.chunk >= 64 && t.chunk <= 65536 &&
+         (t.tally_mode == 0 || t.tally_mode == 1);
 }
 
 extern "C" int32_t ctd_set_tuning(ctd_ctx *ctx, ctd_case *cs, const ctd_tuning *t) {
   if (!ctx || !cs || !t) return CTD_EINVAL;
   NEED(ctx, tuning_ok(*t), "tuning out of range");
+  NEED(ctx, t->tally_mode == 0 || ctx->xcd_tally_ok,
+       "per-XCD tallies unavailable: XCC id %u >= %d", ctx->max_xcc, kTallyCopies);
   cs->tune = *t;
   return CTD_OK;
 }
@@ -668,6 +737,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
   cfg.grid = std::max(1, ctx->n_cu * 4 * t.waves_per_simd / waves_per_wg);
   cfg.refill_min = t.refill_min;
   cfg.chunk = t.chunk;
+  cfg.tally_mode = t.tally_mode;
   if (chunks > 0 &&
       launch_transport((const RoundCase *)d, nrc, chunks, (unsigned long long *)(d + ctr_off),
                        cfg, with_log, ctx->stream) != 0)
@@ -688,12 +758,27 @@ int ctd::batch_prefix(ctd_ctx *ctx, const ctd_case *cs, uint64_t n,
   return CTD_OK;
 }
 
-static int check_headroom(ctd_ctx *ctx, const ctd_case *cs, uint64_t more) {
-  const double total = (double)cs->h_next + (double)more;
-  if (total * cs->e_max * 16777216.0 >= 9.2e18)
-    return set_err(ctx, CTD_EOVERFLOW,
-                   "%.3g histories at %.4g keV exceed the int64 fixed-point range", total,
-                   cs->e_max);
+// Fixed-point headroom before a batch of n histories.  A batch deposits at
+// most n * E_max * 2^24 q in any voxel.  The host keeps pessimistic bounds on
+// the largest S1 and S2 of any voxel and, when they get close to the int64 /
+// 128-bit limits, replaces them by the exact maxima the folds recorded.
+static int check_headroom(ctd_ctx *ctx, ctd_case *cs, uint64_t n) {
+  const double bmax = (double)n * cs->e_max * 16777216.0;
+  if (bmax >= 0x1p62)
+    return set_err(ctx, CTD_EOVERFLOW, "a batch of %.3g histories at %.4g keV exceeds 2^62 q",
+                   (double)n, cs->e_max);
+  double s1 = cs->s1_bound + bmax, s2 = cs->s2_bound + bmax * bmax;
+  if (s1 >= 0x1p62 || s2 >= 0x1p126) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    unsigned long long m[2];
+    HIPCHK(ctx, hipMemcpy(m, cs->d_acc + kAccMaxS1, sizeof m, hipMemcpyDeviceToHost));
+    s1 = (double)m[0] + bmax;
+    s2 = ((double)m[1] + 1.0) * 0x1p64 + bmax * bmax;
+    if (s1 >= 0x1p63 || s2 >= 0x1p128)
+      return set_err(ctx, CTD_EOVERFLOW, "a voxel's fixed-point sums would overflow");
+  }
+  cs->s1_bound = s1;
+  cs->s2_bound = s2;
   return CTD_OK;
 }
 
@@ -705,6 +790,8 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
   bool with_log = false;
   for (size_t i = 0; i < cases.size(); ++i) {
     if (n[i] == 0) continue;
+    int rc0 = check_headroom(ctx, cases[i], n[i]);
+    if (rc0 != CTD_OK) return rc0;
     RoundItem it;
     it.cd = cases[i]->d_desc;
     it.h_begin = cases[i]->h_next;
@@ -730,7 +817,8 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
   for (size_t i = 0; i < cases.size(); ++i) {
     if (n[i] == 0) continue;
     ctd_case *cs = cases[i];
-    if (launch_fold(cs->d_tally, cs->d_s1, cs->d_s2, cs->ph->V, ctx->stream) != 0)
+    if (launch_fold(cs->d_tally, t.tally_mode ? kTallyCopies : 1, cs->d_s1, cs->d_s2, cs->ph->V,
+                    cs->d_acc, ctx->stream) != 0)
       return hip_err(ctx, hipGetLastError(), "fold launch");
     cs->h_next += n[i];
     cs->batches += 1;
@@ -752,11 +840,10 @@ std::vector<uint64_t> ctd::split_batches(uint64_t n, int nb) {
 extern "C" int32_t ctd_run(ctd_ctx *ctx, ctd_case *cs, uint64_t n_histories) {
   if (!ctx || !cs) return CTD_EINVAL;
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  int rc = check_headroom(ctx, cs, n_histories);
-  if (rc != CTD_OK) return rc;
   if (n_histories == 0) return CTD_OK;
   const auto sizes = split_batches(n_histories, cs->p.n_batches);
   std::vector<ctd_case *> one{cs};
+  int rc = CTD_OK;
   for (uint64_t nb : sizes) {
     if (nb == 0) continue;
     rc = run_round(ctx, one, std::vector<uint64_t>{nb}, cs->tune);
@@ -774,8 +861,6 @@ extern "C" int32_t ctd_run_many(ctd_ctx *ctx, ctd_case *const *cs, const uint64_
   for (int i = 0; i < count; ++i) {
     NEED(ctx, cs[i], "null case %d", i);
     for (int j = 0; j < i; ++j) NEED(ctx, cs[j] != cs[i], "case %d listed twice", i);
-    int rc = check_headroom(ctx, cs[i], n[i]);
-    if (rc != CTD_OK) return rc;
     if (n[i]) sizes[i] = split_batches(n[i], cs[i]->p.n_batches);
     rounds = std::max(rounds, sizes[i].size());
   }
@@ -823,8 +908,7 @@ extern "C" int32_t ctd_sigma(ctd_ctx *ctx, ctd_case *cs, int32_t sigma_kind, dou
 }
 
 int ctd::run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count) {
-  int rc = check_headroom(ctx, cs, batch * count);
-  if (rc != CTD_OK) return rc;
+  int rc = CTD_OK;
   std::vector<ctd_case *> one{cs};
   for (uint64_t b = 0; b < count; ++b) {
     rc = run_round(ctx, one, std::vector<uint64_t>{batch}, cs->tune);
@@ -957,12 +1041,17 @@ extern "C" int32_t ctd_read_dose(ctd_ctx *ctx, ctd_case *cs, double *dose, doubl
 extern "C" int32_t ctd_read_balance(ctd_ctx *ctx, ctd_case *cs, ctd_balance *out) {
   if (!ctx || !cs || !out) return CTD_EINVAL;
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  uint64_t a[ACC_COUNT];
+  uint64_t w[kAccWords];
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  HIPCHK(ctx, hipMemcpy(a, cs->d_acc, sizeof a, hipMemcpyDeviceToHost));
-  out->q_incident = (int64_t)a[ACC_Q_INC];
-  out->q_deposited = (int64_t)a[ACC_Q_DEP];
-  out->q_escaped = (int64_t)a[ACC_Q_ESC];
+  HIPCHK(ctx, hipMemcpy(w, cs->d_acc, sizeof w, hipMemcpyDeviceToHost));
+  uint64_t a[ACC_COUNT];
+  for (int i = 0; i < ACC_COUNT; ++i) a[i] = w[kAccTotal + 2 * i];
+  out->q_incident = a[ACC_Q_INC];
+  out->q_deposited = a[ACC_Q_DEP];
+  out->q_escaped = a[ACC_Q_ESC];
+  out->q_incident_hi = w[kAccTotal + 2 * ACC_Q_INC + 1];
+  out->q_deposited_hi = w[kAccTotal + 2 * ACC_Q_DEP + 1];
+  out->q_escaped_hi = w[kAccTotal + 2 * ACC_Q_ESC + 1];
   out->n_histories = a[ACC_N_HIST];
   out->n_missed = a[ACC_N_MISS];
   out->n_unscattered = a[ACC_N_UNSCATTERED];
@@ -977,8 +1066,10 @@ extern "C" int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out) {
   if (!ctx || !cs || !out) return CTD_EINVAL;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  uint64_t w[kAccWords];
+  HIPCHK(ctx, hipMemcpy(w, cs->d_acc, sizeof w, hipMemcpyDeviceToHost));
   uint64_t a[ACC_COUNT];
-  HIPCHK(ctx, hipMemcpy(a, cs->d_acc, sizeof a, hipMemcpyDeviceToHost));
+  for (int i = 0; i < ACC_COUNT; ++i) a[i] = w[kAccTotal + 2 * i];
   for (auto &t : cs->timing) {
     float ms1 = 0.f, ms2 = 0.f;
     if (hipEventElapsedTime(&ms1, t.a, t.b) == hipSuccess) cs->transport_ms += ms1;
@@ -1085,18 +1176,19 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
     dfree(tw.d_desc);
   };
   hipError_t e;
-  if ((e = hipMalloc(&tw.d_tally, 8 * V)) != hipSuccess ||
+  if ((e = hipMalloc(&tw.d_tally, 8 * V * kTallyCopies)) != hipSuccess ||
       (e = hipMalloc(&tw.d_s1, 8 * V)) != hipSuccess ||
       (e = hipMalloc(&tw.d_s2, 16 * V)) != hipSuccess ||
-      (e = hipMalloc(&tw.d_acc, 8 * ACC_COUNT)) != hipSuccess ||
+      (e = hipMalloc(&tw.d_acc, 8 * kAccWords)) != hipSuccess ||
       (e = hipMalloc(&tw.d_desc, sizeof(CaseDev))) != hipSuccess) {
     release();
     return hip_err(ctx, e, "autotune alloc");
   }
-  launch_zero(tw.d_tally, 8 * V, ctx->stream);
+  launch_zero(tw.d_tally, 8 * V * kTallyCopies, ctx->stream);
   launch_zero(tw.d_s1, 8 * V, ctx->stream);
   launch_zero(tw.d_s2, 16 * V, ctx->stream);
-  launch_zero(tw.d_acc, 8 * ACC_COUNT, ctx->stream);
+  launch_zero(tw.d_acc, 8 * kAccWords, ctx->stream);
+  tw.s1_bound = tw.s2_bound = 0.0;
   fill_desc(&tw);
   int rc = upload_desc(ctx, &tw);
   if (rc != CTD_OK) {
@@ -1104,16 +1196,18 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
     return rc;
   }
   std::vector<ctd_tuning> cand;
-  for (int wps : {2, 4, 8})
-    for (int rm : {8, 16, 32})
-      for (int ch : {256, 1024}) {
-        ctd_tuning t;
-        t.block = 256;
-        t.waves_per_simd = wps;
-        t.refill_min = rm;
-        t.chunk = ch;
-        cand.push_back(t);
-      }
+  for (int tm = ctx->xcd_tally_ok ? 1 : 0; tm >= 0; --tm)
+    for (int wps : {2, 4, 8})
+      for (int rm : {8, 16, 32})
+        for (int ch : {256, 1024}) {
+          ctd_tuning t;
+          t.block = 256;
+          t.waves_per_simd = wps;
+          t.refill_min = rm;
+          t.chunk = ch;
+          t.tally_mode = tm;
+          cand.push_back(t);
+        }
   hipEvent_t a, b;
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
@@ -1146,5 +1240,51 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
   if (rc != CTD_OK) return rc;
   cs->tune = best_t;
   if (best) *best = best_t;
+  return CTD_OK;
+}
+
+// -------------------------------------------------------- microbenchmarks
+
+extern "C" int32_t ctd_microbench(ctd_ctx *ctx, int32_t kind, uint64_t bytes, uint64_t ops,
+                                  double *rate, double *ms) {
+  if (!ctx || !rate) return CTD_EINVAL;
+  NEED(ctx, kind >= 0 && kind <= 3, "kind must be 0..3");
+  NEED(ctx, bytes >= 4096 && bytes <= ((uint64_t)1 << 36) && bytes % 16 == 0,
+       "bytes must be a multiple of 16 in [4 KiB, 64 GiB]");
+  NEED(ctx, kind == 0 || (ops > 0 && bytes / 8 <= 0xFFFFFFFFull), "bad ops or size");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  void *a = nullptr, *b = nullptr;
+  HIPCHK(ctx, hipMalloc(&a, bytes));
+  hipError_t e = hipMalloc(&b, kind == 0 ? bytes : 256);
+  if (e != hipSuccess) {
+    dfree(a);
+    return hip_err(ctx, e, "microbench alloc");
+  }
+  launch_zero(a, bytes, ctx->stream);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int grid = ctx->n_cu * 8;
+  int rc = CTD_OK;
+  float best = INFINITY;
+  for (int rep = 0; rep < 4 && rc == CTD_OK; ++rep) {  // first pass warms up
+    (void)hipEventRecord(e0, ctx->stream);
+    if (launch_microbench(kind, a, b, (int64_t)bytes, (int64_t)ops, grid, ctx->stream) != 0)
+      rc = hip_err(ctx, hipGetLastError(), "microbench launch");
+    (void)hipEventRecord(e1, ctx->stream);
+    (void)hipEventSynchronize(e1);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    if (rep > 0) best = std::min(best, t);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(ctx->stream);
+  dfree(a);
+  dfree(b);
+  if (rc != CTD_OK) return rc;
+  const double sec = (double)best * 1e-3;
+  *rate = kind == 0 ? 2.0 * (double)bytes / sec / 1e9 : (double)ops / sec;
+  if (ms) *ms = best;
   return CTD_OK;
 }

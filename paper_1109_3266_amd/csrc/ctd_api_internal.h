@@ -38,6 +38,8 @@ struct ctd_ctx {
   size_t next_slot = 0;
   double *sigma_scratch = nullptr;
   double *sigma_host = nullptr;
+  bool xcd_tally_ok = false;  // every XCC id < kTallyCopies
+  unsigned int max_xcc = 0;
 };
 
 struct ctd_phantom {
@@ -45,6 +47,9 @@ struct ctd_phantom {
   ctd_grid g{};
   int64_t V = 0;
   uint2 *vox = nullptr;   // packed (rho bits, material) records
+  uint8_t *vox8 = nullptr;  // palette indices when npal > 0
+  uint2 *palette = nullptr; // [256] distinct records when npal > 0
+  int npal = 0;
   double rho_max[256] = {};
   bool present[256] = {};
   int max_mat = 0;
@@ -104,6 +109,7 @@ struct ctd_case {
   std::vector<Timing> timing;
   double transport_ms = 0.0, fold_ms = 0.0;
   double sigma_local = NAN, sigma_paper = NAN;
+  double s1_bound = 0.0, s2_bound = 0.0;  // upper bounds on any voxel's S1, S2
   bool in_server = false;
 };
 
@@ -114,9 +120,9 @@ int hip_err(ctd_ctx *ctx, hipError_t e, const char *what);
 int upload_desc(ctd_ctx *ctx, ctd_case *cs);
 void fill_desc(ctd_case *cs);
 void free_case_buffers(ctd_case *cs);
-ctd_tuning default_tuning();
 int submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const ctd_tuning &t,
                  bool with_log);
+ctd_tuning default_tuning(const ctd_ctx *ctx);
 int batch_prefix(ctd_ctx *ctx, const ctd_case *cs, uint64_t n,
                  std::vector<unsigned long long> &prefix);
 int run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vector<uint64_t> &n,

@@ -32,7 +32,17 @@ enum Acc : int {
   ACC_COUNT
 };
 
+// Layout of a case's counter block (uint64 words): [0, ACC_COUNT) counters of
+// the current batch (kernel atomics), [ACC_COUNT, 3 ACC_COUNT) exact 128-bit
+// totals as (lo, hi) pairs, folded after every batch, then the per-voxel
+// maxima seen by the folds: max S1, max high word of S2.
+constexpr int kAccTotal = ACC_COUNT;
+constexpr int kAccMaxS1 = 3 * ACC_COUNT;
+constexpr int kAccMaxS2Hi = 3 * ACC_COUNT + 1;
+constexpr int kAccWords = 3 * ACC_COUNT + 4;
+
 constexpr float kQScale = 16777216.0f;  // 2^24: tally unit q = 2^-24 keV
+constexpr int kTallyCopies = 8;         // one batch tally per XCD of an MI355X
 constexpr uint32_t kStepGuard = 1000000u;
 constexpr float kInvMeC2 = (float)(1.0 / 510.99895);
 
@@ -44,6 +54,11 @@ struct CaseDev {
   float ox, oy, oz, pad2;
   const uint2 *vox;            // [V] (float bits of rho, material id)
   int64_t V;
+  // palette layout (phantoms with <= 256 distinct (rho, material) pairs):
+  // vox8[V] indexes palette[256]; npal = 0 when not used
+  const uint8_t *vox8;
+  const uint2 *palette;
+  int32_t npal, pad9;
   // energy grid and tables
   int32_t ne, nzc, nzr, rayleigh;
   float e0, inv_de, e_cut, pad3;
@@ -65,7 +80,7 @@ struct CaseDev {
   // random stream key
   uint32_t key0, key1;
   // tallies
-  unsigned long long *tally;   // T_b [V]
+  unsigned long long *tally;   // T_b [kTallyCopies][V]
   long long *s1;               // [V]
   unsigned long long *s2;      // [V][2] (lo, hi)
   unsigned long long *acc;     // [ACC_COUNT]
@@ -89,14 +104,20 @@ struct LaunchCfg {
   int grid;
   int refill_min;
   int chunk;
+  int tally_mode;
 };
 
 // Kernel launchers (ctd_kernels.hip).  All enqueue on `stream`.
 int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
                      void *stream);
-int launch_fold(unsigned long long *tally, long long *s1, unsigned long long *s2, int64_t V,
-                void *stream);
+// Fold ncopies batch tallies [ncopies][V]: S1 += sum, S2 += sum^2, zero them;
+// fold the batch counters of acc into its 128-bit totals and record the
+// per-voxel maxima of S1 and of S2's high word.
+int launch_fold(unsigned long long *tally, int ncopies, long long *s1, unsigned long long *s2,
+                int64_t V, unsigned long long *acc, void *stream);
+// Largest XCC id seen by `blocks` workgroups (written to *out, device).
+int launch_xcc_probe(unsigned int *out, int blocks, void *stream);
 // stats[514]: [0,256) max density bits per material, [256,512) presence,
 // [512] largest material id, [513] voxels with a bad density.
 int launch_pack(const uint8_t *mat, const float *rho, uint2 *vox, int64_t V, unsigned int *stats,
@@ -107,6 +128,10 @@ int launch_zero(void *ptr, size_t bytes, void *stream);
 int launch_sigma(const long long *s1, const unsigned long long *s2, const uint2 *vox, int64_t V,
                  uint32_t nb, double rho_min, double frac, int kind, double *scratch,
                  int nblocks, double *out, void *stream);
+// kind 0 copy (n bytes), 1 random atomics / 2 hot-spot atomics (ops on an
+// n-byte uint64 array), 3 random 8-byte gathers (ops over n bytes).
+int launch_microbench(int kind, void *buf_a, void *buf_b, int64_t n, int64_t ops, int grid,
+                      void *stream);
 int device_cu_count(int device);
 
 }  // namespace ctd

@@ -29,8 +29,10 @@ namespace ctd {
 // tag only exists in the device compilation pass).
 #if defined(__HIP_DEVICE_COMPILE__)
 #define GLOBAL __attribute__((address_space(1)))
+#define LOCAL __attribute__((address_space(3)))
 #else
 #define GLOBAL
+#define LOCAL
 #endif
 
 // ---------------------------------------------------------------- helpers
@@ -96,15 +98,23 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
 // is read from the wave's LDS copy of the full descriptor.
 struct StepCase {
   const GLOBAL uint2 *vox;
+  const GLOBAL uint8_t *vox8;
   const GLOBAL float4 *mu_rho;
   const GLOBAL float *mu_max;
   const GLOBAL float4 *comp_quad;
   const GLOBAL float4 *rayl_quad;
   GLOBAL unsigned long long *tally;
   float fnx, fny, fnz, inv_dx, inv_dy, inv_dz, e0, inv_de, e_cut;
-  int32_t nx, ny, ne, nzc, nzr, rayleigh, comp_per_mat;
+  int32_t nx, ny, ne, nzc, nzr, rayleigh, comp_per_mat, npal;
+  int32_t tally_l2;  // 1: this XCD's private tally, atomics performed in its L2
   uint32_t key0, key1;
 };
+
+// Id of the XCD (accelerator complex die) this wave runs on.
+__device__ __forceinline__ uint32_t xcc_id() {
+  // hwreg(HW_REG_XCC_ID, 0, 16): read-only hardware register
+  return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((16 - 1) << 11)) & 0xFu;
+}
 
 template <typename T>
 __device__ __forceinline__ GLOBAL T *uniform_ptr(T *p) {
@@ -120,14 +130,18 @@ __device__ __forceinline__ int32_t uniform_i(int32_t x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
-__device__ __forceinline__ StepCase make_step_case(const CaseDev &c) {
+__device__ __forceinline__ StepCase make_step_case(const CaseDev &c, int tally_mode) {
   StepCase s;
   s.vox = uniform_ptr(c.vox);
+  s.vox8 = uniform_ptr(c.vox8);
+  s.npal = uniform_i(c.npal);
   s.mu_rho = uniform_ptr(c.mu_rho);
   s.mu_max = uniform_ptr(c.mu_max);
   s.comp_quad = uniform_ptr(c.comp_quad);
   s.rayl_quad = uniform_ptr(c.rayl_quad);
   s.tally = uniform_ptr(c.tally);
+  s.tally_l2 = tally_mode;
+  if (tally_mode) s.tally += (size_t)xcc_id() * (size_t)uniform_i((int32_t)c.V);
   s.fnx = uniform_f(c.fnx);
   s.fny = uniform_f(c.fny);
   s.fnz = uniform_f(c.fnz);
@@ -244,14 +258,22 @@ __device__ __forceinline__ void log_event(const CaseDev &G, Photon &p, int type,
   p.seq += 1;
 }
 
+// Exact tally update: e is a multiple of 2^-24 keV, so q = e * 2^24 is an
+// integer (< 2^32 for e < 256 keV) and the int64 sum is exact in any order.
 template <bool LOG>
 __device__ __forceinline__ void deposit(const StepCase &S, const CaseDev &G, Photon &p,
                                         Counters &c, int32_t vox, float e, int type,
                                         float Eafter) {
-  const uint32_t q = (uint32_t)(e * kQScale);  // exact: e is a multiple of 2^-24 keV
+  const uint32_t q = (uint32_t)(e * kQScale);
   if (q) {
-    __hip_atomic_fetch_add(S.tally + vox, (unsigned long long)q, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    // Per-XCD tallies are only touched by waves of one XCD; the single
+    // shared tally needs device scope.
+    if (S.tally_l2)
+      __hip_atomic_fetch_add(S.tally + vox, (unsigned long long)q, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      __hip_atomic_fetch_add(S.tally + vox, (unsigned long long)q, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     c.add(ACC_Q_DEP, q);
   }
   c.add(ACC_N_DEPOSITS, 1);
@@ -338,7 +360,8 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
 
 // One Woodcock step (Sec. 2.1); returns false when the photon is done.
 template <bool LOG>
-__device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G, Counters &c) {
+__device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G,
+                                     const LOCAL uint2 *pal, Counters &c) {
   p.k += 1;
   const uint32_t k = p.k & ~kScatBit;
   if (k > kStepGuard) {
@@ -363,9 +386,17 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
   }
   const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)p.pz, (uint32_t)S.ny) + (uint32_t)p.py,
                                          (uint32_t)S.nx) + (int32_t)p.px;
-  const uint2 rec = S.vox[vox];
-  const float rho = __uint_as_float(rec.x);
-  const int m = (int)rec.y;
+  uint32_t rbits, m;
+  if (S.npal) {  // 1-byte index into the wave's LDS table
+    const uint32_t i8 = S.vox8[vox];
+    rbits = pal[i8].x;
+    m = pal[i8].y;
+  } else {
+    const uint2 rec = S.vox[vox];
+    rbits = rec.x;
+    m = rec.y;
+  }
+  const float rho = __uint_as_float(rbits);
   const GLOBAL float4 *t = S.mu_rho + (size_t)m * (size_t)S.ne + (size_t)p.je;
   const float4 t0 = t[0], t1 = t[1];
   const float mpe = rho * lerpf(t0.x, t1.x, p.we);
@@ -434,11 +465,16 @@ __device__ __forceinline__ int find_bin(const unsigned long long *__restrict__ p
 
 static_assert(sizeof(CaseDev) % 4 == 0 && sizeof(CaseDev) <= 512, "CaseDev copy size");
 
-// Copy a case descriptor into the wave's LDS slot (lanes copy words).
-__device__ __forceinline__ void stage_case(CaseDev *dst, const CaseDev *src, int lane) {
+// Copy a case descriptor (and its voxel palette, if any) into the wave's LDS
+// slots (lanes copy words).
+__device__ __forceinline__ void stage_case(CaseDev *dst, uint2 *pal, const CaseDev *src,
+                                           int lane) {
   const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
   uint32_t *d = reinterpret_cast<uint32_t *>(dst);
   for (int i = lane; i < (int)(sizeof(CaseDev) / 4); i += 64) d[i] = s[i];
+  const uint2 *sp = src->palette;
+  if (__builtin_amdgcn_readfirstlane(src->npal) > 0)
+    for (int i = lane; i < 256; i += 64) pal[i] = sp[i];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -448,13 +484,16 @@ template <bool LOG>
 __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__ rcs, int nrc,
                                                    uint64_t total_chunks,
                                                    unsigned long long *chunk_ctr, int refill_min,
-                                                   int chunk) {
+                                                   int chunk, int tally_mode) {
   __shared__ unsigned long long wave_acc[8][ACC_COUNT];
   __shared__ CaseDev wave_case[8];
+  __shared__ uint2 wave_pal[8][256];
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   CaseDev &G = wave_case[w];
+  uint2 *pal = wave_pal[w];
+  const LOCAL uint2 *pal_lds = (const LOCAL uint2 *)pal;
 
   // wave-uniform state
   StepCase S;
@@ -482,8 +521,8 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
         refills = 0;
         cur = pend;
         pend = -1;
-        stage_case(&G, rcs[cur].cd, lane);
-        S = make_step_case(G);
+        stage_case(&G, pal, rcs[cur].cd, lane);
+        S = make_step_case(G, tally_mode);
         pool_next = pend_lo;
         pool_end = pend_hi;
         wbin = find_bin(rcs[cur].prefix, G.nbins, pool_next);
@@ -505,8 +544,8 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
             if (cur >= 0) flush(cnt, G.acc, lane, refills);
             refills = 0;
             cur = rc;
-            stage_case(&G, rcs[cur].cd, lane);
-            S = make_step_case(G);
+            stage_case(&G, pal, rcs[cur].cd, lane);
+            S = make_step_case(G, tally_mode);
             wbin = find_bin(rcs[cur].prefix, G.nbins, lo);
           }
           pool_next = lo;
@@ -540,29 +579,74 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
       if (queue_done && pend < 0 && pool_next >= pool_end) break;
       continue;
     }
-    if (alive) alive = step<LOG>(p, S, G, cnt);
+    if (alive) alive = step<LOG>(p, S, G, pal_lds, cnt);
   }
   if (cur >= 0) flush(cnt, G.acc, lane, refills);
 }
 
 // --------------------------------------------------------------- fold etc.
 
-// S1 += T_b, S2 += T_b^2 (128-bit), T_b = 0 (Sec. 2.2.1 batch statistics).
-__global__ void __launch_bounds__(256) k_fold(unsigned long long *__restrict__ T,
+// S1 += T_b, S2 += T_b^2 (128-bit), T_b = 0 (Sec. 2.2.1 batch statistics);
+// T_b is the exact sum of the ncopies per-XCD batch tallies.  Block 0 also
+// folds the batch counters into their 128-bit totals; every block records
+// the largest S1 and S2 high word it produced (overflow headroom).
+__global__ void __launch_bounds__(256) k_fold(unsigned long long *__restrict__ T, int ncopies,
                                               long long *__restrict__ S1,
-                                              unsigned long long *__restrict__ S2, int64_t V) {
+                                              unsigned long long *__restrict__ S2, int64_t V,
+                                              unsigned long long *__restrict__ acc) {
+  __shared__ unsigned long long m1[256], m2[256];
+  if (blockIdx.x == 0 && threadIdx.x < ACC_COUNT) {
+    const unsigned long long v = acc[threadIdx.x];
+    if (v) {
+      unsigned long long *tot = acc + kAccTotal + 2 * threadIdx.x;
+      const unsigned long long lo = tot[0] + v;
+      tot[1] += (lo < v) ? 1ull : 0ull;
+      tot[0] = lo;
+      acc[threadIdx.x] = 0ull;
+    }
+  }
+  unsigned long long mx1 = 0ull, mx2 = 0ull;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
-    const unsigned long long t = T[i];
+    unsigned long long t = 0ull;
+    for (int c = 0; c < ncopies; ++c) {
+      const unsigned long long v = T[(int64_t)c * V + i];
+      if (v) {
+        t += v;
+        T[(int64_t)c * V + i] = 0ull;
+      }
+    }
     if (t == 0ull) continue;
-    S1[i] += (long long)t;
+    const long long s1 = S1[i] + (long long)t;
+    S1[i] = s1;
     const unsigned long long lo = S2[2 * i], hi = S2[2 * i + 1];
     const unsigned long long plo = t * t, phi = __umul64hi(t, t);
     const unsigned long long nlo = lo + plo;
+    const unsigned long long nhi = hi + phi + (nlo < lo ? 1ull : 0ull);
     S2[2 * i] = nlo;
-    S2[2 * i + 1] = hi + phi + (nlo < lo ? 1ull : 0ull);
-    T[i] = 0ull;
+    S2[2 * i + 1] = nhi;
+    mx1 = max(mx1, (unsigned long long)s1);
+    mx2 = max(mx2, nhi);
   }
+  m1[threadIdx.x] = mx1;
+  m2[threadIdx.x] = mx2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      m1[threadIdx.x] = max(m1[threadIdx.x], m1[threadIdx.x + o]);
+      m2[threadIdx.x] = max(m2[threadIdx.x], m2[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (m1[0]) atomicMax(acc + kAccMaxS1, m1[0]);
+    if (m2[0]) atomicMax(acc + kAccMaxS2Hi, m2[0]);
+  }
+}
+
+// Largest XCC id over all workgroups (read-only hardware register).
+__global__ void k_xcc_probe(unsigned int *out) {
+  if (threadIdx.x == 0) atomicMax(out, xcc_id());
 }
 
 // Pack (mat, rho) into 8-byte voxel records; per-material max density (as
@@ -693,6 +777,49 @@ __global__ void k_sigma_final(const double *part, int nparts, const double *part
   out[2] = m;
 }
 
+// ------------------------------------------------------- microbenchmarks
+// Peaks the transport is measured against: streaming copy, random 64-bit
+// atomics (no return), atomics into 64 hot words, random 8-byte gathers.
+// Addresses come from a 32-bit integer hash of the operation index.
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ void __launch_bounds__(256) k_mb_copy(const uint4 *__restrict__ a,
+                                                 uint4 *__restrict__ b, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    b[i] = a[i];
+}
+
+__global__ void __launch_bounds__(256) k_mb_atomic(unsigned long long *__restrict__ t,
+                                                   uint32_t mask_or_n, int hot, int64_t ops) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ops; i += stride) {
+    const uint32_t h = mix32((uint32_t)i);
+    const uint32_t idx = hot ? (h & 63u) : (uint32_t)(((uint64_t)h * mask_or_n) >> 32);
+    __hip_atomic_fetch_add(t + idx, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mb_gather(const uint2 *__restrict__ v, uint32_t n,
+                                                   int64_t ops, uint32_t *out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ops; i += stride) {
+    const uint32_t idx = (uint32_t)(((uint64_t)mix32((uint32_t)i ^ acc) * n) >> 32);
+    const uint2 r = v[idx];
+    acc += r.x ^ r.y;
+  }
+  if (acc == 0x12345678u) out[0] = acc;  // keeps the loads live
+}
+
 // ---------------------------------------------------------------- launchers
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
@@ -703,10 +830,10 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
   hipStream_t s = (hipStream_t)stream;
   if (with_log)
     hipLaunchKernelGGL(k_transport<true>, dim3(cfg.grid), dim3(cfg.block), 0, s, rc_dev, nrc,
-                       total_chunks, chunk_ctr, cfg.refill_min, cfg.chunk);
+                       total_chunks, chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode);
   else
     hipLaunchKernelGGL(k_transport<false>, dim3(cfg.grid), dim3(cfg.block), 0, s, rc_dev, nrc,
-                       total_chunks, chunk_ctr, cfg.refill_min, cfg.chunk);
+                       total_chunks, chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode);
   return check_launch();
 }
 
@@ -717,10 +844,15 @@ static int grid_for(int64_t n, int block, int cap) {
   return (int)g;
 }
 
-int launch_fold(unsigned long long *tally, long long *s1, unsigned long long *s2, int64_t V,
-                void *stream) {
+int launch_fold(unsigned long long *tally, int ncopies, long long *s1, unsigned long long *s2,
+                int64_t V, unsigned long long *acc, void *stream) {
   hipLaunchKernelGGL(k_fold, dim3(grid_for(V, 256, 4096)), dim3(256), 0, (hipStream_t)stream,
-                     tally, s1, s2, V);
+                     tally, ncopies, s1, s2, V, acc);
+  return check_launch();
+}
+
+int launch_xcc_probe(unsigned int *out, int blocks, void *stream) {
+  hipLaunchKernelGGL(k_xcc_probe, dim3(blocks), dim3(64), 0, (hipStream_t)stream, out);
   return check_launch();
 }
 
@@ -749,6 +881,29 @@ int launch_sigma(const long long *s1, const unsigned long long *s2, const uint2 
   hipLaunchKernelGGL(k_sigma_sum, dim3(nblocks), dim3(256), 0, s, s1, s2, vox, V, nb, rho_min,
                      frac, kind, pmax, nblocks, psum);
   hipLaunchKernelGGL(k_sigma_final, dim3(1), dim3(64), 0, s, psum, nblocks, pmax, out);
+  return check_launch();
+}
+
+int launch_microbench(int kind, void *buf_a, void *buf_b, int64_t n, int64_t ops, int grid,
+                      void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  switch (kind) {
+    case 0:
+      hipLaunchKernelGGL(k_mb_copy, dim3(grid), dim3(256), 0, s, (const uint4 *)buf_a,
+                         (uint4 *)buf_b, n / 16);
+      break;
+    case 1:
+    case 2:
+      hipLaunchKernelGGL(k_mb_atomic, dim3(grid), dim3(256), 0, s, (unsigned long long *)buf_a,
+                         (uint32_t)(n / 8), kind == 2 ? 1 : 0, ops);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_mb_gather, dim3(grid), dim3(256), 0, s, (const uint2 *)buf_a,
+                         (uint32_t)(n / 8), ops, (uint32_t *)buf_b);
+      break;
+    default:
+      return -1;
+  }
   return check_launch();
 }
 

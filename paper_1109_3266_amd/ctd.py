@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libctd.so")
+# CTD_LIB_PATH selects another build of the same library (e.g. an
+# instrumented variant); by default the in-tree libctd.so is loaded.
+LIB_PATH = os.environ.get("CTD_LIB_PATH") or os.path.join(_HERE, "libctd.so")
 
 CTD_OK = 0
 CTD_EINVAL = -1
@@ -57,9 +59,24 @@ class ctd_params(C.Structure):
 
 
 class ctd_balance(C.Structure):
-    _fields_ = [("q_incident", C.c_int64), ("q_deposited", C.c_int64), ("q_escaped", C.c_int64),
+    _fields_ = [("q_incident_lo", C.c_uint64), ("q_deposited_lo", C.c_uint64),
+                ("q_escaped_lo", C.c_uint64), ("q_incident_hi", C.c_uint64),
+                ("q_deposited_hi", C.c_uint64), ("q_escaped_hi", C.c_uint64),
                 ("n_histories", C.c_uint64), ("n_missed", C.c_uint64),
                 ("n_unscattered", C.c_uint64), ("n_cutoff", C.c_uint64)]
+
+    # exact 128-bit sums as Python ints
+    @property
+    def q_incident(self):
+        return (self.q_incident_hi << 64) | self.q_incident_lo
+
+    @property
+    def q_deposited(self):
+        return (self.q_deposited_hi << 64) | self.q_deposited_lo
+
+    @property
+    def q_escaped(self):
+        return (self.q_escaped_hi << 64) | self.q_escaped_lo
 
 
 class ctd_stats(C.Structure):
@@ -74,7 +91,7 @@ class ctd_stats(C.Structure):
 
 class ctd_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("waves_per_simd", C.c_int32),
-                ("refill_min", C.c_int32), ("chunk", C.c_int32)]
+                ("refill_min", C.c_int32), ("chunk", C.c_int32), ("tally_mode", C.c_int32)]
 
 
 class ctd_event(C.Structure):
@@ -122,6 +139,7 @@ _SIGS = {
     "ctd_read_balance": (I32, [P, P, C.POINTER(ctd_balance)]),
     "ctd_read_stats": (I32, [P, P, C.POINTER(ctd_stats)]),
     "ctd_read_majorant": (I32, [P, P, P]),
+    "ctd_microbench": (I32, [P, I32, U64, U64, C.POINTER(F64), C.POINTER(F64)]),
     "ctd_debug_deposit_log": (I32, [P, P, U64, U64, U64]),
     "ctd_read_event_log": (I32, [P, P, P, U64, C.POINTER(U64)]),
 }
@@ -342,6 +360,15 @@ def ctd_read_majorant(ctx, cs, ne: int) -> np.ndarray:
     out = np.zeros(ne, np.float32)
     check(lib().ctd_read_majorant(ctx, cs, ptr(out)), ctx)
     return out
+
+
+def ctd_microbench(ctx, kind: int, nbytes: int, ops: int = 0):
+    """(rate, ms): kind 0 copy GB/s, 1 random atomics/s, 2 hot-spot
+    atomics/s, 3 random 8-byte gathers/s."""
+    r, t = C.c_double(), C.c_double()
+    check(lib().ctd_microbench(ctx, int(kind), int(nbytes), int(ops), C.byref(r), C.byref(t)),
+          ctx)
+    return r.value, t.value
 
 
 def ctd_debug_deposit_log(ctx, cs, h0: int, nh: int, capacity: int):

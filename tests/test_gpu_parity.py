@@ -152,9 +152,10 @@ def test_tuning_and_repeat_bit_identity(ctx):
     say("bit identity across tunings")
     wl = W.water_cbct(scale=4, n_histories=100_000)
     outs = []
-    for blk, wps, rm, ch in [(256, 4, 16, 256), (256, 8, 1, 64), (512, 2, 64, 4096),
-                             (64, 1, 32, 1024), (256, 4, 16, 256)]:
-        t = L.ctd_tuning(blk, wps, rm, ch)
+    for blk, wps, rm, ch, tm in [(256, 4, 16, 256, 0), (256, 8, 1, 64, 1), (512, 2, 64, 4096, 1),
+                                 (64, 1, 32, 1024, 0), (256, 4, 16, 1024, 1),
+                                 (256, 4, 16, 256, 0)]:
+        t = L.ctd_tuning(blk, wps, rm, ch, tm)
         outs.append(gpu_run(ctx, wl, tuning=t))
     for o in outs[1:]:
         assert np.array_equal(o["s1"], outs[0]["s1"])
@@ -162,6 +163,17 @@ def test_tuning_and_repeat_bit_identity(ctx):
         assert np.array_equal(o["s2_lo"], outs[0]["s2_lo"])
         assert o["bal"].q_escaped == outs[0]["bal"].q_escaped
         assert o["st"].n_steps == outs[0]["st"].n_steps
+
+
+def test_per_xcd_tallies_available(ctx):
+    wl = W.tiny(n_histories=10)
+    with Case(ctx, wl) as c:
+        t = L.ctd_get_tuning(ctx, c.cs)
+        t.tally_mode = 1   # accepted only when every XCC id < 8 (MI355X: 0..7)
+        L.ctd_set_tuning(ctx, c.cs, t)
+        c.run(100_000)
+        b = c.balance()
+        assert int(c.tally()[0].sum()) == b.q_deposited
 
 
 def test_run_many_matches_solo(ctx):
@@ -244,7 +256,9 @@ def test_error_paths(ctx):
             L.ctd_run(ctx, c.cs, 10**18)
         assert e.value.code == L.CTD_EOVERFLOW
         with pytest.raises(L.CtdError):
-            L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(100, 4, 16, 256))
+            L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(100, 4, 16, 256, 0))
+        with pytest.raises(L.CtdError):
+            L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(256, 4, 16, 256, 2))
         with pytest.raises(L.CtdError):
             L.ctd_read_dose(ctx, c.cs, c.V)      # no batches folded yet
         c.run(1000)
@@ -313,3 +327,15 @@ def test_full_size_head_grid_sampled(ctx):
     frac = _pair_histories(g["log"], by_h, hs)
     say(f"head pairing {frac:.4f}")
     assert frac >= 0.99
+
+
+def test_microbenchmarks_report_sane_rates(ctx):
+    say("microbenchmarks")
+    copy, _ = L.ctd_microbench(ctx, 0, 256 << 20)
+    atom, _ = L.ctd_microbench(ctx, 1, 8 << 20, 1 << 24)
+    hot, _ = L.ctd_microbench(ctx, 2, 1 << 20, 1 << 22)
+    gat, _ = L.ctd_microbench(ctx, 3, 8 << 20, 1 << 24)
+    assert 500 < copy < 20_000            # GB/s
+    assert 1e9 < atom < 1e12 and 1e7 < hot < atom and 1e9 < gat < 1e13
+    with pytest.raises(L.CtdError):
+        L.ctd_microbench(ctx, 7, 1 << 20, 1)
