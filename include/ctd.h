@@ -290,6 +290,70 @@ int32_t ctd_debug_deposit_log(ctd_ctx *ctx, ctd_case *cs, uint64_t h0, uint64_t 
 int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out, uint64_t capacity,
                            uint64_t *n);
 
+/* ---------------- serving (continuous batching) ----------------
+ * A server owns a private context on `device` and a host thread.  Phantoms
+ * are registered once (host arrays, copied) and loaded to the device on first
+ * use; they stay resident and are evicted least-recently-used when an
+ * admission needs the room.  Requests (a phantom key, material set, spectrum,
+ * geometry, parameters and a sigma-bar target) queue in arrival order and are
+ * admitted while their device footprint fits hbm_budget_bytes.  Each round
+ * runs one batch of batch_histories for every admitted request in a single
+ * launch of the batched engine; requests arriving meanwhile join the next
+ * round.  Every request follows the batch schedule of ctd_run_to_sigma with
+ * the same batch size, so its result is identical alone or among others.
+ * Material sets, spectra and geometries may come from any context on the same
+ * device and must stay alive until their requests finish. */
+typedef struct {
+  uint64_t hbm_budget_bytes;  /* device memory for request tallies + resident phantoms */
+  uint64_t batch_histories;   /* histories per batch, every request */
+  uint64_t max_histories;     /* per-request cap */
+  double dose_frac;           /* sigma-bar threshold fraction of D_max */
+  int32_t sigma_kind;         /* CTD_SIGMA_LOCAL or CTD_SIGMA_PAPER */
+  int32_t max_active;         /* cap on concurrently admitted requests */
+  ctd_tuning tuning;          /* launch configuration of the rounds; block = 0: default */
+} ctd_server_config;
+
+typedef struct {
+  int32_t state;    /* 0 queued, 1 running, 2 done, 3 cancelled, 4 failed */
+  int32_t status;   /* CTD_* code of a failed or cancelled request */
+  double sigma;     /* last sigma-bar */
+  uint64_t histories;
+  uint32_t batches, reserved;
+  double t_submit, t_admit, t_done; /* seconds on the server clock */
+} ctd_request_info;
+
+typedef struct {
+  uint64_t submitted, completed, rounds, histories;
+  uint64_t phantom_loads, phantom_hits, evictions;
+  uint64_t resident_bytes;
+  uint32_t queued, active;
+} ctd_server_stats;
+
+int32_t ctd_server_start(int32_t device, const ctd_server_config *cfg, ctd_server **out);
+const char *ctd_server_last_error(const ctd_server *sv);
+/* Seconds on the server clock (monotonic, 0 at start). */
+double ctd_server_now(const ctd_server *sv);
+/* Register a phantom under `key` (arrays copied to host memory).  CTD_EBUSY
+ * if the key exists. */
+int32_t ctd_server_add_phantom(ctd_server *sv, uint64_t key, const ctd_grid *g,
+                               const uint8_t *mat, const float *rho);
+/* Queue a request; *ticket identifies it.  CTD_ENOTFOUND for an unknown key. */
+int32_t ctd_server_submit(ctd_server *sv, uint64_t phantom_key, ctd_matset *ms,
+                          ctd_spectrum *sp, ctd_geometry *geo, const ctd_params *p,
+                          double sigma_target, uint64_t *ticket);
+int32_t ctd_server_poll(ctd_server *sv, uint64_t ticket, ctd_request_info *info);
+/* Block until done (CTD_OK), cancelled (CTD_ECANCELLED) or failed. */
+int32_t ctd_server_wait(ctd_server *sv, uint64_t ticket, ctd_request_info *info);
+/* Exact sums of a done request (host copies; V-sized caller arrays). */
+int32_t ctd_server_read_tally(ctd_server *sv, uint64_t ticket, int64_t *s1, uint64_t *s2_hi,
+                              uint64_t *s2_lo, uint32_t *n_batches);
+/* Forget a finished request (frees its host results). */
+int32_t ctd_server_release(ctd_server *sv, uint64_t ticket);
+int32_t ctd_server_cancel(ctd_server *sv, uint64_t ticket);
+int32_t ctd_server_read_stats(ctd_server *sv, ctd_server_stats *out);
+/* Finish the running round, cancel the rest, free everything. */
+int32_t ctd_server_stop(ctd_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

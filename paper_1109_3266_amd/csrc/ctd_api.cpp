@@ -249,7 +249,7 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
 
 extern "C" int32_t ctd_phantom_release(ctd_ctx *ctx, ctd_phantom *ph) {
   if (!ctx || !ph) return CTD_EINVAL;
-  if (ph->refs > 0) return set_err(ctx, CTD_EBUSY, "phantom is used by %d case(s)", ph->refs);
+  if (ph->refs > 0) return set_err(ctx, CTD_EBUSY, "phantom is used by %d case(s)", ph->refs.load());
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   dfree(ph->vox8);
@@ -346,7 +346,7 @@ extern "C" int32_t ctd_materials_load(ctd_ctx *ctx, const ctd_egrid *eg, int32_t
 
 extern "C" int32_t ctd_materials_release(ctd_ctx *ctx, ctd_matset *ms) {
   if (!ctx || !ms) return CTD_EINVAL;
-  if (ms->refs > 0) return set_err(ctx, CTD_EBUSY, "material set is used by %d case(s)", ms->refs);
+  if (ms->refs > 0) return set_err(ctx, CTD_EBUSY, "material set is used by %d case(s)", ms->refs.load());
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   dfree(ms->d_mu);
@@ -382,7 +382,7 @@ extern "C" int32_t ctd_spectrum_set(ctd_ctx *ctx, int32_t nbins, const double *e
 
 extern "C" int32_t ctd_spectrum_release(ctd_ctx *ctx, ctd_spectrum *sp) {
   if (!ctx || !sp) return CTD_EINVAL;
-  if (sp->refs > 0) return set_err(ctx, CTD_EBUSY, "spectrum is used by %d case(s)", sp->refs);
+  if (sp->refs > 0) return set_err(ctx, CTD_EBUSY, "spectrum is used by %d case(s)", sp->refs.load());
   delete sp;
   return CTD_OK;
 }
@@ -418,7 +418,7 @@ extern "C" int32_t ctd_geometry_set(ctd_ctx *ctx, const ctd_geom *g, ctd_geometr
 
 extern "C" int32_t ctd_geometry_release(ctd_ctx *ctx, ctd_geometry *geo) {
   if (!ctx || !geo) return CTD_EINVAL;
-  if (geo->refs > 0) return set_err(ctx, CTD_EBUSY, "geometry is used by %d case(s)", geo->refs);
+  if (geo->refs > 0) return set_err(ctx, CTD_EBUSY, "geometry is used by %d case(s)", geo->refs.load());
   delete geo;
   return CTD_OK;
 }
@@ -491,7 +491,7 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
   };
   hipError_t e;
   std::vector<float> blo(sp->lo.begin(), sp->lo.end());
-  if ((e = hipMalloc(&cs->d_tally, 8 * V * kTallyCopies)) != hipSuccess ||
+  if ((e = hipMalloc(&cs->d_tally, 8 * V)) != hipSuccess ||
       (e = hipMalloc(&cs->d_s1, 8 * V)) != hipSuccess ||
       (e = hipMalloc(&cs->d_s2, 16 * V)) != hipSuccess ||
       (e = hipMalloc(&cs->d_acc, 8 * kAccWords)) != hipSuccess ||
@@ -510,8 +510,8 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
                                     sizeof(float2) * geo->proj_sc.size(),
                                     hipMemcpyHostToDevice)) != hipSuccess))
     return cleanup(hip_err(ctx, e, "case upload"));
-  if (launch_zero(cs->d_tally, 8 * V * kTallyCopies, ctx->stream) ||
-      launch_zero(cs->d_s1, 8 * V, ctx->stream) || launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
+  if (launch_zero(cs->d_tally, 8 * V, ctx->stream) || launch_zero(cs->d_s1, 8 * V, ctx->stream) ||
+      launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
       launch_zero(cs->d_acc, 8 * kAccWords, ctx->stream))
     return cleanup(hip_err(ctx, hipGetLastError(), "case clear"));
   fill_desc(cs);
@@ -631,7 +631,7 @@ extern "C" int32_t ctd_case_reset(ctd_ctx *ctx, ctd_case *cs) {
   if (!ctx || !cs) return CTD_EINVAL;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   const int64_t V = cs->ph->V;
-  if (launch_zero(cs->d_tally, 8 * V * kTallyCopies, ctx->stream) ||
+  if (launch_zero(cs->d_tally, 8 * V * cs->tally_copies, ctx->stream) ||
       launch_zero(cs->d_s1, 8 * V, ctx->stream) || launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
       launch_zero(cs->d_acc, 8 * kAccWords, ctx->stream))
     return hip_err(ctx, hipGetLastError(), "case reset");
@@ -669,11 +669,39 @@ static bool tuning_ok(const ctd_tuning &t) {
          (t.tally_mode == 0 || t.tally_mode == 1);
 }
 
+int ctd::ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies) {
+  if (cs->tally_copies >= copies) return CTD_OK;
+  const int64_t V = cs->ph->V;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  unsigned long long *t = nullptr;
+  HIPCHK(ctx, hipMalloc(&t, 8 * V * copies));
+  // batch tallies are zero between rounds: a fresh zeroed array replaces them
+  if (launch_zero(t, 8 * V * copies, ctx->stream) != 0) {
+    dfree(t);
+    return hip_err(ctx, hipGetLastError(), "tally clear");
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  dfree(cs->d_tally);
+  cs->d_tally = t;
+  cs->tally_copies = copies;
+  fill_desc(cs);
+  return upload_desc(ctx, cs);
+}
+
+uint64_t ctd::case_footprint(int64_t V) {
+  return (uint64_t)V * 32 + 8 * kAccWords + sizeof(CaseDev) + 65536;
+}
+
 extern "C" int32_t ctd_set_tuning(ctd_ctx *ctx, ctd_case *cs, const ctd_tuning *t) {
   if (!ctx || !cs || !t) return CTD_EINVAL;
   NEED(ctx, tuning_ok(*t), "tuning out of range");
   NEED(ctx, t->tally_mode == 0 || ctx->xcd_tally_ok,
        "per-XCD tallies unavailable: XCC id %u >= %d", ctx->max_xcc, kTallyCopies);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (t->tally_mode == 1) {
+    int rc = ensure_tally_copies(ctx, cs, kTallyCopies);
+    if (rc != CTD_OK) return rc;
+  }
   cs->tune = *t;
   return CTD_OK;
 }
@@ -792,6 +820,10 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     if (n[i] == 0) continue;
     int rc0 = check_headroom(ctx, cases[i], n[i]);
     if (rc0 != CTD_OK) return rc0;
+    if (t.tally_mode == 1 && cases[i]->tally_copies < kTallyCopies) {
+      rc0 = ensure_tally_copies(ctx, cases[i], kTallyCopies);
+      if (rc0 != CTD_OK) return rc0;
+    }
     RoundItem it;
     it.cd = cases[i]->d_desc;
     it.h_begin = cases[i]->h_next;
@@ -907,6 +939,14 @@ extern "C" int32_t ctd_sigma(ctd_ctx *ctx, ctd_case *cs, int32_t sigma_kind, dou
   return sigma_now(ctx, cs, sigma_kind, dose_frac, out);
 }
 
+// sigma ~ batches^-1/2 at a fixed batch size: aim 2 % past the target.
+uint64_t ctd::sigma_plan(uint64_t have, double sig, double target, uint64_t max_batches) {
+  if (sig <= target || have >= max_batches) return 0;
+  const double want = std::ceil((double)have * (sig / target) * (sig / target) * 1.02);
+  uint64_t more = (uint64_t)std::max(1.0, want - (double)have);
+  return std::min(more, max_batches - have);
+}
+
 int ctd::run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count) {
   int rc = CTD_OK;
   std::vector<ctd_case *> one{cs};
@@ -945,12 +985,8 @@ extern "C" int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, d
   for (;;) {
     rc = sigma_now(ctx, cs, sigma_kind, dose_frac, &sig);
     if (rc != CTD_OK) return rc;
-    have = cs->batches;
-    if (sig <= target || have >= max_b) break;
-    // sigma ~ batches^-1/2 at fixed batch size
-    const double want = std::ceil((double)have * (sig / target) * (sig / target) * 1.02);
-    uint64_t more = (uint64_t)std::max(1.0, want - (double)have);
-    more = std::min(more, max_b - have);
+    const uint64_t more = sigma_plan(cs->batches, sig, target, max_b);
+    if (more == 0) break;
     rc = run_batches(ctx, cs, batch_histories, more);
     if (rc != CTD_OK) return rc;
   }
@@ -1176,6 +1212,7 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
     dfree(tw.d_desc);
   };
   hipError_t e;
+  tw.tally_copies = kTallyCopies;
   if ((e = hipMalloc(&tw.d_tally, 8 * V * kTallyCopies)) != hipSuccess ||
       (e = hipMalloc(&tw.d_s1, 8 * V)) != hipSuccess ||
       (e = hipMalloc(&tw.d_s2, 16 * V)) != hipSuccess ||
@@ -1238,6 +1275,8 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
   (void)hipStreamSynchronize(ctx->stream);
   release();
   if (rc != CTD_OK) return rc;
+  if (best_t.tally_mode == 1 && (rc = ensure_tally_copies(ctx, cs, kTallyCopies)) != CTD_OK)
+    return rc;
   cs->tune = best_t;
   if (best) *best = best_t;
   return CTD_OK;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -53,7 +54,7 @@ struct ctd_phantom {
   double rho_max[256] = {};
   bool present[256] = {};
   int max_mat = 0;
-  int refs = 0;
+  std::atomic<int> refs{0};
 };
 
 struct ctd_matset {
@@ -63,19 +64,19 @@ struct ctd_matset {
   float4 *d_mu = nullptr;
   float4 *d_comp = nullptr;
   float4 *d_rayl = nullptr;
-  int refs = 0;
+  std::atomic<int> refs{0};
 };
 
 struct ctd_spectrum {
   std::vector<double> lo, w;
   double width = 0.0;
-  int refs = 0;
+  std::atomic<int> refs{0};
 };
 
 struct ctd_geometry {
   ctd_geom g{};
   std::vector<float2> proj_sc;
-  int refs = 0;
+  std::atomic<int> refs{0};
 };
 
 struct ctd_case {
@@ -94,6 +95,7 @@ struct ctd_case {
   float *d_bin_lo = nullptr;
   float2 *d_proj = nullptr;
   unsigned long long *d_tally = nullptr;
+  int tally_copies = 1;     // 1, or kTallyCopies once tally_mode 1 is selected
   long long *d_s1 = nullptr;
   unsigned long long *d_s2 = nullptr;
   unsigned long long *d_acc = nullptr;
@@ -130,5 +132,11 @@ int run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vector<ui
 std::vector<uint64_t> split_batches(uint64_t n, int nb);
 int sigma_now(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *out);
 int run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count);
+// Run-to-sigma schedule shared by ctd_run_to_sigma and the server: batches to
+// add after `have` batches at sigma-bar `sig` (0 = stop).
+uint64_t sigma_plan(uint64_t have, double sig, double target, uint64_t max_batches);
+int ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies);
+// Device bytes a case over V voxels allocates (tallies, sums, counters).
+uint64_t case_footprint(int64_t V);
 
 }  // namespace ctd

@@ -99,6 +99,25 @@ class ctd_event(C.Structure):
                 ("reserved", C.c_int32), ("vox", C.c_int64), ("e", C.c_float), ("E", C.c_float)]
 
 
+class ctd_server_config(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("batch_histories", C.c_uint64),
+                ("max_histories", C.c_uint64), ("dose_frac", C.c_double),
+                ("sigma_kind", C.c_int32), ("max_active", C.c_int32), ("tuning", ctd_tuning)]
+
+
+class ctd_request_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("sigma", C.c_double),
+                ("histories", C.c_uint64), ("batches", C.c_uint32), ("reserved", C.c_uint32),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ctd_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rounds", C.c_uint64),
+                ("histories", C.c_uint64), ("phantom_loads", C.c_uint64),
+                ("phantom_hits", C.c_uint64), ("evictions", C.c_uint64),
+                ("resident_bytes", C.c_uint64), ("queued", C.c_uint32), ("active", C.c_uint32)]
+
+
 EVENT_DTYPE = np.dtype([("h", "<u8"), ("seq", "<u4"), ("k", "<u4"), ("type", "<i4"),
                         ("reserved", "<i4"), ("vox", "<i8"), ("e", "<f4"), ("E", "<f4")])
 
@@ -141,6 +160,18 @@ _SIGS = {
     "ctd_read_majorant": (I32, [P, P, P]),
     "ctd_microbench": (I32, [P, I32, U64, U64, C.POINTER(F64), C.POINTER(F64)]),
     "ctd_debug_deposit_log": (I32, [P, P, U64, U64, U64]),
+    "ctd_server_start": (I32, [I32, C.POINTER(ctd_server_config), PP]),
+    "ctd_server_last_error": (C.c_char_p, [P]),
+    "ctd_server_now": (F64, [P]),
+    "ctd_server_add_phantom": (I32, [P, U64, C.POINTER(ctd_grid), P, P]),
+    "ctd_server_submit": (I32, [P, U64, P, P, P, C.POINTER(ctd_params), F64, C.POINTER(U64)]),
+    "ctd_server_poll": (I32, [P, U64, C.POINTER(ctd_request_info)]),
+    "ctd_server_wait": (I32, [P, U64, C.POINTER(ctd_request_info)]),
+    "ctd_server_read_tally": (I32, [P, U64, P, P, P, C.POINTER(U32)]),
+    "ctd_server_release": (I32, [P, U64]),
+    "ctd_server_cancel": (I32, [P, U64]),
+    "ctd_server_read_stats": (I32, [P, C.POINTER(ctd_server_stats)]),
+    "ctd_server_stop": (I32, [P]),
     "ctd_read_event_log": (I32, [P, P, P, U64, C.POINTER(U64)]),
 }
 
@@ -382,6 +413,78 @@ def ctd_read_event_log(ctx, cs, capacity: int) -> np.ndarray:
     if n.value > capacity:
         raise RuntimeError(f"event log overflow: {n.value} > {capacity}")
     return buf[: n.value]
+
+
+# ---- serving ----
+
+def _scheck(rc: int, sv) -> None:
+    if rc != CTD_OK:
+        s = lib().ctd_server_last_error(sv)
+        raise CtdError(rc, s.decode() if s else "")
+
+
+def ctd_server_start(device: int, cfg: ctd_server_config):
+    h = C.c_void_p()
+    _scheck(lib().ctd_server_start(device, C.byref(cfg), C.byref(h)), None)
+    return h
+
+
+def ctd_server_now(sv) -> float:
+    return lib().ctd_server_now(sv)
+
+
+def ctd_server_add_phantom(sv, key: int, grid: ctd_grid, mat, rho):
+    m = np.ascontiguousarray(mat, dtype=np.uint8)
+    r = np.ascontiguousarray(rho, dtype=np.float32)
+    _scheck(lib().ctd_server_add_phantom(sv, int(key), C.byref(grid), ptr(m), ptr(r)), sv)
+
+
+def ctd_server_submit(sv, key: int, ms, sp, geo, p: ctd_params, target: float) -> int:
+    t = C.c_uint64()
+    _scheck(lib().ctd_server_submit(sv, int(key), ms, sp, geo, C.byref(p), float(target),
+                                    C.byref(t)), sv)
+    return t.value
+
+
+def ctd_server_poll(sv, ticket: int) -> ctd_request_info:
+    info = ctd_request_info()
+    _scheck(lib().ctd_server_poll(sv, int(ticket), C.byref(info)), sv)
+    return info
+
+
+def ctd_server_wait(sv, ticket: int):
+    """(status, info): status CTD_OK, CTD_ECANCELLED or an error code."""
+    info = ctd_request_info()
+    rc = lib().ctd_server_wait(sv, int(ticket), C.byref(info))
+    return rc, info
+
+
+def ctd_server_read_tally(sv, ticket: int, V: int):
+    s1 = np.zeros(V, np.int64)
+    hi = np.zeros(V, np.uint64)
+    lo = np.zeros(V, np.uint64)
+    nb = C.c_uint32()
+    _scheck(lib().ctd_server_read_tally(sv, int(ticket), ptr(s1), ptr(hi), ptr(lo),
+                                        C.byref(nb)), sv)
+    return s1, hi, lo, nb.value
+
+
+def ctd_server_release(sv, ticket: int):
+    _scheck(lib().ctd_server_release(sv, int(ticket)), sv)
+
+
+def ctd_server_cancel(sv, ticket: int):
+    _scheck(lib().ctd_server_cancel(sv, int(ticket)), sv)
+
+
+def ctd_server_read_stats(sv) -> ctd_server_stats:
+    st = ctd_server_stats()
+    _scheck(lib().ctd_server_read_stats(sv, C.byref(st)), sv)
+    return st
+
+
+def ctd_server_stop(sv):
+    return lib().ctd_server_stop(sv)
 
 
 def declared_symbols(header: str | None = None) -> list:

@@ -58,6 +58,42 @@ def surfaces(wl):
     return comp, rayl
 
 
+class Inputs:
+    """Material set, spectrum and geometry of a workload bound in a context
+    (without a phantom or case), e.g. for server requests."""
+
+    def __init__(self, ctx, wl, mu_rho=None):
+        self.ctx = ctx
+        eg = L.ctd_egrid()
+        eg.e0, eg.de, eg.ne = wl.e0, wl.de, wl.ne
+        comp, rayl = surfaces(wl)
+        self.ms = L.ctd_materials_load(ctx, eg, wl.mu_rho() if mu_rho is None else mu_rho,
+                                       comp, 0, rayl)
+        self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
+        self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
+
+    def close(self):
+        if self.ms is not None:
+            L.ctd_geometry_release(self.ctx, self.geo)
+            L.ctd_spectrum_release(self.ctx, self.sp)
+            L.ctd_materials_release(self.ctx, self.ms)
+            self.ms = None
+
+
+def params(wl, seed=None, n_batches=None, rho_min=0.05) -> L.ctd_params:
+    p = L.ctd_params()
+    p.e_cut_kev = wl.e_cut
+    p.seed = wl.seed if seed is None else seed
+    p.n_batches = wl.n_batches if n_batches is None else n_batches
+    p.rayleigh = int(wl.rayleigh)
+    p.sigma_rho_min = rho_min
+    return p
+
+
+def grid(wl) -> L.ctd_grid:
+    return _grid(wl.grid)
+
+
 class Case:
     """One dose problem bound in the library (phantom, tables, spectrum,
     geometry, case).  ``close()`` releases everything."""

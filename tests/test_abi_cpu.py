@@ -62,3 +62,21 @@ def test_surface_builder_rejects_bad_input():
     assert lib.ctd_surface_build(2, 5, L.ptr(pdf), 4, L.ptr(out)) == L.CTD_OK
     # uniform pdf: the inverse CDF is the identity map zeta -> 2 zeta - 1
     assert np.allclose(out, np.linspace(-1, 1, 4)[None, :], atol=1e-7)
+
+
+def test_server_start_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cfg = L.ctd_server_config()
+    cfg.hbm_budget_bytes = 1 << 30
+    cfg.batch_histories = 1000
+    cfg.max_histories = 10**6
+    cfg.dose_frac = 0.5
+    cfg.max_active = 4
+    with pytest.raises(L.CtdError) as e:
+        L.ctd_server_start(0, cfg)
+    assert e.value.code == L.CTD_EDEVICE
+    bad = L.ctd_server_config()   # zero batch size
+    h = ctypes.c_void_p()
+    assert L.lib().ctd_server_start(0, ctypes.byref(bad), ctypes.byref(h)) == L.CTD_EINVAL

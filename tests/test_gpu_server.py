@@ -1,0 +1,156 @@
+"""Serving loop (continuous batching) on the GPU: each request's exact sums
+equal a solo ctd_run_to_sigma with the same batch size; admission by device
+footprint with resident phantoms; cancellation and error codes."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1109_3266_amd import ctd as L
+from paper_1109_3266_amd.session import Case, Inputs, grid, params
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BATCH = 50_000
+TARGET = 0.08
+MAX_H = 20_000_000
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    h = L.ctd_create(0)
+    yield h
+    L.ctd_destroy(h)
+
+
+def _cfg(budget=8 << 30, max_active=16, max_h=MAX_H):
+    c = L.ctd_server_config()
+    c.hbm_budget_bytes = budget
+    c.batch_histories = BATCH
+    c.max_histories = max_h
+    c.dose_frac = 0.5
+    c.sigma_kind = L.CTD_SIGMA_LOCAL
+    c.max_active = max_active
+    return c
+
+
+def _requests(n, seed=77):
+    rng = np.random.default_rng(seed)
+    return [W.batched_case(rng, 9000 + i, f"r{i}", size_scale=0.25) for i in range(n)]
+
+
+def _solo(ctx, wl):
+    with Case(ctx, wl) as c:
+        sig = L.ctd_run_to_sigma(ctx, c.cs, TARGET, 0.5, L.CTD_SIGMA_LOCAL, BATCH, MAX_H)
+        s1, hi, lo, nb = c.tally()
+    return sig, s1, hi, lo, nb
+
+
+def test_server_results_identical_to_solo(ctx):
+    say("server vs solo")
+    wls = _requests(5)
+    solo = [_solo(ctx, wl) for wl in wls]
+    sv = L.ctd_server_start(0, _cfg())
+    inputs = [Inputs(ctx, wl) for wl in wls]
+    try:
+        tickets = []
+        for i, (wl, inp) in enumerate(zip(wls, inputs)):
+            L.ctd_server_add_phantom(sv, i, grid(wl), wl.mat, wl.rho)
+            tickets.append(L.ctd_server_submit(sv, i, inp.ms, inp.sp, inp.geo, params(wl),
+                                               TARGET))
+            time.sleep(0.01 * i)   # staggered arrivals join running rounds
+        for i, (t, wl) in enumerate(zip(tickets, wls)):
+            rc, info = L.ctd_server_wait(sv, t)
+            assert rc == L.CTD_OK and info.state == 2
+            s1, hi, lo, nb = L.ctd_server_read_tally(sv, t, wl.n_voxels)
+            sig, r1, rhi, rlo, rnb = solo[i]
+            assert nb == rnb and info.batches == rnb
+            assert info.sigma == pytest.approx(sig, rel=0, abs=0)
+            assert np.array_equal(s1, r1) and np.array_equal(hi, rhi) and np.array_equal(lo, rlo)
+            assert info.t_submit <= info.t_admit <= info.t_done
+            L.ctd_server_release(sv, t)
+        st = L.ctd_server_read_stats(sv)
+        assert st.completed == 5 and st.rounds >= 10 and st.phantom_loads == 5
+    finally:
+        L.ctd_server_stop(sv)
+        for inp in inputs:
+            inp.close()
+
+
+def test_server_admission_budget_and_resident_phantoms(ctx):
+    say("server admission")
+    wls = _requests(3, seed=5)
+    V = max(wl.n_voxels for wl in wls)
+    # room for about one request (tallies 32 B/voxel + phantom 9 B/voxel)
+    sv = L.ctd_server_start(0, _cfg(budget=V * 41 + (4 << 20)))
+    inputs = [Inputs(ctx, wl) for wl in wls]
+    try:
+        for i, wl in enumerate(wls):
+            L.ctd_server_add_phantom(sv, i, grid(wl), wl.mat, wl.rho)
+        # the same phantom twice in a row is served from the resident copy
+        keys = [0, 0, 1, 2, 0]
+        tickets = [L.ctd_server_submit(sv, k, inputs[k].ms, inputs[k].sp, inputs[k].geo,
+                                       params(wls[k]), TARGET) for k in keys]
+        infos = []
+        for t in tickets:
+            rc, info = L.ctd_server_wait(sv, t)
+            assert rc == L.CTD_OK
+            infos.append(info)
+        st = L.ctd_server_read_stats(sv)
+        assert st.completed == 5
+        assert st.phantom_hits >= 1
+        assert st.evictions >= 1
+        assert st.active == 0 and st.queued == 0
+        # identical inputs give identical results
+        a = L.ctd_server_read_tally(sv, tickets[0], wls[0].n_voxels)
+        b = L.ctd_server_read_tally(sv, tickets[4], wls[0].n_voxels)
+        assert np.array_equal(a[0], b[0])
+    finally:
+        L.ctd_server_stop(sv)
+        for inp in inputs:
+            inp.close()
+
+
+def test_server_cancel_and_errors(ctx):
+    say("server cancel")
+    wl = _requests(1, seed=9)[0]
+    sv = L.ctd_server_start(0, _cfg(max_h=10**15))
+    inp = Inputs(ctx, wl)
+    try:
+        L.ctd_server_add_phantom(sv, 1, grid(wl), wl.mat, wl.rho)
+        with pytest.raises(L.CtdError) as e:
+            L.ctd_server_submit(sv, 99, inp.ms, inp.sp, inp.geo, params(wl), TARGET)
+        assert e.value.code == L.CTD_ENOTFOUND
+        with pytest.raises(L.CtdError) as e:
+            L.ctd_server_add_phantom(sv, 1, grid(wl), wl.mat, wl.rho)
+        assert e.value.code == L.CTD_EBUSY
+        t = L.ctd_server_submit(sv, 1, inp.ms, inp.sp, inp.geo, params(wl), 1e-9)
+        time.sleep(0.2)
+        assert L.ctd_server_poll(sv, t).state == 1   # running: the target is out of reach
+        L.ctd_server_cancel(sv, t)
+        rc, info = L.ctd_server_wait(sv, t)
+        assert rc == L.CTD_ECANCELLED and info.state == 3
+        with pytest.raises(L.CtdError) as e:
+            L.ctd_server_poll(sv, 12345)
+        assert e.value.code == L.CTD_ENOTFOUND
+    finally:
+        L.ctd_server_stop(sv)
+        inp.close()
+    # a request larger than the whole budget fails with ENOMEM
+    sv = L.ctd_server_start(0, _cfg(budget=1 << 20))
+    inp = Inputs(ctx, wl)
+    try:
+        L.ctd_server_add_phantom(sv, 1, grid(wl), wl.mat, wl.rho)
+        t = L.ctd_server_submit(sv, 1, inp.ms, inp.sp, inp.geo, params(wl), TARGET)
+        rc, info = L.ctd_server_wait(sv, t)
+        assert rc == L.CTD_ENOMEM and info.state == 4
+    finally:
+        L.ctd_server_stop(sv)
+        inp.close()
