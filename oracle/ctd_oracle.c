@@ -54,7 +54,7 @@ typedef struct {
   int32_t ne, nzeta, rayleigh, kind; /* kind: 0 pencil, 1 cone */
   double e0, de;            /* energy grid: E_j = e0 + j*de */
   const float *mu_rho;      /* [nmat][ne][3] cm^2/g: pe, Compton, Rayleigh */
-  const float *comp_surf;   /* [ne][nzeta]   Compton inverse CDF mu(zeta,E) */
+  const float *comp_surf;   /* [1 or nmat][ne][nzeta] Compton inverse CDF mu(zeta,E) */
   const float *rayl_surf;   /* [nmat][ne][nzeta] Rayleigh inverse CDF or NULL */
   const float *mu_max;      /* [ne] majorant nodes, cm^-1 */
   int32_t nbins, nproj;
@@ -65,6 +65,7 @@ typedef struct {
   double sad, iso[3], a0, a1, b0, b1, phi0_deg, arc_deg; /* cone source */
   double e_cut;             /* keV */
   uint64_t seed;
+  int32_t comp_per_mat, pad_c;  /* 1: one Compton surface per material (Eq. 2 with S) */
 } or_case;
 
 typedef struct {
@@ -416,7 +417,8 @@ static int history(const or_case *c, uint64_t h, int j, tally_t *t, log_t *L) {
     } else if (xi < mpe + mc) {                       /* Compton */
       t->n_real += 1; t->n_compton += 1;
       scattered = 1;
-      double mu = surface(c->comp_surf, c->nzeta, je, we, u[2]);
+      const float *CS = c->comp_surf + (c->comp_per_mat ? (size_t)m * c->ne * c->nzeta : 0);
+      double mu = surface(CS, c->nzeta, je, we, u[2]);
       double Ep = E / (1.0 + (E / ME_C2_KEV) * (1.0 - mu));
       deposit(t, vox, E - Ep);
       rotate(d, mu, TWO_PI * u[3]);

@@ -57,6 +57,7 @@ class Case(C.Structure):
         ("a0", C.c_double), ("a1", C.c_double), ("b0", C.c_double), ("b1", C.c_double),
         ("phi0_deg", C.c_double), ("arc_deg", C.c_double),
         ("e_cut", C.c_double), ("seed", C.c_uint64),
+        ("comp_per_mat", C.c_int32), ("pad_c", C.c_int32),
     ]
 
 
@@ -159,8 +160,17 @@ class OracleCase:
         self.rho = np.ascontiguousarray(wl.rho, dtype=np.float32)
         self.mu_rho = np.ascontiguousarray(wl.mu_rho() if mu_rho is None else mu_rho,
                                            dtype=np.float32)
-        self.comp = (np.ascontiguousarray(comp_surf, dtype=np.float32) if comp_surf is not None
-                     else build_surface(wl.compton_pdf(), wl.n_zeta))
+        per_mat = getattr(wl, "compton_per_material", False)
+        if comp_surf is not None:
+            self.comp = np.ascontiguousarray(comp_surf, dtype=np.float32)
+        elif per_mat:
+            self.comp = np.stack([build_surface(wl.compton_pdf(m), wl.n_zeta)
+                                  for m in range(len(wl.materials))])
+        else:
+            self.comp = build_surface(wl.compton_pdf(), wl.n_zeta)
+        want = ((len(wl.materials),) if per_mat else ()) + (wl.ne, wl.n_zeta)
+        if self.comp.shape != want:
+            raise ValueError(f"Compton surface shape {self.comp.shape}, expected {want}")
         if wl.rayleigh:
             self.rayl = (np.ascontiguousarray(rayl_surf, dtype=np.float32)
                          if rayl_surf is not None
@@ -199,6 +209,7 @@ class OracleCase:
             c.nproj = geo["nproj"]
         c.e_cut = wl.e_cut
         c.seed = wl.seed
+        c.comp_per_mat = int(per_mat)
         self.c = c
         rc = lib().or_majorant(C.byref(c), _p(self.mu_max))
         if rc != 0:

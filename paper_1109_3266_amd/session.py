@@ -42,10 +42,19 @@ def _geom(geo: dict) -> L.ctd_geom:
 def surfaces(wl):
     """(Compton surface [ne][nz], Rayleigh surfaces [M][ne][nz] or None),
     cached by material and grid."""
-    key_c = ("compton", wl.e0, wl.de, wl.ne, wl.n_mu_c, wl.n_zeta)
-    if key_c not in _surface_cache:
-        _surface_cache[key_c] = L.ctd_surface_build(wl.compton_pdf(), wl.n_zeta)
-    comp = _surface_cache[key_c]
+    if getattr(wl, "compton_per_material", False):
+        rows = []
+        for m, name in enumerate(wl.materials):
+            key = ("compton-wh", name, wl.e0, wl.de, wl.ne, wl.n_mu_c, wl.n_zeta)
+            if key not in _surface_cache:
+                _surface_cache[key] = L.ctd_surface_build(wl.compton_pdf(m), wl.n_zeta)
+            rows.append(_surface_cache[key])
+        comp = np.stack(rows)
+    else:
+        key_c = ("compton", wl.e0, wl.de, wl.ne, wl.n_mu_c, wl.n_zeta)
+        if key_c not in _surface_cache:
+            _surface_cache[key_c] = L.ctd_surface_build(wl.compton_pdf(), wl.n_zeta)
+        comp = _surface_cache[key_c]
     rayl = None
     if wl.rayleigh:
         rows = []
@@ -68,7 +77,7 @@ class Inputs:
         eg.e0, eg.de, eg.ne = wl.e0, wl.de, wl.ne
         comp, rayl = surfaces(wl)
         self.ms = L.ctd_materials_load(ctx, eg, wl.mu_rho() if mu_rho is None else mu_rho,
-                                       comp, 0, rayl)
+                                       comp, int(comp.ndim == 3), rayl)
         self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
         self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
 
@@ -113,7 +122,7 @@ class Case:
         eg.e0, eg.de, eg.ne = wl.e0, wl.de, wl.ne
         comp, rayl = surfaces(wl)
         mu = wl.mu_rho() if mu_rho is None else mu_rho
-        self.ms = L.ctd_materials_load(ctx, eg, mu, comp, 0, rayl)
+        self.ms = L.ctd_materials_load(ctx, eg, mu, comp, int(comp.ndim == 3), rayl)
         self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
         self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
         p = L.ctd_params()

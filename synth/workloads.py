@@ -62,17 +62,27 @@ class Workload:
     n_zeta: int = N_ZETA
     n_mu_c: int = N_MU_COMPTON
     n_mu_r: int = N_MU_RAYLEIGH
+    compton: str = "kn"        # "kn" free electron, "wh" Waller-Hartree (Eq. 2 with S)
     extra: dict = field(default_factory=dict)
 
     # --- physics data for this workload's material list ---
     def mu_rho(self) -> np.ndarray:
         """float32 [M][N_E][3] (pe, Compton, Rayleigh) cm^2/g."""
         t = ph.mu_rho_table(self.materials, e_nodes(self.e0, self.de, self.ne),
-                            rayleigh=self.rayleigh)
+                            rayleigh=self.rayleigh, compton=self.compton)
         return t.astype(np.float32)
 
-    def compton_pdf(self) -> np.ndarray:
-        return ph.kn_pdf_table(e_nodes(self.e0, self.de, self.ne), self.n_mu_c)
+    @property
+    def compton_per_material(self) -> bool:
+        return self.compton == "wh"
+
+    def compton_pdf(self, m: int = 0) -> np.ndarray:
+        """Compton angular pdf [N_E][n_mu_c]: one shared K-N table, or the
+        bound-electron table of material m."""
+        en = e_nodes(self.e0, self.de, self.ne)
+        if self.compton == "wh":
+            return ph.wh_compton_pdf_table(self.materials[m], en, self.n_mu_c)
+        return ph.kn_pdf_table(en, self.n_mu_c)
 
     def rayleigh_pdf(self, m: int) -> np.ndarray:
         """Rayleigh angular pdf of material m, [N_E][n_mu_r] (one material at

@@ -91,6 +91,25 @@ def test_paired_parity(ctx, name, kw):
     assert abs(st.n_compton - r["n_compton"]) <= 2e-3 * r["n_compton"] + 5
 
 
+@pytest.mark.parametrize("name,kw", [
+    ("head", dict(n_histories=200_000, scale=4)),
+    ("water_cbct", dict(n_histories=100_000, scale=4)),
+])
+def test_paired_parity_bound_electron_compton(ctx, name, kw):
+    """Per-material Compton surfaces (Eq. 2 with S) on the GPU vs the oracle."""
+    say(f"paired parity bound-electron Compton {name} {kw}")
+    wl = W.by_name(name, **kw)
+    wl.compton = "wh"
+    g = gpu_run(ctx, wl)
+    check_balance(g, wl.n_histories)
+    oc = O.OracleCase(wl)
+    assert oc.comp.ndim == 3
+    assert np.array_equal(g["mu_max"], oc.mu_max)
+    r = O.run(oc, threads=8)
+    paired_compare(g, r)
+    assert abs(g["st"].n_compton - r["n_compton"]) <= 2e-3 * r["n_compton"] + 5
+
+
 @pytest.mark.parametrize("shape,seed", [((2, 2, 2), 3), ((4, 4, 4), 5), ((3, 5, 7), 8)])
 def test_deposit_log_replay_bit_exact(ctx, shape, seed):
     say(f"log replay {shape}")
@@ -119,9 +138,11 @@ def _pair_histories(gev, oev_by_h, hs):
     return same / len(hs)
 
 
-def test_per_history_event_pairing(ctx):
-    say("per-history pairing water_cbct/4")
-    wl = W.water_cbct(scale=4, n_histories=20_000)
+@pytest.mark.parametrize("name,compton", [("water_cbct", "kn"), ("head", "wh")])
+def test_per_history_event_pairing(ctx, name, compton):
+    say(f"per-history pairing {name}/4 compton={compton}")
+    wl = W.by_name(name, scale=4, n_histories=20_000)
+    wl.compton = compton
     g = gpu_run(ctx, wl, log=(0, 5000, 200_000))
     oc = O.OracleCase(wl)
     r = O.run(oc, threads=8, log_range=(0, 5000), log_cap=200_000)

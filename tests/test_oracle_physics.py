@@ -147,3 +147,55 @@ def test_mean_energy_transfer_fraction_60kev():
     num, _ = integrate.quad(f, -1, 1, epsrel=1e-13)
     den, _ = integrate.quad(_kn_pdf(E), -1, 1, epsrel=1e-13)
     assert num / den == pytest.approx(0.093629, abs=2e-6)
+
+
+# ---------------- bound-electron Compton (Eq. 2 with S) ----------------
+
+def _wh_pdf(name, E):
+    return lambda mu: float(ph.kn_dsigma_dmu(E, mu) * ph.incoherent_sf(name, E, mu))
+
+
+def test_wh_cross_section_quadrature_and_limits():
+    for name in ["water", "cortical_bone"]:
+        z = ph.MATERIALS[name][1]
+        for E in [10.0, 35.0, 90.0]:
+            exact, _ = integrate.quad(lambda m: _wh_pdf(name, E)(m) / z, -1, 1,
+                                      epsabs=0, epsrel=1e-13, limit=400)
+            assert ph.sigma_compton_wh(name, E)[0] == pytest.approx(exact, rel=1e-11)
+        E = np.linspace(5.0, 250.0, 50)
+        ratio = ph.sigma_compton_wh(name, E) / ph.sigma_kn(E)
+        # S <= Z suppresses scattering, less so as the momentum transfer grows
+        assert np.all(ratio < 1.0) and np.all(np.diff(ratio) > 0)
+        assert ratio[-1] > 0.99
+    # S -> Z at large momentum transfer: backscatter matches K-N exactly in the limit
+    assert ph.incoherent_sf("water", 1e5, -1.0) == pytest.approx(7.4, rel=1e-9)
+    assert ph.incoherent_sf("water", 60.0, 1.0) == 0.0
+
+
+@pytest.mark.parametrize("name,E", [("water", 10.0), ("cortical_bone", 30.0),
+                                    ("cortical_bone", 120.0)])
+def test_wh_surface_vs_exact_inverse_cdf(name, E):
+    """S rises from 0 to Z_eff within 1 - mu ~ 2 x_b^2 (hc/E)^2 of the forward
+    direction, a few mu cells at high E, so the trapezoid CDF error is larger
+    than for K-N; it must still fall as h^2 when the mu grid is refined."""
+    j = int(round(E - W.E0_KEV))
+    idx = np.arange(1, W.N_ZETA - 1, 5)
+    exact = _exact_quantile(_wh_pdf(name, E), idx / (W.N_ZETA - 1))
+    errs = []
+    for n_mu in [W.N_MU_COMPTON, 2 * W.N_MU_COMPTON - 1]:
+        S = O.build_surface(ph.wh_compton_pdf_table(name, W.e_nodes(), n_mu), W.N_ZETA)
+        assert np.all(np.diff(S[j]) >= 0)
+        errs.append(np.max(np.abs(S[j, idx] - exact)))
+    assert errs[0] < 5e-5
+    assert errs[1] < errs[0] / 3.0 or errs[0] < 2e-6
+
+
+@pytest.mark.parametrize("name,E", [("water", 20.0), ("cortical_bone", 60.0),
+                                    ("cortical_bone", 45.5)])
+def test_wh_sampling_chi2(name, E):
+    """1e6 samples from a per-material C surface vs K-N x S, and a check that
+    the test separates it from the free-electron law at the same energy."""
+    S = O.build_surface(ph.wh_compton_pdf_table(name, W.e_nodes(), W.N_MU_COMPTON), W.N_ZETA)
+    mu = O.sample_surface(S, E, np.random.default_rng(int(E * 7)).random(1_000_000))
+    assert _chi2_sampled(mu, _wh_pdf(name, E)) > 1e-3
+    assert _chi2_sampled(mu, _kn_pdf(E)) < 1e-6

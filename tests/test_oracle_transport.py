@@ -389,3 +389,64 @@ def test_rotation_deflection_and_azimuth(d):
     a1 = O.rotate(d, 0.3, 0.4)
     a2 = O.rotate(d, 0.3, 0.4 + np.pi / 2)
     assert abs(((a1 - (a1 @ d) * d) @ (a2 - (a2 @ d) * d))) < max(tol, 1e-12)
+
+
+# ---------------- P9: per-material Compton surfaces ----------------
+
+def test_per_material_compton_surface_selects_voxel_material():
+    """A stack of C surfaces is indexed by the material of the interaction
+    voxel: a phantom made only of material 1 with the stack [K-N, bone] must
+    reproduce, bit for bit, the run with the bone surface shared by all."""
+    wl = random_phantom((4, 5, 6), 2, seed=21, n_hist=20_000)
+    wl.mat[:] = 1
+    wl.compton = "wh"
+    kn = O.build_surface(ph.kn_pdf_table(W.e_nodes(), W.N_MU_COMPTON), W.N_ZETA)
+    bone = O.build_surface(ph.wh_compton_pdf_table("cortical_bone", W.e_nodes(),
+                                                   W.N_MU_COMPTON), W.N_ZETA)
+    mu_rho = wl.mu_rho()
+    r_stack = O.run(O.OracleCase(wl, comp_surf=np.stack([kn, bone]), mu_rho=mu_rho),
+                    threads=THREADS)
+    wl.compton = "kn"         # shared-surface mode, same attenuation table
+    r_shared = O.run(O.OracleCase(wl, comp_surf=bone, mu_rho=mu_rho), threads=THREADS)
+    r_wrong = O.run(O.OracleCase(wl, comp_surf=kn, mu_rho=mu_rho), threads=THREADS)
+    assert np.array_equal(r_stack["s1"], r_shared["s1"])
+    assert r_stack["n_compton"] == r_shared["n_compton"]
+    assert not np.array_equal(r_stack["s1"], r_wrong["s1"])
+
+
+def test_bound_electron_compton_angles_in_transport():
+    """Compton-only slab of bone then water, pencil beam at 60 keV: the
+    scattering cosine recovered from each first Compton event's energy
+    transfer follows K-N x S of the material of that voxel."""
+    wl = slab_workload([("cortical_bone", 1.85, 6), ("water", 1.0, 12)], e_kev=60.0,
+                       n_hist=300_000, seed=23, nxy=8, dz=0.25)
+    wl.compton = "wh"
+    c = O.OracleCase(wl, mu_rho=_table_only(wl, [1]))
+    r = O.run(c, batches=[wl.n_histories], threads=1, log_range=(0, wl.n_histories),
+              log_cap=4_000_000)
+    ev = r["log"]
+    ev = ev[np.lexsort((ev["seq"], ev["h"]))]
+    first = ev[ev["type"] == O.EV_COMPTON]
+    first = first[np.r_[True, first["h"][1:] != first["h"][:-1]]]
+    E0 = first["e"] + first["E"]
+    assert np.allclose(E0, 60.0, rtol=0, atol=1e-9)
+    mu = 1.0 - (E0 / first["E"] - 1.0) * ph.ME_C2_KEV / E0
+    iz = first["vox"] // 64
+    for name, sel in [("cortical_bone", iz < 6), ("water", iz >= 6)]:
+        m = np.clip(mu[sel], -1.0, 1.0)
+        assert m.size > 50_000
+        p_right = _chi2_mu(m, lambda x: float(ph.kn_dsigma_dmu(60.0, x)
+                                              * ph.incoherent_sf(name, 60.0, x)))
+        p_kn = _chi2_mu(m, lambda x: float(ph.kn_dsigma_dmu(60.0, x)))
+        assert p_right > 1e-3 and p_kn < 1e-6, (name, p_right, p_kn)
+
+
+def _chi2_mu(mu, pdf, nbins=50):
+    from scipy import integrate, optimize
+    Z, _ = integrate.quad(pdf, -1, 1, epsrel=1e-12, limit=400)
+    cdf = lambda m: integrate.quad(pdf, -1, m, epsrel=1e-12, limit=400)[0] / Z
+    edges = [optimize.brentq(lambda m: cdf(m) - z, -1, 1, xtol=1e-13)
+             for z in np.arange(1, nbins) / nbins]
+    n, _ = np.histogram(mu, bins=np.concatenate([[-1.0], edges, [1.0]]))
+    e = mu.size / nbins
+    return stats.chi2.sf(((n - e) ** 2 / e).sum(), nbins - 1)
