@@ -118,6 +118,96 @@ def batched_leg(ctx, L, W, Case, tuning, torch, hist_scale):
                 identical_to_plain=bool(same))
 
 
+def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
+                batch: int = 10_000_000, max_h: int = 300_000_000_000):
+    """Poisson stream of run-to-1%-sigma requests from the batched case
+    distribution.  Baseline: the same requests run one at a time in arrival
+    order (FIFO), latencies from the measured service times and the trace.
+    Served: the continuous-batching server fed in real time."""
+    import threading
+
+    import numpy as np
+
+    from paper_1109_3266_amd.session import Case, Inputs, grid, params
+
+    arrivals, seeds = W.serving_trace(200, rate_hz, 5005)
+    arrivals = arrivals[:n_req]
+    log(f"serving: generating {n_req} requests")
+    wls = [W.serving_request(seeds[i], i) for i in range(n_req)]
+    service, hist_plain, ref = [], 0, {}
+    for i, wl in enumerate(wls):
+        with Case(ctx, wl) as c:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L.ctd_run_to_sigma(ctx, c.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, batch, max_h)
+            torch.cuda.synchronize()
+            service.append(time.perf_counter() - t0)
+            hist_plain += L.ctd_read_stats(ctx, c.cs).n_histories
+            if i < 3:
+                ref[i] = c.tally()[0]
+    end, lat_plain = 0.0, []
+    for a, sv_t in zip(arrivals, service):
+        end = max(end, a) + sv_t
+        lat_plain.append(end - a)
+    makespan_plain = end - arrivals[0]
+    log(f"serving: FIFO plain p50 {np.percentile(lat_plain, 50):.2f} s")
+
+    cfg = L.ctd_server_config()
+    cfg.hbm_budget_bytes = 64 << 30
+    cfg.batch_histories = batch
+    cfg.max_histories = max_h
+    cfg.dose_frac = 0.5
+    cfg.sigma_kind = L.CTD_SIGMA_LOCAL
+    cfg.max_active = 64
+    sv = L.ctd_server_start(0, cfg)
+    inputs = [Inputs(ctx, wl) for wl in wls]
+    try:
+        for i, wl in enumerate(wls):
+            L.ctd_server_add_phantom(sv, i, grid(wl), wl.mat, wl.rho)
+        tickets = [None] * n_req
+        t_base = L.ctd_server_now(sv) + 0.05
+
+        def feed():
+            for i in range(n_req):
+                while L.ctd_server_now(sv) < t_base + arrivals[i]:
+                    time.sleep(0.001)
+                tickets[i] = L.ctd_server_submit(sv, i, inputs[i].ms, inputs[i].sp,
+                                                 inputs[i].geo, params(wls[i]), 0.01)
+
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        infos = [L.ctd_server_wait(sv, t)[1] for t in tickets]
+        same = all(np.array_equal(ref[i], L.ctd_server_read_tally(sv, tickets[i],
+                                                                  wls[i].n_voxels)[0])
+                   for i in ref)
+        st = L.ctd_server_read_stats(sv)
+    finally:
+        L.ctd_server_stop(sv)
+        for inp in inputs:
+            inp.close()
+    lat = [x.t_done - x.t_submit for x in infos]
+    hist = sum(x.histories for x in infos)
+    makespan = max(x.t_done for x in infos) - min(x.t_submit for x in infos)
+    service_rate = n_req / sum(service)
+    log(f"serving: served p50 {np.percentile(lat, 50):.2f} s, {hist / makespan:.4g} hist/s")
+    return dict(requests=n_req, arrival_rate_hz=rate_hz, sigma_target=0.01,
+                batch_histories=batch,
+                p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                histories_per_s=hist / makespan,
+                plain_fifo_p50_s=float(np.percentile(lat_plain, 50)),
+                plain_fifo_p99_s=float(np.percentile(lat_plain, 99)),
+                plain_histories_per_s=hist_plain / makespan_plain,
+                mean_service_s=float(np.mean(service)),
+                single_gpu_service_rate_hz=service_rate,
+                queue_stable=bool(service_rate > rate_hz),
+                note=("offered load exceeds one GPU (service rate < arrival rate): the queue "
+                      "is unstable; latencies are for this finite trace, not a steady state")
+                if service_rate <= rate_hz else "",
+                identical_to_plain=bool(same), rounds=st.rounds,
+                phantom_loads=st.phantom_loads)
+
+
 def calibrate_copy():
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -140,6 +230,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-histories", type=int, default=None)
     ap.add_argument("--batched-scale", type=float, default=1.0)
+    ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -260,6 +351,8 @@ def main():
         c2.close()
         log(f"time to 1% sigma {tts:.2f} s ({s2.n_histories:.3g} histories)")
         out["batched"] = batched_leg(ctx, L, W, Case, tuning, torch, args.batched_scale)
+        if args.serving_requests > 0:
+            out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests)
 
     if not args.no_cpu:
         log("cpu baseline")
