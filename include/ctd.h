@@ -82,18 +82,36 @@ typedef struct {
   int32_t ne, reserved;
 } ctd_egrid;
 
-/* Scan geometry (Sec. 2.2.6).  PENCIL: a fixed point src and direction dir.
- * CONE: point source on the circle iso + sad*(sin phi, cos phi, 0), aimed at
- * the field rectangle [a0,a1] x [b0,b1] (cm) spanned at the isocentre by
- * e_lat = (cos phi, -sin phi, 0) and e_z; phi = phi0 + p*arc/n_proj for a
- * projection p drawn uniformly (n_proj > 0), or phi0 + u*arc (n_proj = 0,
- * continuous t). */
+/* Scan geometry (Sec. 2.2.6 source trajectory r(t); the CT use of the
+ * method, Sec. 1 and 4, adds table travel).  PENCIL: a fixed point src and
+ * direction dir.  CONE: point source at
+ *   iso + sad*(sin phi, cos phi, 0) + (0, 0, z_feed*(phi - phi0)/360),
+ * aimed at the field rectangle [a0,a1] x [b0,b1] (cm) spanned by
+ * e_lat = (cos phi, -sin phi, 0) and e_z around the point of the axis at the
+ * source's height; phi = phi0 + p*arc/n_proj for a projection p drawn
+ * uniformly (n_proj > 0), or phi0 + u*arc (n_proj = 0, continuous t).
+ * z_feed = 0 is the circular (CBCT) orbit; z_feed != 0 with arc spanning
+ * several turns is a helical CT scan (pitch = z_feed / (b1 - b0) at the
+ * isocentre). */
 typedef struct {
   int32_t kind, n_proj;
   double src[3], dir[3];
   double sad, iso[3];
   double a0, a1, b0, b1;
   double phi0_deg, arc_deg;
+  double z_feed;            /* cm of travel along z per 360 deg */
+  /* Fluence map (Sec. 2.2.4): the field rectangle split into na x nb equal
+   * beamlets, beamlet I = ib*na + ia covering [a0 + ia*da, a0 + (ia+1)*da) x
+   * [b0 + ib*db, ...), da = (a1-a0)/na, db = (b1-b0)/nb.  A source photon
+   * comes from beamlet I with probability f_I / sum f and is uniform inside
+   * it.  fluence = NULL (na = nb = 0) is the uniform field.  The map is read
+   * during ctd_geometry_set only (copied).  The beamlet is drawn from the
+   * first uniform of the history's second source block (Philox counter
+   * (0, h_lo, h_hi, 1)) as the smallest I with C_I > u*F, C_I the FP64
+   * running sum of f in index order and F = C_{N-1}; the decision is exact
+   * in FP64.  CONE only. */
+  int32_t fluence_na, fluence_nb;
+  const float *fluence;     /* [nb][na], f_I >= 0 and finite, sum > 0 */
 } ctd_geom;
 
 typedef struct {

@@ -66,6 +66,9 @@ typedef struct {
   double e_cut;             /* keV */
   uint64_t seed;
   int32_t comp_per_mat, pad_c;  /* 1: one Compton surface per material (Eq. 2 with S) */
+  double z_feed;            /* cone source: travel along z per 360 deg (helical CT) */
+  int32_t fl_na, fl_nb;     /* fluence map beamlets along a and b (0: uniform field) */
+  const double *fl_cdf;     /* [fl_na*fl_nb] running sums of the map intensities */
 } or_case;
 
 typedef struct {
@@ -120,13 +123,18 @@ static double unif(uint32_t r) { return (double)(2u * (r >> 9) + 1u) * (1.0 / Q_
 
 double or_uniform(uint32_t r) { return unif(r); }
 
-static void block(const or_case *c, uint64_t h, uint32_t k, double u[4]) {
-  uint32_t ctr[4] = {k, (uint32_t)h, (uint32_t)(h >> 32), 0u};
+/* Four uniforms of history h: counter (k, h_lo, h_hi, s); k = 0 is the
+ * source, k >= 1 the k-th transport step; s = 1 only for the source's second
+ * block (fluence-map beamlet). */
+static void block_s(const or_case *c, uint64_t h, uint32_t k, uint32_t s, double u[4]) {
+  uint32_t ctr[4] = {k, (uint32_t)h, (uint32_t)(h >> 32), s};
   uint32_t key[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
   uint32_t r[4];
   philox4x32_10(ctr, key, r);
   for (int i = 0; i < 4; ++i) u[i] = unif(r[i]);
 }
+
+static void block(const or_case *c, uint64_t h, uint32_t k, double u[4]) { block_s(c, h, k, 0u, u); }
 
 /* ---------------- Tables: linear interpolation (Sec. 2.2.7 (3)) ---------------- */
 
@@ -285,31 +293,61 @@ static void escape(tally_t *t, double E, int scattered) {
 }
 
 /* Source photon for history h drawn from spectrum bin j (Sec. 2.2.5-2.2.6). */
-static void source(const or_case *c, uint64_t h, int j, double x[3], double d[3], double *E) {
+/* Fluence map (Sec. 2.2.4): beamlet I is drawn with probability f_I / F, by
+ * inverse CDF: the smallest I whose running sum C_I exceeds u F. */
+static int beamlet_of(const or_case *c, double u) {
+  int n = c->fl_na * c->fl_nb;
+  double x = u * c->fl_cdf[n - 1];
+  int lo = 0, hi = n - 1;   /* C_{n-1} = F > x, so the answer is in [lo, hi] */
+  while (lo < hi) {
+    int mid = lo + (hi - lo) / 2;
+    if (c->fl_cdf[mid] > x) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+static void source(const or_case *c, uint64_t h, int j, double x[3], double d[3], double *E,
+                   int *beamlet) {
   double u[4];
   block(c, h, 0u, u);
+  *beamlet = -1;
   *E = c->bin_lo[j] + u[0] * c->bin_width;
   if (c->kind == 0) {
     double n = sqrt(c->dir[0] * c->dir[0] + c->dir[1] * c->dir[1] + c->dir[2] * c->dir[2]);
     for (int a = 0; a < 3; ++a) { x[a] = c->src[a]; d[a] = c->dir[a] / n; }
     return;
   }
-  /* circular trajectory r(t) = iso + R (sin wt, cos wt, 0) at a projection angle */
-  double phi_deg;
+  /* trajectory r(t) = iso + R (sin wt, cos wt, 0) + (0, 0, feed * wt / 2pi):
+   * a circle when feed = 0, a helix otherwise; t at a projection angle */
+  double swept_deg;
   if (c->nproj > 0) {
     double p = floor(u[1] * (double)c->nproj);
     if (p > (double)(c->nproj - 1)) p = (double)(c->nproj - 1);
-    phi_deg = c->phi0_deg + p * c->arc_deg / (double)c->nproj;
+    swept_deg = p * c->arc_deg / (double)c->nproj;
   } else {
-    phi_deg = c->phi0_deg + u[1] * c->arc_deg;
+    swept_deg = u[1] * c->arc_deg;
   }
-  double phi = phi_deg * DEG2RAD;
+  double phi = (c->phi0_deg + swept_deg) * DEG2RAD;
   double sp = sin(phi), cp = cos(phi);
-  double S[3] = {c->iso[0] + c->sad * sp, c->iso[1] + c->sad * cp, c->iso[2]};
-  double a = c->a0 + u[2] * (c->a1 - c->a0);
-  double b = c->b0 + u[3] * (c->b1 - c->b0);
-  /* point on the field rectangle at the isocentre plane: iso + a e_lat + b e_z */
-  double P[3] = {c->iso[0] + a * cp, c->iso[1] - a * sp, c->iso[2] + b};
+  double zs = c->iso[2] + c->z_feed * swept_deg / 360.0;
+  double S[3] = {c->iso[0] + c->sad * sp, c->iso[1] + c->sad * cp, zs};
+  double a, b;
+  if (c->fl_na > 0) {
+    double v[4];
+    block_s(c, h, 0u, 1u, v);
+    int I = beamlet_of(c, v[0]);
+    int ia = I % c->fl_na, ib = I / c->fl_na;
+    /* uniform inside the beamlet */
+    a = c->a0 + (ia + u[2]) * ((c->a1 - c->a0) / c->fl_na);
+    b = c->b0 + (ib + u[3]) * ((c->b1 - c->b0) / c->fl_nb);
+    *beamlet = I;
+  } else {
+    a = c->a0 + u[2] * (c->a1 - c->a0);
+    b = c->b0 + u[3] * (c->b1 - c->b0);
+  }
+  /* point on the field rectangle through the axis at the source's height:
+   * (iso_x, iso_y, zs) + a e_lat + b e_z */
+  double P[3] = {c->iso[0] + a * cp, c->iso[1] - a * sp, zs + b};
   double v[3] = {P[0] - S[0], P[1] - S[1], P[2] - S[2]};
   double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   for (int k = 0; k < 3; ++k) { x[k] = S[k]; d[k] = v[k] / n; }
@@ -359,11 +397,12 @@ static void rotate(double d[3], double mu, double phi) {
 static int history(const or_case *c, uint64_t h, int j, tally_t *t, log_t *L) {
   double x[3], d[3], E;
   uint32_t seq = 0;
-  source(c, h, j, x, d, &E);
+  int beamlet;
+  source(c, h, j, x, d, &E, &beamlet);
   t->n_hist += 1;
   t->e_inc += E;
   t->q_inc += quant(E);
-  log_event(L, h, &seq, 0, EV_SOURCE, -1, E, E);
+  log_event(L, h, &seq, 0, EV_SOURCE, beamlet, E, E);
   if (!enter_box(c, x, d)) {
     t->n_miss += 1;
     escape(t, E, 0);
@@ -627,12 +666,14 @@ int or_sample_surface(const float *S, int ne, int nzeta, double e0, double de, d
 /* out[8] = x, y, z, u, v, w, E, hit (after the slab entry when hit = 1) */
 int or_sample_source(const or_case *c, uint64_t h, int j, double *out) {
   double x[3], d[3], E;
-  source(c, h, j, x, d, &E);
+  int beamlet;
+  source(c, h, j, x, d, &E, &beamlet);
   double y[3] = {x[0], x[1], x[2]};
   int hit = enter_box(c, y, d);
   for (int a = 0; a < 3; ++a) { out[a] = x[a]; out[3 + a] = d[a]; }
   out[6] = E;
   out[7] = (double)hit;
+  out[8] = (double)beamlet;
   return OR_OK;
 }
 

@@ -58,6 +58,8 @@ class Case(C.Structure):
         ("phi0_deg", C.c_double), ("arc_deg", C.c_double),
         ("e_cut", C.c_double), ("seed", C.c_uint64),
         ("comp_per_mat", C.c_int32), ("pad_c", C.c_int32),
+        ("z_feed", C.c_double),
+        ("fl_na", C.c_int32), ("fl_nb", C.c_int32), ("fl_cdf", C.c_void_p),
     ]
 
 
@@ -206,6 +208,16 @@ class OracleCase:
             c.iso[:] = geo["iso"]
             c.a0, c.a1, c.b0, c.b1 = geo["a0"], geo["a1"], geo["b0"], geo["b1"]
             c.phi0_deg, c.arc_deg = geo["phi0_deg"], geo["arc_deg"]
+            c.z_feed = geo.get("feed", 0.0)
+            f = geo.get("fluence")
+            if f is not None:
+                f = np.asarray(f, dtype=np.float32)
+                if f.ndim != 2 or np.any(~np.isfinite(f)) or np.any(f < 0) or f.sum() <= 0:
+                    raise ValueError("fluence map must be [nb][na], finite, >= 0, nonzero")
+                # running sums in beamlet order I = ib * na + ia, FP64 (Sec. 2.2.4)
+                self.fl_cdf = np.cumsum(f.reshape(-1).astype(np.float64))
+                c.fl_nb, c.fl_na = f.shape
+                c.fl_cdf = _p(self.fl_cdf)
             c.nproj = geo["nproj"]
         c.e_cut = wl.e_cut
         c.seed = wl.seed
@@ -320,8 +332,9 @@ def sample_surface(S, E: float, zeta, e0: float = 1.0, de: float = 1.0) -> np.nd
 
 
 def sample_source(case: OracleCase, h: int, j: int) -> np.ndarray:
-    """(x, y, z, u, v, w, E, hit) of the source photon of history h."""
-    out = np.zeros(8)
+    """(x, y, z, u, v, w, E, hit, beamlet) of the source photon of history h
+    (beamlet -1 without a fluence map)."""
+    out = np.zeros(9)
     lib().or_sample_source(C.byref(case.c), int(h), int(j), _p(out))
     return out
 

@@ -400,16 +400,63 @@ extern "C" int32_t ctd_geometry_set(ctd_ctx *ctx, const ctd_geom *g, ctd_geometr
     NEED(ctx, g->sad > 0 && std::isfinite(g->sad), "sad must be positive");
     NEED(ctx, g->a1 > g->a0 && g->b1 > g->b0, "empty field rectangle");
     NEED(ctx, g->n_proj >= 0 && g->n_proj <= (1 << 20), "0 <= n_proj <= 2^20");
+    NEED(ctx, std::isfinite(g->z_feed) && std::isfinite(g->arc_deg) &&
+                  std::isfinite(g->phi0_deg), "non-finite trajectory parameter");
+  }
+  NEED(ctx, g->kind == CTD_GEOM_CONE || g->fluence == nullptr,
+       "a fluence map needs the cone source");
+  const bool has_map = g->fluence != nullptr;
+  if (has_map) {
+    NEED(ctx, g->fluence_na > 0 && g->fluence_nb > 0 &&
+                  (int64_t)g->fluence_na * g->fluence_nb <= (1 << 24),
+         "fluence map needs 1 <= na*nb <= 2^24 beamlets");
+  }
+  std::vector<double> cdf;
+  if (has_map) {
+    // running sums in beamlet order, FP64 (Sec. 2.2.4: P(I) = f_I / sum f)
+    const int64_t n = (int64_t)g->fluence_na * g->fluence_nb;
+    cdf.resize((size_t)n);
+    double run = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const float f = g->fluence[i];
+      NEED(ctx, std::isfinite(f) && f >= 0.0f, "fluence[%lld] = %g is not a finite value >= 0",
+           (long long)i, (double)f);
+      run += (double)f;
+      cdf[(size_t)i] = run;
+    }
+    NEED(ctx, run > 0.0, "fluence map sums to zero");
   }
   ctd_geometry *geo = new (std::nothrow) ctd_geometry();
   if (!geo) return CTD_ENOMEM;
   geo->g = *g;
+  geo->g.fluence = nullptr;   // the caller's buffer is not kept
+  if (has_map) {
+    // guide table over 2^gbits >= N equal slices of [0, F): entry k is the
+    // first beamlet whose running sum exceeds (k / 2^gbits) F, a lower bound
+    // of the answer for every u in slice k since k / 2^gbits <= u exactly.
+    const int64_t n = (int64_t)cdf.size();
+    int gbits = 0;
+    while ((int64_t(1) << gbits) < n) ++gbits;
+    const int64_t G = int64_t(1) << gbits;
+    const double F = cdf.back();
+    geo->fl_guide.resize((size_t)G);
+    int64_t I = 0;
+    for (int64_t k = 0; k < G; ++k) {
+      const double t = ((double)k / (double)G) * F;
+      while (I < n - 1 && cdf[(size_t)I] <= t) ++I;
+      geo->fl_guide[(size_t)k] = (int32_t)I;
+    }
+    geo->fl_gbits = gbits;
+    geo->fl_cdf = std::move(cdf);
+  }
   if (g->kind == CTD_GEOM_CONE && g->n_proj > 0) {
     geo->proj_sc.resize((size_t)g->n_proj);
     const double d2r = 0.017453292519943295769236907684886;
     for (int p = 0; p < g->n_proj; ++p) {
-      const double phi = (g->phi0_deg + (double)p * g->arc_deg / (double)g->n_proj) * d2r;
-      geo->proj_sc[p] = make_float2((float)std::sin(phi), (float)std::cos(phi));
+      const double turn_deg = (double)p * g->arc_deg / (double)g->n_proj;
+      const double phi = (g->phi0_deg + turn_deg) * d2r;
+      geo->proj_sc[p] = make_float4((float)std::sin(phi), (float)std::cos(phi),
+                                    (float)(g->z_feed * turn_deg / 360.0), 0.0f);
     }
   }
   *out = geo;
@@ -500,14 +547,23 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
       (e = hipMalloc(&cs->d_bin_lo, 4 * blo.size())) != hipSuccess)
     return cleanup(hip_err(ctx, e, "case alloc"));
   if (!geo->proj_sc.empty() &&
-      (e = hipMalloc(&cs->d_proj, sizeof(float2) * geo->proj_sc.size())) != hipSuccess)
+      (e = hipMalloc(&cs->d_proj, sizeof(float4) * geo->proj_sc.size())) != hipSuccess)
     return cleanup(hip_err(ctx, e, "case alloc"));
+  if (!geo->fl_cdf.empty() &&
+      ((e = hipMalloc(&cs->d_fl_cdf, sizeof(double) * geo->fl_cdf.size())) != hipSuccess ||
+       (e = hipMalloc(&cs->d_fl_guide, sizeof(int32_t) * geo->fl_guide.size())) != hipSuccess ||
+       (e = hipMemcpy(cs->d_fl_cdf, geo->fl_cdf.data(), sizeof(double) * geo->fl_cdf.size(),
+                      hipMemcpyHostToDevice)) != hipSuccess ||
+       (e = hipMemcpy(cs->d_fl_guide, geo->fl_guide.data(),
+                      sizeof(int32_t) * geo->fl_guide.size(), hipMemcpyHostToDevice)) !=
+           hipSuccess))
+    return cleanup(hip_err(ctx, e, "fluence map upload"));
   if ((e = hipMemcpy(cs->d_mu_max, cs->mu_max.data(), 4 * eg.ne, hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (e = hipMemcpy(cs->d_bin_lo, blo.data(), 4 * blo.size(), hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (cs->d_proj && (e = hipMemcpy(cs->d_proj, geo->proj_sc.data(),
-                                    sizeof(float2) * geo->proj_sc.size(),
+                                    sizeof(float4) * geo->proj_sc.size(),
                                     hipMemcpyHostToDevice)) != hipSuccess))
     return cleanup(hip_err(ctx, e, "case upload"));
   if (launch_zero(cs->d_tally, 8 * V, ctx->stream) || launch_zero(cs->d_s1, 8 * V, ctx->stream) ||
@@ -580,7 +636,19 @@ void ctd::fill_desc(ctd_case *cs) {
   d.b1 = (float)G.b1;
   d.phi0_turns = (float)(G.phi0_deg / 360.0);
   d.arc_turns = (float)(G.arc_deg / 360.0);
+  d.z_feed = (float)G.z_feed;
   d.proj_sc = cs->d_proj;
+  const ctd_geometry *geo = cs->geo;
+  d.fl_n = (int32_t)geo->fl_cdf.size();
+  if (d.fl_n > 0) {
+    d.fl_na = G.fluence_na;
+    d.fl_gbits = geo->fl_gbits;
+    d.fl_da = (float)((G.a1 - G.a0) / G.fluence_na);
+    d.fl_db = (float)((G.b1 - G.b0) / G.fluence_nb);
+    d.fl_total = geo->fl_cdf.back();
+  }
+  d.fl_cdf = cs->d_fl_cdf;
+  d.fl_guide = cs->d_fl_guide;
   d.key0 = (uint32_t)cs->p.seed;
   d.key1 = (uint32_t)(cs->p.seed >> 32);
   d.tally = cs->d_tally;
@@ -603,6 +671,8 @@ void ctd::free_case_buffers(ctd_case *cs) {
   dfree(cs->d_mu_max);
   dfree(cs->d_bin_lo);
   dfree(cs->d_proj);
+  dfree(cs->d_fl_cdf);
+  dfree(cs->d_fl_guide);
   dfree(cs->d_log);
   dfree(cs->d_log_n);
   for (auto &t : cs->timing) {
@@ -688,8 +758,9 @@ int ctd::ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies) {
   return upload_desc(ctx, cs);
 }
 
-uint64_t ctd::case_footprint(int64_t V) {
-  return (uint64_t)V * 32 + 8 * kAccWords + sizeof(CaseDev) + 65536;
+uint64_t ctd::case_footprint(int64_t V, int64_t n_proj, int tally_copies) {
+  return (uint64_t)V * (24 + 8 * (uint64_t)tally_copies) + 8 * kAccWords + sizeof(CaseDev) +
+         sizeof(float4) * (uint64_t)n_proj + 65536;
 }
 
 extern "C" int32_t ctd_set_tuning(ctd_ctx *ctx, ctd_case *cs, const ctd_tuning *t) {

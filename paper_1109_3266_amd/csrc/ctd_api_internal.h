@@ -75,7 +75,10 @@ struct ctd_spectrum {
 
 struct ctd_geometry {
   ctd_geom g{};
-  std::vector<float2> proj_sc;
+  std::vector<float4> proj_sc;   // per projection (sin phi, cos phi, z offset, 0)
+  std::vector<double> fl_cdf;    // fluence map running sums C_I (empty: uniform field)
+  std::vector<int32_t> fl_guide; // [2^fl_gbits] first beamlet with C_I > k F / 2^gbits
+  int32_t fl_gbits = 0;
   std::atomic<int> refs{0};
 };
 
@@ -93,7 +96,9 @@ struct ctd_case {
   ctd::CaseDev *d_desc = nullptr;
   float *d_mu_max = nullptr;
   float *d_bin_lo = nullptr;
-  float2 *d_proj = nullptr;
+  float4 *d_proj = nullptr;
+  double *d_fl_cdf = nullptr;
+  int32_t *d_fl_guide = nullptr;
   unsigned long long *d_tally = nullptr;
   int tally_copies = 1;     // 1, or kTallyCopies once tally_mode 1 is selected
   long long *d_s1 = nullptr;
@@ -136,7 +141,8 @@ int run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count);
 // add after `have` batches at sigma-bar `sig` (0 = stop).
 uint64_t sigma_plan(uint64_t have, double sig, double target, uint64_t max_batches);
 int ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies);
-// Device bytes a case over V voxels allocates (tallies, sums, counters).
-uint64_t case_footprint(int64_t V);
+// Device bytes a case over V voxels allocates (batch tally copies, S1/S2
+// sums, counters, projection table).
+uint64_t case_footprint(int64_t V, int64_t n_proj, int tally_copies);
 
 }  // namespace ctd

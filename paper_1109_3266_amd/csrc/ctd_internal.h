@@ -75,8 +75,14 @@ struct CaseDev {
   float src[3], dir[3];
   float iso[3], pad6;
   float a0, a1, b0, b1;
-  float phi0_turns, arc_turns, pad7, pad8;
-  const float2 *proj_sc;       // [nproj] (sin phi_p, cos phi_p)
+  float phi0_turns, arc_turns, z_feed, pad8;   // z_feed: cm per turn
+  const float4 *proj_sc;       // [nproj] (sin phi_p, cos phi_p, z offset of p, 0)
+  // fluence map: fl_n beamlets (0 = uniform field), fl_na along a
+  int32_t fl_n, fl_na, fl_gbits, pad10;
+  float fl_da, fl_db;          // beamlet size at the isocentre (cm)
+  double fl_total;             // F = C_{n-1}
+  const double *fl_cdf;        // [fl_n] running sums of f
+  const int32_t *fl_guide;     // [2^fl_gbits]
   // random stream key
   uint32_t key0, key1;
   // tallies

@@ -37,9 +37,9 @@ namespace ctd {
 
 // ---------------------------------------------------------------- helpers
 
-__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0,
-                                          uint32_t k1) {
-  uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = 0u;
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+  uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
@@ -289,34 +289,54 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
   p.hhi = (uint32_t)(h >> 32);
   p.k = 0;
   p.seq = 0;
-  const uint4 r = philox10(0u, p.hlo, p.hhi, S.key0, S.key1);
+  const uint4 r = philox10(0u, p.hlo, p.hhi, 0u, S.key0, S.key1);
   const float E = fmaf(unif(r.x), G.bin_width, G.bin_lo[j]);
   float sx, sy, sz, dx, dy, dz;
+  int beamlet = -1;
   if (G.kind == CTD_GEOM_PENCIL) {
     sx = G.src[0]; sy = G.src[1]; sz = G.src[2];
     dx = G.dir[0]; dy = G.dir[1]; dz = G.dir[2];
   } else {
-    float sp, cp;
+    float sp, cp, zoff;
     if (G.nproj > 0) {
       // exact in double: 24-bit uniform times an integer < 2^31
       int pi = (int)((double)unif(r.y) * (double)G.nproj);
       pi = min(pi, G.nproj - 1);
-      const float2 sc = G.proj_sc[pi];
+      const float4 sc = G.proj_sc[pi];
       sp = sc.x;
       cp = sc.y;
+      zoff = sc.z;
     } else {
-      const float t = fmaf(unif(r.y), G.arc_turns, G.phi0_turns);
+      const float rel = unif(r.y) * G.arc_turns;     // turns since phi0
+      const float t = rel + G.phi0_turns;
       sp = sin_turns(t);
       cp = cos_turns(t);
+      zoff = G.z_feed * rel;
     }
     sx = fmaf(G.sad, sp, G.iso[0]);
     sy = fmaf(G.sad, cp, G.iso[1]);
-    sz = G.iso[2];
-    const float a = fmaf(unif(r.z), G.a1 - G.a0, G.a0);
-    const float b = fmaf(unif(r.w), G.b1 - G.b0, G.b0);
+    sz = G.iso[2] + zoff;
+    float a, b;
+    if (G.fl_n > 0) {
+      // beamlet I = min{I : C_I > u F}, decided in FP64 (exact inputs: u has
+      // 24 bits, k / 2^gbits <= u exactly, so the guide entry is a lower bound)
+      const uint4 r2 = philox10(0u, p.hlo, p.hhi, 1u, S.key0, S.key1);
+      const double u = (double)unif(r2.x);
+      const double x = u * G.fl_total;
+      int I = G.fl_guide[(int)(u * (double)(1 << G.fl_gbits))];
+      while (I < G.fl_n - 1 && G.fl_cdf[I] <= x) ++I;
+      const int ib = I / G.fl_na;
+      const int ia = I - ib * G.fl_na;
+      a = fmaf((float)ia + unif(r.z), G.fl_da, G.a0);
+      b = fmaf((float)ib + unif(r.w), G.fl_db, G.b0);
+      beamlet = I;
+    } else {
+      a = fmaf(unif(r.z), G.a1 - G.a0, G.a0);
+      b = fmaf(unif(r.w), G.b1 - G.b0, G.b0);
+    }
     const float Px = fmaf(a, cp, G.iso[0]);
     const float Py = fmaf(-a, sp, G.iso[1]);
-    const float Pz = G.iso[2] + b;
+    const float Pz = sz + b;
     const float vx = Px - sx, vy = Py - sy, vz = Pz - sz;
     const float inv = rsqrtf(vx * vx + vy * vy + vz * vz);
     dx = vx * inv; dy = vy * inv; dz = vz * inv;
@@ -324,7 +344,7 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
   c.add(ACC_N_HIST, 1);
   c.add(ACC_Q_INC, (uint32_t)(E * kQScale));
   p.E = E;
-  log_event<LOG>(G, p, 0, -1, E, E);
+  log_event<LOG>(G, p, 0, beamlet, E, E);
   // slab entry into the box [0, n) in voxel units
   const float Sv[3] = {(sx - G.ox) * S.inv_dx, (sy - G.oy) * S.inv_dy, (sz - G.oz) * S.inv_dz};
   const float D[3] = {dx * S.inv_dx, dy * S.inv_dy, dz * S.inv_dz};
@@ -369,7 +389,7 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
     c.add(ACC_N_STEPS, k);
     return false;
   }
-  const uint4 r = philox10(k, p.hlo, p.hhi, S.key0, S.key1);
+  const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
   const float s = -__log2f(unif(r.x)) * p.sc;  // -ln(u) / mu_max
   p.px = fmaf(s, p.ux * S.inv_dx, p.px);
   p.py = fmaf(s, p.uy * S.inv_dy, p.py);

@@ -24,6 +24,8 @@ def _grid(g: dict) -> L.ctd_grid:
 
 
 def _geom(geo: dict) -> L.ctd_geom:
+    """ctd_geom for a geometry dict; a fluence map [nb][na] (key "fluence")
+    is referenced by pointer, so the dict must outlive ctd_geometry_set."""
     g = L.ctd_geom()
     if geo["kind"] == "pencil":
         g.kind = L.CTD_GEOM_PENCIL
@@ -36,6 +38,13 @@ def _geom(geo: dict) -> L.ctd_geom:
         g.iso[:] = geo["iso"]
         g.a0, g.a1, g.b0, g.b1 = geo["a0"], geo["a1"], geo["b0"], geo["b1"]
         g.phi0_deg, g.arc_deg = geo["phi0_deg"], geo["arc_deg"]
+        g.z_feed = geo.get("feed", 0.0)
+        f = geo.get("fluence")
+        if f is not None:
+            f = np.ascontiguousarray(f, dtype=np.float32)
+            g.fluence_nb, g.fluence_na = f.shape
+            g.fluence = f.ctypes.data
+            g._keep = f
     return g
 
 

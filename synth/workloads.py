@@ -173,6 +173,57 @@ def head(n_histories: int = 2_000_000_000, seed: int = 3, gen_seed: int = 3003,
     return Workload("head", g, mat, rho, mats, True, lo, 1.0, w, geo, seed, n_histories)
 
 
+def head_helical(n_histories: int = 1_000_000_000, seed: int = 6, gen_seed: int = 3003,
+                 scale: int = 1) -> Workload:
+    """The synthetic head under a helical CT scan: 120 kVp fan beam of 2 cm
+    collimation at the isocentre (60 cm source-axis distance), pitch 1
+    (2 cm feed per turn), 6 turns from z = -6 cm, 180 projections per turn."""
+    wl = head(n_histories, seed, gen_seed, scale)
+    wl.name = "head_helical"
+    wl.spectrum_lo, wl.spectrum_w = ph.kramers_spectrum(120, 2.0)
+    geo = _cone(60.0, -12.0, 12.0, -1.0, 1.0, 6 * 180, arc_deg=6 * 360.0)
+    geo["iso"] = (0.0, 0.0, -6.0)
+    geo["feed"] = 2.0
+    wl.geometry = geo
+    return wl
+
+
+def bowtie_fluence(na: int, nb: int, half_a: float, half_b: float, gen_seed: int = 7007,
+                   noise: float = 0.01) -> np.ndarray:
+    """Synthetic air-scan fluence [nb][na] behind a full-fan aluminium bow-tie
+    filter: transmission exp(-mu t(a)) with t rising from 0.5 mm at the centre
+    to 12 mm at |a| >= 0.9 half_a (quadratic), mu of Al at 50 keV; a 10 %
+    heel-effect slope along b; +-noise multiplicative seeded noise (an air
+    scan is measured).  Strictly positive."""
+    rng = np.random.default_rng(gen_seed)
+    a = (np.arange(na) + 0.5) / na * 2.0 - 1.0          # in units of half_a
+    b = (np.arange(nb) + 0.5) / nb * 2.0 - 1.0
+    t_cm = 0.05 + (1.2 - 0.05) * np.minimum(1.0, (a / 0.9) ** 2)
+    mu_al = float(ph.mu_rho_total("aluminium", 50.0).item()) * ph.MATERIALS["aluminium"][0]
+    fa = np.exp(-mu_al * t_cm)
+    fb = 1.0 - 0.05 * b
+    f = fb[:, None] * fa[None, :] * (1.0 + noise * np.clip(rng.standard_normal((nb, na)), -3, 3))
+    return f.astype(np.float32)
+
+
+def water_box_bowtie(n_histories: int = 250_000_000, seed: int = 7, scale: int = 1,
+                     na: int = 128, nb: int = 96) -> Workload:
+    """Water cube 20 cm on 0.4 cm voxels under a static cone beam at normal
+    incidence (100 cm source-isocentre distance, 26.7 x 20 cm field at the
+    isocentre), 125 kVp with 2 mm Al, bow-tie fluence map of na x nb
+    beamlets; 10 batches, 1 keV cutoff (the shape of the paper's Sec. 3
+    validation case, synthetic fluence)."""
+    n = 50 // scale
+    g = _centered_grid(n, n, n, 0.4 * scale, 0.4 * scale, 0.4 * scale)
+    mat = np.zeros((n, n, n), np.uint8)
+    rho = np.ones((n, n, n), np.float32)
+    lo, w = ph.kramers_spectrum(125, 2.0)
+    geo = _cone(100.0, -13.35, 13.35, -10.0, 10.0, 1, arc_deg=0.0)
+    geo["fluence"] = bowtie_fluence(na, nb, 13.35, 10.0)
+    return Workload("water_box_bowtie", g, mat, rho, ["water"], True, lo, 1.0, w, geo, seed,
+                    n_histories)
+
+
 _C4_EXTRA = ["water", "brain", "lung", "cortical_bone"]
 
 
@@ -231,7 +282,8 @@ def serving_request(req_seed: int, idx: int, size_scale: float = 1.0) -> Workloa
 
 
 def by_name(name: str, **kw) -> Workload:
-    return {"tiny": tiny, "water_cbct": water_cbct, "head": head}[name](**kw)
+    return {"tiny": tiny, "water_cbct": water_cbct, "head": head,
+            "head_helical": head_helical, "water_box_bowtie": water_box_bowtie}[name](**kw)
 
 
 def geometry_turns(geo: dict) -> dict:

@@ -76,6 +76,8 @@ def paired_compare(g, r, min_frac=0.99):
     ("tiny", dict(n_histories=100_000)),
     ("water_cbct", dict(n_histories=200_000, scale=4)),
     ("head", dict(n_histories=200_000, scale=4)),
+    ("head_helical", dict(n_histories=200_000, scale=4)),
+    ("water_box_bowtie", dict(n_histories=200_000, scale=2)),
 ])
 def test_paired_parity(ctx, name, kw):
     say(f"paired parity {name} {kw}")
@@ -110,6 +112,27 @@ def test_paired_parity_bound_electron_compton(ctx, name, kw):
     assert abs(g["st"].n_compton - r["n_compton"]) <= 2e-3 * r["n_compton"] + 5
 
 
+def test_fluence_map_beamlets_bit_exact(ctx):
+    """Every history's beamlet (an integer decided in FP64 on both sides)
+    equals the oracle's, including a map with empty beamlets."""
+    for f in [None, np.array([[1.0, 0.0, 2.0, 0.25], [5.0, 0.5, 0.0, 3.0]], np.float32)]:
+        wl = W.water_box_bowtie(scale=5, n_histories=30_000)
+        if f is not None:
+            wl.geometry["fluence"] = f
+        say(f"fluence beamlets {wl.geometry['fluence'].shape}")
+        g = gpu_run(ctx, wl, log=(0, 30_000, 400_000))
+        r = O.run(O.OracleCase(wl), threads=8, log_range=(0, 30_000), log_cap=400_000)
+        gs = g["log"][g["log"]["type"] == 0]
+        os_ = r["log"][r["log"]["type"] == 0]
+        os_ = os_[np.argsort(os_["h"], kind="stable")]
+        assert np.array_equal(gs["h"], np.arange(30_000))
+        assert np.array_equal(gs["h"], os_["h"])
+        assert np.array_equal(gs["vox"], os_["vox"])
+        assert gs["vox"].min() >= 0
+        if f is not None:
+            assert not np.isin(gs["vox"], [1, 6]).any()
+
+
 @pytest.mark.parametrize("shape,seed", [((2, 2, 2), 3), ((4, 4, 4), 5), ((3, 5, 7), 8)])
 def test_deposit_log_replay_bit_exact(ctx, shape, seed):
     say(f"log replay {shape}")
@@ -138,7 +161,8 @@ def _pair_histories(gev, oev_by_h, hs):
     return same / len(hs)
 
 
-@pytest.mark.parametrize("name,compton", [("water_cbct", "kn"), ("head", "wh")])
+@pytest.mark.parametrize("name,compton", [("water_cbct", "kn"), ("head", "wh"),
+                                           ("head_helical", "kn"), ("water_box_bowtie", "kn")])
 def test_per_history_event_pairing(ctx, name, compton):
     say(f"per-history pairing {name}/4 compton={compton}")
     wl = W.by_name(name, scale=4, n_histories=20_000)
@@ -284,6 +308,21 @@ def test_error_paths(ctx):
             L.ctd_read_dose(ctx, c.cs, c.V)      # no batches folded yet
         c.run(1000)
         assert c.balance().n_histories == 1000
+    # geometry: fluence maps and trajectories
+    from paper_1109_3266_amd.session import _geom
+    bow = W.water_box_bowtie(scale=10)
+    for f in [np.array([[1.0, -1.0]], np.float32), np.zeros((2, 3), np.float32),
+              np.array([[np.inf]], np.float32)]:
+        with pytest.raises(L.CtdError) as e:
+            L.ctd_geometry_set(ctx, _geom(dict(bow.geometry, fluence=f)))
+        assert e.value.code == L.CTD_EINVAL
+    pen = _geom(wl.geometry)
+    keep = np.ones((2, 2), np.float32)
+    pen.fluence_na, pen.fluence_nb, pen.fluence = 2, 2, keep.ctypes.data
+    with pytest.raises(L.CtdError):
+        L.ctd_geometry_set(ctx, pen)
+    with pytest.raises(L.CtdError):
+        L.ctd_geometry_set(ctx, _geom(dict(bow.geometry, feed=float("nan"))))
 
 
 def test_run_to_sigma_and_host_sigma(ctx):

@@ -1,6 +1,7 @@
 """Pins of the oracle's transport (Sec. 2.1 Woodcock tracking and interaction
 sampling; Sec. 2.2.1 batches; Sec. 2.2.5 spectrum stratification; Sec. 2.2.6
 source trajectory) against closed forms, invariances and brute force."""
+from dataclasses import replace as dataclass_replace
 from fractions import Fraction
 
 import numpy as np
@@ -450,3 +451,151 @@ def _chi2_mu(mu, pdf, nbins=50):
     n, _ = np.histogram(mu, bins=np.concatenate([[-1.0], edges, [1.0]]))
     e = mu.size / nbins
     return stats.chi2.sf(((n - e) ** 2 / e).sum(), nbins - 1)
+
+
+# ---------------- P11: helical CT trajectory ----------------
+
+def test_helical_source_on_helix():
+    """Source points lie on the helix iso + R(sin phi, cos phi, 0) +
+    (0, 0, feed (phi - phi0)/360) at one of nproj uniformly drawn angles over
+    several turns, and each ray crosses the field rectangle centred on the
+    axis at the source's height uniformly."""
+    wl = W.head_helical(scale=8)
+    geo = wl.geometry
+    c = O.OracleCase(wl)
+    N = 20_000
+    S = np.array([O.sample_source(c, h, 3) for h in range(N)])
+    iso = np.array(geo["iso"])
+    r = np.hypot(S[:, 0] - iso[0], S[:, 1] - iso[1])
+    assert np.allclose(r, geo["sad"], rtol=1e-12)
+    swept = (S[:, 2] - iso[2]) * 360.0 / geo["feed"]       # degrees since phi0
+    p = np.rint(swept * geo["nproj"] / geo["arc_deg"]).astype(int)
+    assert p.min() >= 0 and p.max() < geo["nproj"]
+    assert np.allclose(swept, p * geo["arc_deg"] / geo["nproj"], atol=1e-9)
+    phi = np.degrees(np.arctan2(S[:, 0] - iso[0], S[:, 1] - iso[1]))
+    dphi = (phi - geo["phi0_deg"] - swept + 180.0) % 360.0 - 180.0
+    assert np.max(np.abs(dphi)) < 1e-9, "angle and height on the same helix"
+    assert stats.chisquare(np.bincount(p, minlength=geo["nproj"])).pvalue > 1e-3
+    ph_ = np.radians(geo["phi0_deg"] + swept)
+    axis = -np.stack([np.sin(ph_), np.cos(ph_), 0 * ph_], 1)
+    centre = np.stack([np.full(N, iso[0]), np.full(N, iso[1]), S[:, 2]], 1)
+    t = -np.einsum("ij,ij->i", S[:, :3] - centre, axis) / np.einsum("ij,ij->i", S[:, 3:6], axis)
+    P = S[:, :3] + t[:, None] * S[:, 3:6] - centre
+    elat = np.stack([np.cos(ph_), -np.sin(ph_), 0 * ph_], 1)
+    a = np.einsum("ij,ij->i", P, elat)
+    assert stats.kstest((a - geo["a0"]) / (geo["a1"] - geo["a0"]), "uniform").pvalue > 1e-3
+    assert stats.kstest((P[:, 2] - geo["b0"]) / (geo["b1"] - geo["b0"]),
+                        "uniform").pvalue > 1e-3
+
+
+def test_helical_history_equals_circular_with_shifted_isocentre():
+    """A helical history whose projection is p is the history of a circular
+    scan whose isocentre sits at the helix height of p: identical events."""
+    wl = W.head_helical(scale=8, n_histories=1000)
+    geo = dict(wl.geometry)
+    hel = O.OracleCase(wl)
+    nproj, arc, feed = geo["nproj"], geo["arc_deg"], geo["feed"]
+    checked = 0
+    for h in range(0, 400, 7):
+        x = O.sample_source(hel, h, 5)
+        swept = (x[2] - geo["iso"][2]) * 360.0 / feed
+        p = int(round(swept * nproj / arc))
+        sw = p * arc / nproj
+        circ = dict(geo, feed=0.0, iso=(geo["iso"][0], geo["iso"][1],
+                                        geo["iso"][2] + feed * sw / 360.0))
+        wl.geometry = circ
+        cc = O.OracleCase(wl)
+        wl.geometry = geo
+        a = O.history(hel, h, 5)
+        b = O.history(cc, h, 5)
+        assert np.array_equal(O.sample_source(cc, h, 5), x)
+        assert a.tobytes() == b.tobytes()
+        checked += len(a)
+    assert checked > 100
+
+
+# ---------------- P12: fluence-map source (Sec. 2.2.4) ----------------
+
+def _field_coords(S, geo):
+    """(a, b) where each source ray crosses the field rectangle (static cone
+    source at phi0, circular orbit)."""
+    phi = np.radians(geo["phi0_deg"])
+    iso = np.array(geo["iso"])
+    axis = -np.array([np.sin(phi), np.cos(phi), 0.0])
+    t = -((S[:, :3] - iso) @ axis) / (S[:, 3:6] @ axis)
+    P = S[:, :3] + t[:, None] * S[:, 3:6] - iso
+    return P @ np.array([np.cos(phi), -np.sin(phi), 0.0]), P[:, 2]
+
+
+def test_fluence_map_beamlet_probabilities_and_positions():
+    """Beamlets are drawn with probability f_I / sum f (chi-square), the
+    logged beamlet is the one that contains the ray's crossing of the field,
+    and the crossing is uniform inside its beamlet."""
+    wl = W.water_box_bowtie(scale=5, na=16, nb=12)
+    geo = wl.geometry
+    f = geo["fluence"].astype(np.float64)
+    c = O.OracleCase(wl)
+    N = 120_000
+    S = np.array([O.sample_source(c, h, 0) for h in range(N)])
+    I = S[:, 8].astype(int)
+    cnt = np.bincount(I, minlength=f.size)
+    exp = N * f.reshape(-1) / f.sum()
+    assert stats.chisquare(cnt, exp).pvalue > 1e-3
+    a, b = _field_coords(S, geo)
+    na, nb = f.shape[1], f.shape[0]
+    fa = (a - geo["a0"]) / (geo["a1"] - geo["a0"]) * na
+    fb = (b - geo["b0"]) / (geo["b1"] - geo["b0"]) * nb
+    ia, ib = np.floor(fa + 1e-9).astype(int), np.floor(fb + 1e-9).astype(int)
+    inside = (np.abs(fa - np.rint(fa)) > 1e-7) & (np.abs(fb - np.rint(fb)) > 1e-7)
+    assert np.array_equal((ib * na + ia)[inside], I[inside])
+    assert stats.kstest((fa - ia)[inside], "uniform").pvalue > 1e-3
+    assert stats.kstest((fb - ib)[inside], "uniform").pvalue > 1e-3
+
+
+def test_fluence_map_zero_beamlets_and_brute_force_tiny_map():
+    """A 3 x 2 map with two empty beamlets: exact multinomial frequencies,
+    and an empty beamlet is never drawn."""
+    wl = W.water_box_bowtie(scale=10)
+    f = np.array([[1.0, 0.0, 2.0], [5.0, 0.5, 0.0]], np.float32)
+    wl.geometry["fluence"] = f
+    c = O.OracleCase(wl)
+    N = 60_000
+    I = np.array([O.sample_source(c, h, 0)[8] for h in range(N)]).astype(int)
+    cnt = np.bincount(I, minlength=6)
+    assert cnt[1] == 0 and cnt[5] == 0
+    p = f.reshape(-1).astype(np.float64) / float(f.sum())
+    nz = p > 0
+    assert stats.chisquare(cnt[nz], N * p[nz] / p[nz].sum()).pvalue > 1e-3
+
+
+def test_fluence_map_error_decreases_like_fig5c():
+    """Fig. 5c: e = ||p_f - p_f*|| over beamlets falls as the photon count
+    grows; for exact sampling E[e^2] = sum p (1 - p) / N."""
+    wl = W.water_box_bowtie(scale=10, na=32, nb=24)
+    f = wl.geometry["fluence"].astype(np.float64).reshape(-1)
+    p = f / f.sum()
+    c = O.OracleCase(wl)
+    I = np.array([O.sample_source(c, h, 0)[8] for h in range(200_000)]).astype(int)
+    es = []
+    for n in [2_000, 20_000, 200_000]:
+        q = np.bincount(I[:n], minlength=p.size) / n
+        es.append(np.linalg.norm(q - p))
+        expect = np.sqrt((p * (1 - p)).sum() / n)
+        assert 0.8 * expect < es[-1] < 1.2 * expect, (n, es[-1], expect)
+    assert es[0] > es[1] > es[2]
+
+
+def test_single_beamlet_map_equals_uniform_field():
+    """A 1 x 1 map is the uniform field: identical transport events (the
+    beamlet draw uses its own counter block and perturbs no other draw)."""
+    wl = W.water_box_bowtie(scale=10, n_histories=400)
+    geo = dict(wl.geometry)
+    geo.pop("fluence")
+    plain = O.OracleCase(dataclass_replace(wl, geometry=geo))
+    wl.geometry["fluence"] = np.array([[3.0]], np.float32)
+    one = O.OracleCase(wl)
+    for h in range(0, 400, 13):
+        a, b = O.history(one, h, 0), O.history(plain, h, 0)
+        assert a[0]["vox"] == 0 and b[0]["vox"] == -1
+        a["vox"][0] = -1
+        assert a.tobytes() == b.tobytes()
