@@ -298,6 +298,35 @@ int32_t ctd_read_majorant(ctd_ctx *ctx, ctd_case *cs, float *out);
 int32_t ctd_microbench(ctd_ctx *ctx, int32_t kind, uint64_t bytes, uint64_t ops, double *rate,
                        double *ms);
 
+/* ---------------- dose comparison ----------------
+ * Gamma index (the agreement test of Sec. 3.1, after Low et al. 1998):
+ *   gamma(r) = min_{r'} sqrt((D_ref(r) - D_eval(r'))^2 / dose_tol^2
+ *                            + |r - r'|^2 / dta_cm^2)
+ * for every voxel centre r with D_ref(r) > region_min.  r' runs over the
+ * lattice r + h*(i,j,k), h = dta_cm / substeps, |r' - r| <= gamma_cap*dta_cm,
+ * and D_eval(r') is the trilinear interpolant of D_eval between voxel centres,
+ * clamped to the outermost centres.  Values that would exceed gamma_cap are
+ * reported as gamma_cap.  The paper's test: dose_tol = 0.02 D_max, dta_cm =
+ * 0.2, region_min = 0.2 D_max, pass when gamma < 1. */
+typedef struct {
+  double dose_tol;    /* Delta D, in the arrays' dose units (> 0) */
+  double dta_cm;      /* Delta r (> 0) */
+  double region_min;  /* voxels with D_ref > region_min are evaluated */
+  double gamma_cap;   /* 1 <= gamma_cap <= 4 */
+  int32_t substeps;   /* 1 <= substeps <= 20 */
+  int32_t reserved;
+} ctd_gamma_params;
+
+/* ref, eval: [nz][ny][nx] float doses on grid g, in host (mem = CTD_MEM_HOST)
+ * or device memory (CTD_MEM_DEVICE); read only.  gamma: optional [V] output in
+ * the same memory kind (NULL to skip), -1 outside the evaluated region.
+ * *n_region = evaluated voxels, *n_pass = those with gamma < 1 (decided in
+ * FP64).  Synchronous on the context stream.  CTD_EINVAL on bad parameters or
+ * more than 2^22 lattice offsets. */
+int32_t ctd_gamma(ctd_ctx *ctx, const ctd_grid *g, const float *ref, const float *eval,
+                  int32_t mem, const ctd_gamma_params *p, float *gamma, uint64_t *n_region,
+                  uint64_t *n_pass);
+
 /* ---------------- debug log (tests) ----------------
  * Arm event logging of histories [h0, h0+nh) for the following runs, with
  * room for `capacity` events (0 disarms).  Read them back with

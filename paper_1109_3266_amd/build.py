@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libctd.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["ctd_kernels.hip", "ctd_api.cpp", "ctd_tables.cpp", "ctd_server.cpp"]
+SOURCES = ["ctd_kernels.hip", "ctd_gamma.hip", "ctd_api.cpp", "ctd_tables.cpp", "ctd_server.cpp",
+           "ctd_tools.cpp"]
 
 # packed-fp32 instructions are disabled for all device code; FP contraction
 # off so every launch configuration computes bit-identical float results.

@@ -139,5 +139,11 @@ int launch_sigma(const long long *s1, const unsigned long long *s2, const uint2 
 int launch_microbench(int kind, void *buf_a, void *buf_b, int64_t n, int64_t ops, int grid,
                       void *stream);
 int device_cu_count(int device);
+// Gamma index of ev against ref on an nx*ny*nz grid (ctd_gamma.hip); offs is
+// a device double4 table sorted by distance; gamma may be null; counts[2]
+// (region voxels, passing voxels) are accumulated, not cleared.
+int launch_gamma(const float *ref, const float *ev, int nx, int ny, int nz, const void *offs,
+                 int n_off, double inv_dd2, double region, double cap2, float *gamma,
+                 unsigned long long *counts, void *stream);
 
 }  // namespace ctd

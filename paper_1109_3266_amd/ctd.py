@@ -95,6 +95,11 @@ class ctd_tuning(C.Structure):
                 ("refill_min", C.c_int32), ("chunk", C.c_int32), ("tally_mode", C.c_int32)]
 
 
+class ctd_gamma_params(C.Structure):
+    _fields_ = [("dose_tol", C.c_double), ("dta_cm", C.c_double), ("region_min", C.c_double),
+                ("gamma_cap", C.c_double), ("substeps", C.c_int32), ("reserved", C.c_int32)]
+
+
 class ctd_event(C.Structure):
     _fields_ = [("h", C.c_uint64), ("seq", C.c_uint32), ("k", C.c_uint32), ("type", C.c_int32),
                 ("reserved", C.c_int32), ("vox", C.c_int64), ("e", C.c_float), ("E", C.c_float)]
@@ -160,6 +165,8 @@ _SIGS = {
     "ctd_read_stats": (I32, [P, P, C.POINTER(ctd_stats)]),
     "ctd_read_majorant": (I32, [P, P, P]),
     "ctd_microbench": (I32, [P, I32, U64, U64, C.POINTER(F64), C.POINTER(F64)]),
+    "ctd_gamma": (I32, [P, C.POINTER(ctd_grid), P, P, I32, C.POINTER(ctd_gamma_params), P,
+                        C.POINTER(U64), C.POINTER(U64)]),
     "ctd_debug_deposit_log": (I32, [P, P, U64, U64, U64]),
     "ctd_server_start": (I32, [I32, C.POINTER(ctd_server_config), PP]),
     "ctd_server_last_error": (C.c_char_p, [P]),
@@ -401,6 +408,24 @@ def ctd_microbench(ctx, kind: int, nbytes: int, ops: int = 0):
     check(lib().ctd_microbench(ctx, int(kind), int(nbytes), int(ops), C.byref(r), C.byref(t)),
           ctx)
     return r.value, t.value
+
+
+def ctd_gamma(ctx, grid: ctd_grid, ref, ev, dose_tol: float, dta_cm: float, region_min: float,
+              gamma_cap: float = 2.0, substeps: int = 5, want_gamma: bool = True):
+    """Gamma index of host dose arrays ev against ref on grid: returns
+    (gamma [V] float32 or None, n_region, n_pass)."""
+    r = np.ascontiguousarray(ref, dtype=np.float32)
+    e = np.ascontiguousarray(ev, dtype=np.float32)
+    V = grid.nx * grid.ny * grid.nz
+    if r.size != V or e.size != V:
+        raise ValueError(f"dose arrays must hold {V} voxels")
+    p = ctd_gamma_params(float(dose_tol), float(dta_cm), float(region_min), float(gamma_cap),
+                         int(substeps), 0)
+    g = np.empty(V, np.float32) if want_gamma else None
+    nr, npass = C.c_uint64(), C.c_uint64()
+    check(lib().ctd_gamma(ctx, C.byref(grid), ptr(r), ptr(e), CTD_MEM_HOST, C.byref(p),
+                          ptr(g) if g is not None else None, C.byref(nr), C.byref(npass)), ctx)
+    return g, nr.value, npass.value
 
 
 def ctd_debug_deposit_log(ctx, cs, h0: int, nh: int, capacity: int):

@@ -1,0 +1,91 @@
+"""GPU gamma index (ctd_gamma through the C ABI) against the brute-force FP64
+oracle: element-wise gamma and pass counts on smooth noisy fields over
+ragged and degenerate grids, and the paper's use, the 2 %/2 mm agreement of
+a GPU dose with the oracle's dose of the same problem."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gamma as OG
+from oracle import oracle as O
+from paper_1109_3266_amd import ctd as L
+from paper_1109_3266_amd.session import Case, grid
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    h = L.ctd_create(0)
+    yield h
+    L.ctd_destroy(h)
+
+
+def _g(shape, d):
+    g = L.ctd_grid()
+    g.nz, g.ny, g.nx = shape
+    g.dx, g.dy, g.dz = d
+    return g
+
+
+def _field(shape, seed, noise, bias):
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*[np.linspace(-1, 1, n) for n in shape], indexing="ij")
+    base = np.exp(-(x ** 2 + 0.5 * y ** 2 + 2 * z ** 2)) + 0.3 * np.sin(3 * x + y) + 0.5
+    return base.astype(np.float32), \
+        (base * (1 + bias) + noise * rng.standard_normal(shape)).astype(np.float32)
+
+
+def _compare(ctx, shape, d, ref, ev, **kw):
+    go, nr_o, np_o = OG.gamma_index(ref, ev, d, **kw)
+    gg, nr_g, np_g = L.ctd_gamma(ctx, _g(shape, d), ref, ev, **kw)
+    gg = gg.reshape(shape)
+    assert nr_g == nr_o
+    assert np.allclose(gg, go, rtol=1e-6, atol=1e-6)
+    # near-ties of gamma^2 = 1 may fall either way in a different FP64 order
+    ties = int(np.count_nonzero(np.abs(go ** 2 - 1.0) < 1e-9))
+    assert abs(np_g - np_o) <= ties
+    return nr_o, np_o
+
+
+@pytest.mark.parametrize("shape,d,noise,bias,cap,sub,mixed", [
+    ((11, 17, 23), (0.1, 0.15, 0.2), 0.01, 0.03, 2.0, 5, False),
+    ((7, 9, 1), (0.2, 0.2, 0.2), 0.05, 0.0, 1.0, 4, False),
+    ((1, 1, 37), (0.05, 0.3, 0.3), 0.04, 0.0, 3.0, 6, True),
+    ((5, 33, 65), (0.25, 0.25, 0.1), 0.03, 0.02, 2.0, 8, True),
+])
+def test_gamma_matches_oracle(ctx, shape, d, noise, bias, cap, sub, mixed):
+    say(f"gamma {shape} {d} cap={cap} sub={sub}")
+    ref, ev = _field(shape, 3, noise, bias)
+    dmax = float(ref.max())
+    nr, npass = _compare(ctx, shape, d, ref, ev, dose_tol=0.02 * dmax, dta_cm=0.2,
+                         region_min=0.2 * dmax, gamma_cap=cap, substeps=sub)
+    say(f"  region {nr} pass {npass}")
+    assert 0 < npass <= nr
+    assert (npass < nr) == mixed
+
+
+def test_gamma_gpu_dose_vs_oracle_dose(ctx):
+    """P_gamma (2 %, 2 mm, D > 20 % D_max) of the GPU dose of the bow-tie
+    water box against the oracle's dose of the same histories."""
+    wl = W.water_box_bowtie(scale=2, n_histories=2_000_000)
+    say("gamma of GPU vs oracle dose, water box bow-tie /2")
+    with Case(ctx, wl) as c:
+        c.run(wl.n_histories)
+        dg = c.dose()[0].reshape(wl.rho.shape)
+    oc = O.OracleCase(wl)
+    r = O.run(oc, threads=8)
+    do = O.dose_and_sigma(r, oc, wl.n_histories)[0].reshape(wl.rho.shape)
+    dmax = float(do.max())
+    gg, nr, npass = L.ctd_gamma(ctx, grid(wl), do, dg, 0.02 * dmax, 0.2, 0.2 * dmax)
+    go, nr_o, np_o = OG.gamma_index(do, dg, (wl.grid["dx"],) * 3, 0.02 * dmax, 0.2, 0.2 * dmax)
+    assert nr == nr_o and abs(npass - np_o) <= 1
+    say(f"  P_gamma {npass / nr:.4f} over {nr} voxels")
+    assert npass / nr >= 0.95
