@@ -109,9 +109,19 @@ typedef struct {
    * first uniform of the history's second source block (Philox counter
    * (0, h_lo, h_hi, 1)) as the smallest I with C_I > u*F, C_I the FP64
    * running sum of f in index order and F = C_{N-1}; the decision is exact
-   * in FP64.  CONE only. */
+   * in FP64.  CONE only.
+   * fluence_chains = C > 0 selects Alg. A1 (Metropolis-Hastings) instead:
+   * history h belongs to logical chain h mod C and each chain visits its
+   * histories in increasing h, from a uniformly drawn start (counter
+   * (0, c_lo, c_hi, 2)); the step of history h proposes J = floor(u0 N) and
+   * moves there when u1 * f_{I_last} < f_J (u0, u1 from the second source
+   * block; exact in FP64).  Needs every f_I > 0, and the case's runs to
+   * follow each other in history order (they do: runs continue at the next
+   * id).  Results do not depend on launch configuration. */
   int32_t fluence_na, fluence_nb;
   const float *fluence;     /* [nb][na], f_I >= 0 and finite, sum > 0 */
+  int32_t fluence_chains;   /* 0: exact inverse CDF; 1 .. 2^24: Alg. A1 chains */
+  int32_t reserved_f;
 } ctd_geom;
 
 typedef struct {

@@ -69,6 +69,12 @@ typedef struct {
   double z_feed;            /* cone source: travel along z per 360 deg (helical CT) */
   int32_t fl_na, fl_nb;     /* fluence map beamlets along a and b (0: uniform field) */
   const double *fl_cdf;     /* [fl_na*fl_nb] running sums of the map intensities */
+  /* Alg. A1 (Metropolis-Hastings) instead of the inverse CDF when fl_chains > 0:
+   * beamlet of history h = fl_beam[h - fl_h0], filled by or_mh_fill */
+  int32_t fl_chains, pad_f;
+  const float *fl_f;        /* [fl_na*fl_nb] map intensities */
+  const int32_t *fl_beam;
+  uint64_t fl_h0, fl_nbeam;
 } or_case;
 
 typedef struct {
@@ -306,6 +312,47 @@ static int beamlet_of(const or_case *c, double u) {
   return lo;
 }
 
+/* Alg. A1 on logical chains: history h belongs to chain h mod C and the chain
+ * visits its histories in increasing h.  Each step draws a trial beamlet J
+ * uniformly and zeta from the history's second source block and moves to J
+ * when zeta < f_J / f_{I_last}; the comparison is taken as zeta * f_I < f_J,
+ * exact in FP64 (24-bit operands).  A chain starts (at h = c) from a beamlet
+ * drawn uniformly from the counter (0, c_lo, c_hi, 2). */
+static int mh_initial(const or_case *c, uint64_t chain) {
+  double v[4];
+  uint32_t ctr[4] = {0u, (uint32_t)chain, (uint32_t)(chain >> 32), 2u};
+  uint32_t key[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
+  uint32_t r[4];
+  philox4x32_10(ctr, key, r);
+  for (int i = 0; i < 4; ++i) v[i] = unif(r[i]);
+  return (int)(v[0] * (double)(c->fl_na * c->fl_nb));
+}
+
+/* Advance the chains over histories [h0, h0 + n) in increasing h; state[C]
+ * holds each chain's last beamlet (read for chains already started). */
+int or_mh_fill(const or_case *c, uint64_t h0, uint64_t n, int32_t *state, int32_t *out) {
+  const uint64_t C = (uint64_t)c->fl_chains;
+  const int nf = c->fl_na * c->fl_nb;
+  if (C == 0 || nf <= 0 || !c->fl_f) return OR_EINVAL;
+  for (uint64_t h = h0; h < h0 + n; ++h) {
+    uint64_t chain = h % C;
+    int I = h < C ? mh_initial(c, chain) : state[chain];
+    double v[4];
+    block_s(c, h, 0u, 1u, v);
+    int J = (int)(v[0] * (double)nf);           /* 1. uniform trial beamlet */
+    double zeta = v[1];                         /* 2. */
+    if (zeta * (double)c->fl_f[I] < (double)c->fl_f[J]) I = J;   /* 3. */
+    state[chain] = I;                           /* 5. */
+    out[h - h0] = I;
+  }
+  return OR_OK;
+}
+
+static int beam_ok(const or_case *c, uint64_t h) {
+  return c->fl_chains <= 0 || c->fl_na <= 0 ||
+         (c->fl_beam && h >= c->fl_h0 && h - c->fl_h0 < c->fl_nbeam);
+}
+
 static void source(const or_case *c, uint64_t h, int j, double x[3], double d[3], double *E,
                    int *beamlet) {
   double u[4];
@@ -333,9 +380,14 @@ static void source(const or_case *c, uint64_t h, int j, double x[3], double d[3]
   double S[3] = {c->iso[0] + c->sad * sp, c->iso[1] + c->sad * cp, zs};
   double a, b;
   if (c->fl_na > 0) {
-    double v[4];
-    block_s(c, h, 0u, 1u, v);
-    int I = beamlet_of(c, v[0]);
+    int I;
+    if (c->fl_chains > 0) {
+      I = c->fl_beam[h - c->fl_h0];   /* callers check the range (beam_ok) */
+    } else {
+      double v[4];
+      block_s(c, h, 0u, 1u, v);
+      I = beamlet_of(c, v[0]);
+    }
     int ia = I % c->fl_na, ib = I / c->fl_na;
     /* uniform inside the beamlet */
     a = c->a0 + (ia + u[2]) * ((c->a1 - c->a0) / c->fl_na);
@@ -395,6 +447,7 @@ static void rotate(double d[3], double mu, double phi) {
 }
 
 static int history(const or_case *c, uint64_t h, int j, tally_t *t, log_t *L) {
+  if (!beam_ok(c, h)) return OR_EINVAL;
   double x[3], d[3], E;
   uint32_t seq = 0;
   int beamlet;
@@ -665,6 +718,7 @@ int or_sample_surface(const float *S, int ne, int nzeta, double e0, double de, d
 
 /* out[8] = x, y, z, u, v, w, E, hit (after the slab entry when hit = 1) */
 int or_sample_source(const or_case *c, uint64_t h, int j, double *out) {
+  if (!beam_ok(c, h)) return OR_EINVAL;
   double x[3], d[3], E;
   int beamlet;
   source(c, h, j, x, d, &E, &beamlet);

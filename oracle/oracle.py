@@ -60,6 +60,8 @@ class Case(C.Structure):
         ("comp_per_mat", C.c_int32), ("pad_c", C.c_int32),
         ("z_feed", C.c_double),
         ("fl_na", C.c_int32), ("fl_nb", C.c_int32), ("fl_cdf", C.c_void_p),
+        ("fl_chains", C.c_int32), ("pad_f", C.c_int32), ("fl_f", C.c_void_p),
+        ("fl_beam", C.c_void_p), ("fl_h0", C.c_uint64), ("fl_nbeam", C.c_uint64),
     ]
 
 
@@ -113,6 +115,8 @@ def lib():
                                            C.c_double, C.c_double, C.c_void_p, C.c_int64,
                                            C.c_void_p]
         _lib.or_sample_source.argtypes = [C.POINTER(Case), C.c_uint64, C.c_int, C.c_void_p]
+        _lib.or_mh_fill.argtypes = [C.POINTER(Case), C.c_uint64, C.c_uint64, C.c_void_p,
+                                    C.c_void_p]
         _lib.or_rotate.argtypes = [C.c_void_p, C.c_double, C.c_double]
         _lib.or_rotate.restype = None
         _lib.or_batch_stats.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -218,6 +222,16 @@ class OracleCase:
                 self.fl_cdf = np.cumsum(f.reshape(-1).astype(np.float64))
                 c.fl_nb, c.fl_na = f.shape
                 c.fl_cdf = _p(self.fl_cdf)
+                chains = int(geo.get("fluence_chains", 0))
+                if chains > 0:
+                    # Alg. A1 (Metropolis-Hastings) needs f_I > 0 for every beamlet
+                    if np.any(f <= 0):
+                        raise ValueError("Metropolis-Hastings sampling needs f_I > 0")
+                    self.fl_f = np.ascontiguousarray(f.reshape(-1))
+                    self.mh_state = np.zeros(chains, np.int32)
+                    self.mh_next = 0
+                    c.fl_chains = chains
+                    c.fl_f = _p(self.fl_f)
             c.nproj = geo["nproj"]
         c.e_cut = wl.e_cut
         c.seed = wl.seed
@@ -271,6 +285,11 @@ def run(case: OracleCase, n_histories: int | None = None, n_batches: int | None 
         batches = batch_sizes(n_histories if n_histories is not None else wl.n_histories,
                               n_batches if n_batches is not None else wl.n_batches)
     bs = np.ascontiguousarray(batches, dtype=np.uint64)
+    if case.c.fl_chains > 0:
+        if h0 != case.mh_next:
+            raise ValueError(f"Metropolis-Hastings chains are at history {case.mh_next}, "
+                             f"not {h0}: runs must follow each other in history order")
+        mh_advance(case, int(bs.sum()))
     V = case.n_voxels
     s1 = np.zeros(V, np.int64)
     s2h = np.zeros(V, np.uint64)
@@ -298,6 +317,20 @@ def run(case: OracleCase, n_histories: int | None = None, n_batches: int | None 
         ev = log[:n]
         out["log"] = ev[np.lexsort((ev["seq"], ev["h"]))]
     return out
+
+
+def mh_advance(case: OracleCase, n: int) -> np.ndarray:
+    """Alg. A1: advance the logical chains over the next n histories (in id
+    order) and make their beamlets the ones the source uses; returns them."""
+    out = np.zeros(max(n, 1), np.int32)
+    rc = lib().or_mh_fill(C.byref(case.c), int(case.mh_next), int(n), _p(case.mh_state),
+                          _p(out))
+    if rc != 0:
+        raise RuntimeError(f"or_mh_fill failed: {rc}")
+    case.mh_beam = out
+    case.c.fl_beam, case.c.fl_h0, case.c.fl_nbeam = _p(out), case.mh_next, n
+    case.mh_next += n
+    return out[:n]
 
 
 def history(case: OracleCase, h: int, j: int, cap: int = 100000) -> np.ndarray:
@@ -335,7 +368,9 @@ def sample_source(case: OracleCase, h: int, j: int) -> np.ndarray:
     """(x, y, z, u, v, w, E, hit, beamlet) of the source photon of history h
     (beamlet -1 without a fluence map)."""
     out = np.zeros(9)
-    lib().or_sample_source(C.byref(case.c), int(h), int(j), _p(out))
+    if lib().or_sample_source(C.byref(case.c), int(h), int(j), _p(out)) != 0:
+        raise ValueError(f"no source for history {h} (Metropolis-Hastings beamlets "
+                         "not advanced that far)")
     return out
 
 

@@ -410,6 +410,10 @@ extern "C" int32_t ctd_geometry_set(ctd_ctx *ctx, const ctd_geom *g, ctd_geometr
     NEED(ctx, g->fluence_na > 0 && g->fluence_nb > 0 &&
                   (int64_t)g->fluence_na * g->fluence_nb <= (1 << 24),
          "fluence map needs 1 <= na*nb <= 2^24 beamlets");
+    NEED(ctx, g->fluence_chains >= 0 && g->fluence_chains <= (1 << 24),
+         "0 <= fluence_chains <= 2^24");
+  } else {
+    NEED(ctx, g->fluence_chains == 0, "fluence_chains without a fluence map");
   }
   std::vector<double> cdf;
   if (has_map) {
@@ -421,6 +425,8 @@ extern "C" int32_t ctd_geometry_set(ctd_ctx *ctx, const ctd_geom *g, ctd_geometr
       const float f = g->fluence[i];
       NEED(ctx, std::isfinite(f) && f >= 0.0f, "fluence[%lld] = %g is not a finite value >= 0",
            (long long)i, (double)f);
+      NEED(ctx, g->fluence_chains == 0 || f > 0.0f,
+           "Metropolis-Hastings sampling needs f_I > 0 (fluence[%lld] = 0)", (long long)i);
       run += (double)f;
       cdf[(size_t)i] = run;
     }
@@ -448,6 +454,7 @@ extern "C" int32_t ctd_geometry_set(ctd_ctx *ctx, const ctd_geom *g, ctd_geometr
     }
     geo->fl_gbits = gbits;
     geo->fl_cdf = std::move(cdf);
+    if (g->fluence_chains > 0) geo->fl_f.assign(g->fluence, g->fluence + n);
   }
   if (g->kind == CTD_GEOM_CONE && g->n_proj > 0) {
     geo->proj_sc.resize((size_t)g->n_proj);
@@ -558,6 +565,13 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
                       sizeof(int32_t) * geo->fl_guide.size(), hipMemcpyHostToDevice)) !=
            hipSuccess))
     return cleanup(hip_err(ctx, e, "fluence map upload"));
+  if (!geo->fl_f.empty() &&
+      ((e = hipMalloc(&cs->d_fl_f, sizeof(float) * geo->fl_f.size())) != hipSuccess ||
+       (e = hipMalloc(&cs->d_mh_state, sizeof(int32_t) * (size_t)geo->g.fluence_chains)) !=
+           hipSuccess ||
+       (e = hipMemcpy(cs->d_fl_f, geo->fl_f.data(), sizeof(float) * geo->fl_f.size(),
+                      hipMemcpyHostToDevice)) != hipSuccess))
+    return cleanup(hip_err(ctx, e, "fluence chain upload"));
   if ((e = hipMemcpy(cs->d_mu_max, cs->mu_max.data(), 4 * eg.ne, hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (e = hipMemcpy(cs->d_bin_lo, blo.data(), 4 * blo.size(), hipMemcpyHostToDevice)) !=
@@ -649,6 +663,7 @@ void ctd::fill_desc(ctd_case *cs) {
   }
   d.fl_cdf = cs->d_fl_cdf;
   d.fl_guide = cs->d_fl_guide;
+  d.fl_chains = geo->fl_f.empty() ? 0 : G.fluence_chains;
   d.key0 = (uint32_t)cs->p.seed;
   d.key1 = (uint32_t)(cs->p.seed >> 32);
   d.tally = cs->d_tally;
@@ -673,6 +688,9 @@ void ctd::free_case_buffers(ctd_case *cs) {
   dfree(cs->d_proj);
   dfree(cs->d_fl_cdf);
   dfree(cs->d_fl_guide);
+  dfree(cs->d_fl_f);
+  dfree(cs->d_mh_state);
+  dfree(cs->d_mh_beam);
   dfree(cs->d_log);
   dfree(cs->d_log_n);
   for (auto &t : cs->timing) {
@@ -758,9 +776,26 @@ int ctd::ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies) {
   return upload_desc(ctx, cs);
 }
 
-uint64_t ctd::case_footprint(int64_t V, int64_t n_proj, int tally_copies) {
-  return (uint64_t)V * (24 + 8 * (uint64_t)tally_copies) + 8 * kAccWords + sizeof(CaseDev) +
-         sizeof(float4) * (uint64_t)n_proj + 65536;
+int ctd::ensure_mh_buffer(ctd_ctx *ctx, ctd_case *cs, uint64_t n) {
+  if (cs->mh_cap >= n) return CTD_OK;
+  // the buffer may still be read by an earlier round on the stream
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  dfree(cs->d_mh_beam);
+  cs->d_mh_beam = nullptr;
+  cs->mh_cap = 0;
+  HIPCHK(ctx, hipMalloc(&cs->d_mh_beam, sizeof(int32_t) * n));
+  cs->mh_cap = n;
+  return CTD_OK;
+}
+
+uint64_t ctd::case_footprint(int64_t V, const ctd_geometry *geo, int tally_copies,
+                             uint64_t round_histories) {
+  uint64_t b = (uint64_t)V * (24 + 8 * (uint64_t)tally_copies) + 8 * kAccWords +
+               sizeof(CaseDev) + sizeof(float4) * geo->proj_sc.size() + 65536;
+  b += 8 * geo->fl_cdf.size() + 4 * geo->fl_guide.size();
+  if (!geo->fl_f.empty())
+    b += 4 * geo->fl_f.size() + 4 * (uint64_t)geo->g.fluence_chains + 4 * round_histories;
+  return b;
 }
 
 extern "C" int32_t ctd_set_tuning(ctd_ctx *ctx, ctd_case *cs, const ctd_tuning *t) {
@@ -824,7 +859,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
     rc[i].h_begin = items[i].h_begin;
     rc[i].n = items[i].n;
     rc[i].chunk_begin = chunks;
-    rc[i].pad = 0;
+    rc[i].beamlets = items[i].beamlets;
     chunks += (items[i].n + (uint64_t)t.chunk - 1) / (uint64_t)t.chunk;
     std::memcpy(h + poff[i], items[i].prefix.data(), 8 * items[i].prefix.size());
   }
@@ -899,6 +934,11 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     it.cd = cases[i]->d_desc;
     it.h_begin = cases[i]->h_next;
     it.n = n[i];
+    if (cases[i]->d_mh_state) {
+      rc0 = ensure_mh_buffer(ctx, cases[i], n[i]);
+      if (rc0 != CTD_OK) return rc0;
+      it.beamlets = cases[i]->d_mh_beam;
+    }
     int rc = batch_prefix(ctx, cases[i], n[i], it.prefix);
     if (rc != CTD_OK) return rc;
     items.push_back(std::move(it));
@@ -913,6 +953,18 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     HIPCHK(ctx, hipEventCreate(&tm.b));
     HIPCHK(ctx, hipEventCreate(&tm.c));
     HIPCHK(ctx, hipEventRecord(tm.a, ctx->stream));
+  }
+  // Alg. A1 chains of this round's histories (same stream: ordered before the
+  // transport that reads them and after the previous round's)
+  for (size_t i = 0, k = 0; i < cases.size(); ++i) {
+    if (n[i] == 0) continue;
+    ctd_case *cs = cases[i];
+    const RoundItem &it = items[k++];
+    if (!it.beamlets) continue;
+    if (launch_mh_fill(cs->d_fl_f, (int)cs->geo->fl_f.size(), cs->geo->g.fluence_chains,
+                       it.h_begin, it.n, cs->desc.key0, cs->desc.key1, cs->d_mh_state,
+                       cs->d_mh_beam, ctx->stream) != 0)
+      return hip_err(ctx, hipGetLastError(), "Metropolis-Hastings fill launch");
   }
   int rc = submit_round(ctx, items, t, with_log);
   if (rc != CTD_OK) return rc;

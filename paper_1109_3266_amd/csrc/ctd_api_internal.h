@@ -19,6 +19,7 @@ struct RoundItem {
   const CaseDev *cd;
   uint64_t h_begin, n;
   std::vector<unsigned long long> prefix;
+  const int32_t *beamlets = nullptr;   // Alg. A1 beamlets of the round, or null
 };
 
 }  // namespace ctd
@@ -79,6 +80,7 @@ struct ctd_geometry {
   std::vector<double> fl_cdf;    // fluence map running sums C_I (empty: uniform field)
   std::vector<int32_t> fl_guide; // [2^fl_gbits] first beamlet with C_I > k F / 2^gbits
   int32_t fl_gbits = 0;
+  std::vector<float> fl_f;       // map intensities, kept for Alg. A1 chains
   std::atomic<int> refs{0};
 };
 
@@ -99,6 +101,10 @@ struct ctd_case {
   float4 *d_proj = nullptr;
   double *d_fl_cdf = nullptr;
   int32_t *d_fl_guide = nullptr;
+  float *d_fl_f = nullptr;         // Alg. A1: intensities [N_f]
+  int32_t *d_mh_state = nullptr;   // Alg. A1: last beamlet of each chain [C]
+  int32_t *d_mh_beam = nullptr;    // Alg. A1: beamlets of the current round
+  uint64_t mh_cap = 0;
   unsigned long long *d_tally = nullptr;
   int tally_copies = 1;     // 1, or kTallyCopies once tally_mode 1 is selected
   long long *d_s1 = nullptr;
@@ -142,7 +148,11 @@ int run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count);
 uint64_t sigma_plan(uint64_t have, double sig, double target, uint64_t max_batches);
 int ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies);
 // Device bytes a case over V voxels allocates (batch tally copies, S1/S2
-// sums, counters, projection table).
-uint64_t case_footprint(int64_t V, int64_t n_proj, int tally_copies);
+// sums, counters, projection and fluence tables, Alg. A1 buffers for rounds
+// of up to round_histories).
+uint64_t case_footprint(int64_t V, const ctd_geometry *geo, int tally_copies,
+                        uint64_t round_histories);
+// Alg. A1 beamlet buffer of at least n entries.
+int ensure_mh_buffer(ctd_ctx *ctx, ctd_case *cs, uint64_t n);
 
 }  // namespace ctd

@@ -78,7 +78,7 @@ struct CaseDev {
   float phi0_turns, arc_turns, z_feed, pad8;   // z_feed: cm per turn
   const float4 *proj_sc;       // [nproj] (sin phi_p, cos phi_p, z offset of p, 0)
   // fluence map: fl_n beamlets (0 = uniform field), fl_na along a
-  int32_t fl_n, fl_na, fl_gbits, pad10;
+  int32_t fl_n, fl_na, fl_gbits, fl_chains;   // fl_chains > 0: Alg. A1 beamlets
   float fl_da, fl_db;          // beamlet size at the isocentre (cm)
   double fl_total;             // F = C_{n-1}
   const double *fl_cdf;        // [fl_n] running sums of f
@@ -102,7 +102,8 @@ struct CaseDev {
 struct RoundCase {
   const CaseDev *cd;
   const unsigned long long *prefix;
-  uint64_t h_begin, n, chunk_begin, pad;
+  uint64_t h_begin, n, chunk_begin;
+  const int32_t *beamlets;     // [n] Alg. A1 beamlet per history, or null
 };
 
 struct LaunchCfg {
@@ -139,6 +140,10 @@ int launch_sigma(const long long *s1, const unsigned long long *s2, const uint2 
 int launch_microbench(int kind, void *buf_a, void *buf_b, int64_t n, int64_t ops, int grid,
                       void *stream);
 int device_cu_count(int device);
+// Alg. A1: advance C logical chains (chain = h mod C) over histories
+// [h_begin, h_begin + n): state[C] in/out, out[n] the beamlet of each history.
+int launch_mh_fill(const float *f, int n_f, int C, uint64_t h_begin, uint64_t n, uint32_t key0,
+                   uint32_t key1, int32_t *state, int32_t *out, void *stream);
 // Gamma index of ev against ref on an nx*ny*nz grid (ctd_gamma.hip); offs is
 // a device double4 table sorted by distance; gamma may be null; counts[2]
 // (region voxels, passing voxels) are accumulated, not cleared.

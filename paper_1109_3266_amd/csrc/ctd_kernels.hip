@@ -284,7 +284,7 @@ __device__ __forceinline__ void deposit(const StepCase &S, const CaseDev &G, Pho
 // false when the ray misses the voxel box (the photon escapes at once).
 template <bool LOG>
 __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t h, int j,
-                       Counters &c) {
+                       const int32_t *__restrict__ mh_beam, uint64_t local, Counters &c) {
   p.hlo = (uint32_t)h;
   p.hhi = (uint32_t)(h >> 32);
   p.k = 0;
@@ -318,13 +318,18 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
     sz = G.iso[2] + zoff;
     float a, b;
     if (G.fl_n > 0) {
-      // beamlet I = min{I : C_I > u F}, decided in FP64 (exact inputs: u has
-      // 24 bits, k / 2^gbits <= u exactly, so the guide entry is a lower bound)
-      const uint4 r2 = philox10(0u, p.hlo, p.hhi, 1u, S.key0, S.key1);
-      const double u = (double)unif(r2.x);
-      const double x = u * G.fl_total;
-      int I = G.fl_guide[(int)(u * (double)(1 << G.fl_gbits))];
-      while (I < G.fl_n - 1 && G.fl_cdf[I] <= x) ++I;
+      int I;
+      if (G.fl_chains > 0) {
+        I = mh_beam[local];               // Alg. A1 chain step of this history
+      } else {
+        // beamlet I = min{I : C_I > u F}, decided in FP64 (exact inputs: u has
+        // 24 bits, k / 2^gbits <= u exactly, so the guide entry is a lower bound)
+        const uint4 r2 = philox10(0u, p.hlo, p.hhi, 1u, S.key0, S.key1);
+        const double u = (double)unif(r2.x);
+        const double x = u * G.fl_total;
+        I = G.fl_guide[(int)(u * (double)(1 << G.fl_gbits))];
+        while (I < G.fl_n - 1 && G.fl_cdf[I] <= x) ++I;
+      }
       const int ib = I / G.fl_na;
       const int ia = I - ib * G.fl_na;
       a = fmaf((float)ia + unif(r.z), G.fl_da, G.a0);
@@ -586,7 +591,7 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
           const uint64_t local = pool_next + rank;
           int j = wbin;
           while (j + 1 < G.nbins && local >= R.prefix[j + 1]) ++j;
-          alive = source<LOG>(p, S, G, R.h_begin + local, j, cnt);
+          alive = source<LOG>(p, S, G, R.h_begin + local, j, R.beamlets, local, cnt);
         }
         pool_next += m;
         refills += 1;
@@ -602,6 +607,44 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
     if (alive) alive = step<LOG>(p, S, G, pal_lds, cnt);
   }
   if (cur >= 0) flush(cnt, G.acc, lane, refills);
+}
+
+// Alg. A1 (Metropolis-Hastings) on logical chains: lane c advances chain c
+// over its histories h = c (mod C) of [h_begin, h_begin + n) in increasing h.
+// Step of history h: trial J = floor(u0 N_f) and zeta = u1 from the second
+// source block; move to J when zeta f_I < f_J (exact in FP64: 24-bit
+// operands).  A chain's first history (h = c) starts from a beamlet drawn
+// from the counter (0, c_lo, c_hi, 2).
+__global__ void __launch_bounds__(256) k_mh_fill(const float *__restrict__ f, int n_f, int C,
+                                                 uint64_t h_begin, uint64_t n, uint32_t key0,
+                                                 uint32_t key1, int32_t *__restrict__ state,
+                                                 int32_t *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const uint64_t Cu = (uint64_t)C;
+  const uint64_t r = h_begin % Cu;
+  uint64_t h = h_begin + (((uint64_t)c + Cu - r) % Cu);
+  const uint64_t end = h_begin + n;
+  if (h >= end) return;
+  int I;
+  if (h < Cu) {
+    const uint4 r0 = philox10(0u, (uint32_t)c, 0u, 2u, key0, key1);
+    I = min((int)((double)unif(r0.x) * (double)n_f), n_f - 1);
+  } else {
+    I = state[c];
+  }
+  double fI = (double)f[I];
+  for (; h < end; h += Cu) {
+    const uint4 r2 = philox10(0u, (uint32_t)h, (uint32_t)(h >> 32), 1u, key0, key1);
+    const int J = min((int)((double)unif(r2.x) * (double)n_f), n_f - 1);
+    const double fJ = (double)f[J];
+    if ((double)unif(r2.y) * fI < fJ) {
+      I = J;
+      fI = fJ;
+    }
+    out[h - h_begin] = I;
+  }
+  state[c] = I;
 }
 
 // --------------------------------------------------------------- fold etc.
@@ -880,6 +923,14 @@ int launch_pack(const uint8_t *mat, const float *rho, uint2 *vox, int64_t V,
                 unsigned int *stats, void *stream) {
   hipLaunchKernelGGL(k_pack, dim3(grid_for(V, 256, 2048)), dim3(256), 0, (hipStream_t)stream,
                      mat, rho, vox, V, stats);
+  return check_launch();
+}
+
+int launch_mh_fill(const float *f, int n_f, int C, uint64_t h_begin, uint64_t n, uint32_t key0,
+                   uint32_t key1, int32_t *state, int32_t *out, void *stream) {
+  if (C <= 0 || n == 0) return 0;
+  hipLaunchKernelGGL(k_mh_fill, dim3((unsigned)((C + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, f, n_f, C, h_begin, n, key0, key1, state, out);
   return check_launch();
 }
 

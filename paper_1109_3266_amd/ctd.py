@@ -51,7 +51,8 @@ class ctd_geom(C.Structure):
                 ("dir", C.c_double * 3), ("sad", C.c_double), ("iso", C.c_double * 3),
                 ("a0", C.c_double), ("a1", C.c_double), ("b0", C.c_double), ("b1", C.c_double),
                 ("phi0_deg", C.c_double), ("arc_deg", C.c_double), ("z_feed", C.c_double),
-                ("fluence_na", C.c_int32), ("fluence_nb", C.c_int32), ("fluence", C.c_void_p)]
+                ("fluence_na", C.c_int32), ("fluence_nb", C.c_int32), ("fluence", C.c_void_p),
+                ("fluence_chains", C.c_int32), ("reserved_f", C.c_int32)]
 
 
 class ctd_params(C.Structure):

@@ -44,6 +44,7 @@ def _geom(geo: dict) -> L.ctd_geom:
             f = np.ascontiguousarray(f, dtype=np.float32)
             g.fluence_nb, g.fluence_na = f.shape
             g.fluence = f.ctypes.data
+            g.fluence_chains = int(geo.get("fluence_chains", 0))
             g._keep = f
     return g
 

@@ -33,6 +33,9 @@ def cases():
     yield "head_s8_bound_compton", wh
     yield "head_helical_s8", W.head_helical(scale=8, n_histories=N)
     yield "water_box_bowtie_s5", W.water_box_bowtie(scale=5, n_histories=N)
+    mh = W.water_box_bowtie(scale=5, n_histories=N)
+    mh.geometry["fluence_chains"] = 256
+    yield "water_box_bowtie_s5_mh", mh
 
 
 def summarise(wl):

@@ -112,25 +112,33 @@ def test_paired_parity_bound_electron_compton(ctx, name, kw):
     assert abs(g["st"].n_compton - r["n_compton"]) <= 2e-3 * r["n_compton"] + 5
 
 
-def test_fluence_map_beamlets_bit_exact(ctx):
+@pytest.mark.parametrize("f,chains", [
+    (None, 0),
+    (np.array([[1.0, 0.0, 2.0, 0.25], [5.0, 0.5, 0.0, 3.0]], np.float32), 0),
+    (None, 64),
+    (np.array([[1.0, 3.0, 0.5]], np.float32), 1000),
+])
+def test_fluence_map_beamlets_bit_exact(ctx, f, chains):
     """Every history's beamlet (an integer decided in FP64 on both sides)
-    equals the oracle's, including a map with empty beamlets."""
-    for f in [None, np.array([[1.0, 0.0, 2.0, 0.25], [5.0, 0.5, 0.0, 3.0]], np.float32)]:
-        wl = W.water_box_bowtie(scale=5, n_histories=30_000)
-        if f is not None:
-            wl.geometry["fluence"] = f
-        say(f"fluence beamlets {wl.geometry['fluence'].shape}")
-        g = gpu_run(ctx, wl, log=(0, 30_000, 400_000))
-        r = O.run(O.OracleCase(wl), threads=8, log_range=(0, 30_000), log_cap=400_000)
-        gs = g["log"][g["log"]["type"] == 0]
-        os_ = r["log"][r["log"]["type"] == 0]
-        os_ = os_[np.argsort(os_["h"], kind="stable")]
-        assert np.array_equal(gs["h"], np.arange(30_000))
-        assert np.array_equal(gs["h"], os_["h"])
-        assert np.array_equal(gs["vox"], os_["vox"])
-        assert gs["vox"].min() >= 0
-        if f is not None:
-            assert not np.isin(gs["vox"], [1, 6]).any()
+    equals the oracle's: exact inverse CDF (with empty beamlets) and Alg. A1
+    chains carried across the 10 batches of the run."""
+    wl = W.water_box_bowtie(scale=5, n_histories=30_000)
+    if f is not None:
+        wl.geometry["fluence"] = f
+    wl.geometry["fluence_chains"] = chains
+    say(f"fluence beamlets {wl.geometry['fluence'].shape} chains={chains}")
+    g = gpu_run(ctx, wl, log=(0, 30_000, 400_000))
+    r = O.run(O.OracleCase(wl), threads=8, log_range=(0, 30_000), log_cap=400_000)
+    gs = g["log"][g["log"]["type"] == 0]
+    os_ = r["log"][r["log"]["type"] == 0]
+    os_ = os_[np.argsort(os_["h"], kind="stable")]
+    assert np.array_equal(gs["h"], np.arange(30_000))
+    assert np.array_equal(gs["h"], os_["h"])
+    assert np.array_equal(gs["vox"], os_["vox"])
+    assert gs["vox"].min() >= 0
+    if f is not None and chains == 0:
+        assert not np.isin(gs["vox"], [1, 6]).any()
+    paired_compare(g, r)
 
 
 @pytest.mark.parametrize("shape,seed", [((2, 2, 2), 3), ((4, 4, 4), 5), ((3, 5, 7), 8)])

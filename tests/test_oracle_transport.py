@@ -2,6 +2,7 @@
 sampling; Sec. 2.2.1 batches; Sec. 2.2.5 spectrum stratification; Sec. 2.2.6
 source trajectory) against closed forms, invariances and brute force."""
 from dataclasses import replace as dataclass_replace
+import math
 from fractions import Fraction
 
 import numpy as np
@@ -599,3 +600,61 @@ def test_single_beamlet_map_equals_uniform_field():
         assert a[0]["vox"] == 0 and b[0]["vox"] == -1
         a["vox"][0] = -1
         assert a.tobytes() == b.tobytes()
+
+
+def _mh_case(f, chains, scale=10):
+    wl = W.water_box_bowtie(scale=scale)
+    wl.geometry["fluence"] = np.asarray(f, np.float32)
+    wl.geometry["fluence_chains"] = chains
+    return O.OracleCase(wl)
+
+
+def test_metropolis_hastings_two_beamlet_chain():
+    """Alg. A1 on a 2-beamlet map f = (1, 3): the chain moves 0 -> 1 with
+    probability 1/2 (trial J = 1, always accepted) and 1 -> 0 with 1/2 x 1/3,
+    so its stationary law is (1/4, 3/4) = f / sum f."""
+    c = _mh_case([[1.0, 3.0]], chains=1)
+    I = O.mh_advance(c, 300_000).astype(int)
+    a, b = I[:-1], I[1:]
+    p01 = np.mean(b[a == 0] == 1)
+    p10 = np.mean(b[a == 1] == 0)
+    assert abs(p01 - 0.5) < 5 * math.sqrt(0.25 / np.sum(a == 0))
+    assert abs(p10 - 1 / 6) < 5 * math.sqrt((1 / 6) * (5 / 6) / np.sum(a == 1))
+    # second eigenvalue 1/3: asymptotic variance factor (1 + 1/3) / (1 - 1/3) = 2
+    assert abs(np.mean(I == 1) - 0.75) < 5 * math.sqrt(0.75 * 0.25 * 2 / I.size)
+
+
+def test_metropolis_hastings_chains_and_fig5c():
+    """64 logical chains over the bow-tie map: e = ||p_f - p_f*|| falls with
+    the photon count (Fig. 5c), within a few times the independent-sampling
+    value; resuming the chains in pieces gives the same beamlets."""
+    wl = W.water_box_bowtie(scale=10, na=32, nb=24)
+    wl.geometry["fluence_chains"] = 64
+    f = wl.geometry["fluence"].astype(np.float64).reshape(-1)
+    p = f / f.sum()
+    I = O.mh_advance(O.OracleCase(wl), 200_000).astype(int)
+    es = []
+    for n in [2_000, 20_000, 200_000]:
+        q = np.bincount(I[:n], minlength=p.size) / n
+        es.append(np.linalg.norm(q - p))
+        assert es[-1] < 3.0 * np.sqrt((p * (1 - p)).sum() / n)
+    assert es[0] > es[1] > es[2]
+    c2 = O.OracleCase(wl)
+    parts = np.concatenate([O.mh_advance(c2, k) for k in (1, 63, 1000, 198_936)])
+    assert np.array_equal(parts, I)
+
+
+def test_metropolis_hastings_transport_and_guards():
+    wl = W.water_box_bowtie(scale=10, n_histories=20_000)
+    wl.geometry["fluence_chains"] = 16
+    c = O.OracleCase(wl)
+    r = O.run(c, threads=THREADS)
+    assert r["e_inc"] == pytest.approx(r["e_dep"] + r["e_esc"], rel=1e-12)
+    with pytest.raises(ValueError):
+        O.run(c, threads=THREADS)               # chains are past history 0
+    r2 = O.run(c, h0=20_000, threads=THREADS, n_histories=1000)
+    assert r2["n_hist"] == 1000
+    with pytest.raises(ValueError):
+        O.sample_source(O.OracleCase(wl), 0, 0)  # chains not advanced
+    with pytest.raises(ValueError):
+        _mh_case([[1.0, 0.0]], chains=4)
