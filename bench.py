@@ -10,7 +10,8 @@ the batch fold.  Inputs are resident in device memory before timing.
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--quick]
 
 Prints one JSON line (rank 0).  Extra legs (time to 1 % sigma, batched
-engine vs per-case runs, serving) are included unless --quick.
+engine vs per-case runs, serving, the model variants and the gamma tool) are
+included unless --quick.
 """
 from __future__ import annotations
 
@@ -116,6 +117,110 @@ def batched_leg(ctx, L, W, Case, tuning, torch, hist_scale):
     return dict(cases=len(cases), histories=total, histories_per_s=total / t_many,
                 plain_histories_per_s=total / t_plain, speedup=t_plain / t_many,
                 identical_to_plain=bool(same))
+
+
+def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
+    """Throughput of the variants beside the plain path (bound-electron
+    Compton, helical CT, fluence-map source), the paper's Table 1 water-box
+    case timed end to end as the paper times it (set-up and upload included),
+    and the gamma-index kernel on a full head grid."""
+    import numpy as np
+    from paper_1109_3266_amd.session import grid
+    out = {}
+
+    def timed_run(wl, n, **kw):
+        with Case(ctx, wl, **kw) as c:
+            L.ctd_set_tuning(ctx, c.cs, tuning)
+            L.ctd_run(ctx, c.cs, 10_000_000)          # warm
+            L.ctd_case_reset(ctx, c.cs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L.ctd_run(ctx, c.cs, n)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = L.ctd_read_stats(ctx, c.cs)
+            return dict(histories_per_s=n / dt, steps_per_history=st.n_steps / n,
+                        deposits_per_history=st.n_deposits / n,
+                        crossings_per_history=st.n_crossings / n,
+                        sigma_paper=L.ctd_sigma(ctx, c.cs, L.CTD_SIGMA_PAPER, 0.2))
+
+    from dataclasses import replace
+    hw = W.head()
+    bow = W.water_box_bowtie()
+    bow_mh = W.water_box_bowtie()
+    bow_mh.geometry["fluence_chains"] = 1 << 18
+    macro = dict(tracking=L.CTD_TRACK_MACRO)
+    for name, mk, kw in [("head", lambda: hw, {}),
+                         ("head_macro_tracking", lambda: hw, macro),
+                         ("head_bound_electron_compton", lambda: replace(hw, compton="wh"), {}),
+                         ("head_helical", lambda: W.head_helical(), {}),
+                         ("head_helical_macro_tracking", lambda: W.head_helical(), macro),
+                         ("water_box_bowtie", lambda: bow, {}),
+                         ("water_box_bowtie_metropolis_hastings", lambda: bow_mh, {})]:
+        log(f"extensions: {name}")
+        out[name] = timed_run(mk(), n_hist, **kw)
+
+    # the head to 1 % sigma (local, D > 0.5 D_max), batches of 1e8, with the
+    # paper's global majorant and with macro-cell majorants
+    for name, kw in [("head_time_to_1pct_sigma", {}),
+                     ("head_time_to_1pct_sigma_macro_tracking", macro)]:
+        log(f"extensions: {name}")
+        with Case(ctx, hw, **kw) as c:
+            L.ctd_set_tuning(ctx, c.cs, tuning)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sig = L.ctd_run_to_sigma(ctx, c.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, 100_000_000,
+                                     200_000_000_000)
+            st = L.ctd_read_stats(ctx, c.cs)
+            out[name] = dict(seconds=time.perf_counter() - t0, sigma_local=sig,
+                             histories=st.n_histories)
+
+    # Table 1 water phantom: 2.5e8 histories in 10 batches, T from host
+    # inputs to the dose on the host (the paper includes initialisation)
+    wl = W.water_box_bowtie()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with Case(ctx, wl) as c:
+        L.ctd_set_tuning(ctx, c.cs, tuning)
+        L.ctd_run(ctx, c.cs, wl.n_histories)
+        dose, _ = c.dose()
+        T = time.perf_counter() - t0
+        sig = L.ctd_sigma(ctx, c.cs, L.CTD_SIGMA_PAPER, 0.2)
+    out["table1_water_bowtie"] = dict(
+        histories=wl.n_histories, seconds_end_to_end=T, sigma_paper=sig,
+        efficiency_1_over_sigma2_T=1.0 / (sig * sig * T),
+        paper_context="gCTD Table 1 water phantom: 2.5e8 histories, 6.95 s, sigma 0.64 %, "
+                      "Tesla C2050 (efficiency 1/(sigma^2 T) = 3.5e3 /s)")
+
+    # gamma index (2 %, 2 mm, D > 20 % D_max) between two independent runs:
+    # the head on 0.4 cm voxels with 2.5e8 histories each (the paper's Zubal
+    # resolution and history count), and the tool's speed on the full head grid
+    def two_doses(wl, n):
+        doses = []
+        for seed in (3, 13):
+            with Case(ctx, wl, seed=seed) as c:
+                L.ctd_set_tuning(ctx, c.cs, tuning)
+                L.ctd_run(ctx, c.cs, n)
+                doses.append(c.dose()[0].astype(np.float32))
+        return doses
+
+    def gamma(wl, doses):
+        dmax = float(doses[0].max())
+        L.ctd_gamma(ctx, grid(wl), doses[0], doses[1], 0.02 * dmax, 0.2, 0.2 * dmax)  # warm
+        t0 = time.perf_counter()
+        _, nr, npass = L.ctd_gamma(ctx, grid(wl), doses[0], doses[1], 0.02 * dmax, 0.2,
+                                   0.2 * dmax, want_gamma=False)
+        return dict(voxels=wl.n_voxels, region_voxels=nr, pass_rate=npass / max(nr, 1),
+                    seconds=time.perf_counter() - t0)
+
+    log("extensions: gamma index")
+    h4 = W.head(scale=4)
+    out["gamma_head_0p4cm"] = dict(gamma(h4, two_doses(h4, 250_000_000)),
+                                   note="two independent 2.5e8-history runs (seeds 3, 13)")
+    out["gamma_head_full_grid"] = dict(gamma(hw, two_doses(hw, 1_000_000_000)),
+                                       note="two independent 1e9-history runs; time includes "
+                                            "the host-to-device copy of both doses")
+    return out
 
 
 def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
@@ -353,6 +458,7 @@ def main():
         out["batched"] = batched_leg(ctx, L, W, Case, tuning, torch, args.batched_scale)
         if args.serving_requests > 0:
             out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests)
+        out["extensions"] = extensions_leg(ctx, L, W, Case, torch, tuning)
 
     if not args.no_cpu:
         log("cpu baseline")

@@ -124,12 +124,27 @@ typedef struct {
   int32_t reserved_f;
 } ctd_geom;
 
+/* Free-path tracking (Sec. 2.1).  GLOBAL: Woodcock tracking against one
+ * majorant mu_max(E) over the whole phantom, as in the paper.  MACRO: the same
+ * method with a piecewise-constant majorant over cubic cells of macro_cell^3
+ * voxels -- the optical depth -ln(u) to the next tentative collision is spent
+ * cell by cell along the ray (boundary crossings draw no random number) and
+ * the interaction is selected against the cell's majorant, which bounds
+ * every voxel of the cell at every energy.  Both are exact; MACRO consumes
+ * random numbers differently, so its histories are not the GLOBAL ones, and it
+ * saves the voxel reads of fictitious steps where dense and light tissue mix
+ * (a bone-dominated global majorant). */
+#define CTD_TRACK_GLOBAL 0
+#define CTD_TRACK_MACRO 1
+
 typedef struct {
   double e_cut_kev;      /* photon absorption energy (Sec. 3.1 uses 1 keV) */
   uint64_t seed;         /* Philox key */
   int32_t n_batches;     /* batches per ctd_run (Sec. 2.2.1 uses 10), >= 2 */
   int32_t rayleigh;      /* 1 = Rayleigh scattering on */
   double sigma_rho_min;  /* voxels with rho >= this count as "inside" for sigma-bar */
+  int32_t tracking;      /* CTD_TRACK_GLOBAL (default) or CTD_TRACK_MACRO */
+  int32_t macro_cell;    /* MACRO cell edge in voxels, 1..64 (0: about 1.6 cm) */
 } ctd_params;
 
 /* Energy balance in units of q = 2^-24 keV as exact 128-bit sums (hi:lo). */
@@ -149,6 +164,7 @@ typedef struct {
   uint32_t n_batches;    /* batches folded so far */
   uint32_t reserved;
   uint64_t n_histories;  /* histories run so far */
+  uint64_t n_crossings;  /* MACRO tracking: macro-cell boundary crossings */
 } ctd_stats;
 
 /* Launch configuration of the persistent transport kernel. */

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libctd.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["ctd_kernels.hip", "ctd_gamma.hip", "ctd_api.cpp", "ctd_tables.cpp", "ctd_server.cpp",
-           "ctd_tools.cpp"]
+           "ctd_tools.cpp", "ctd_macro.cpp"]
 
 # packed-fp32 instructions are disabled for all device code; FP contraction
 # off so every launch configuration computes bit-identical float results.

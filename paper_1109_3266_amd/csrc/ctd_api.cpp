@@ -509,6 +509,9 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
   NEED(ctx, emax <= etop, "spectrum reaches %.6g keV beyond the energy grid (%.6g)", emax, etop);
   NEED(ctx, emax < 255.0, "spectrum energies must stay below 255 keV");
   NEED(ctx, !p->rayleigh || ms->d_rayl, "Rayleigh on but no Rayleigh surfaces loaded");
+  NEED(ctx, p->tracking == CTD_TRACK_GLOBAL || p->tracking == CTD_TRACK_MACRO,
+       "unknown tracking mode %d", p->tracking);
+  NEED(ctx, p->macro_cell >= 0 && p->macro_cell <= 64, "macro_cell must be 0..64");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctd_case *cs = new (std::nothrow) ctd_case();
   if (!cs) return CTD_ENOMEM;
@@ -580,6 +583,8 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
                                     sizeof(float4) * geo->proj_sc.size(),
                                     hipMemcpyHostToDevice)) != hipSuccess))
     return cleanup(hip_err(ctx, e, "case upload"));
+  if (p->tracking == CTD_TRACK_MACRO && (rc = build_macro(ctx, cs)) != CTD_OK)
+    return cleanup(rc);
   if (launch_zero(cs->d_tally, 8 * V, ctx->stream) || launch_zero(cs->d_s1, 8 * V, ctx->stream) ||
       launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
       launch_zero(cs->d_acc, 8 * kAccWords, ctx->stream))
@@ -664,6 +669,14 @@ void ctd::fill_desc(ctd_case *cs) {
   d.fl_cdf = cs->d_fl_cdf;
   d.fl_guide = cs->d_fl_guide;
   d.fl_chains = geo->fl_f.empty() ? 0 : G.fluence_chains;
+  d.mc_cs = cs->mc_cs;
+  d.mc_nx = cs->mc_n[0];
+  d.mc_ny = cs->mc_n[1];
+  d.mc_nz = cs->mc_n[2];
+  d.mc_fcs = (float)cs->mc_cs;
+  d.mc_inv_cs = cs->mc_cs ? 1.0f / (float)cs->mc_cs : 0.0f;
+  d.mc_cls = cs->d_mc_cls;
+  d.mc_tab = cs->d_mc_tab;
   d.key0 = (uint32_t)cs->p.seed;
   d.key1 = (uint32_t)(cs->p.seed >> 32);
   d.tally = cs->d_tally;
@@ -691,6 +704,8 @@ void ctd::free_case_buffers(ctd_case *cs) {
   dfree(cs->d_fl_f);
   dfree(cs->d_mh_state);
   dfree(cs->d_mh_beam);
+  dfree(cs->d_mc_cls);
+  dfree(cs->d_mc_tab);
   dfree(cs->d_log);
   dfree(cs->d_log_n);
   for (auto &t : cs->timing) {
@@ -788,10 +803,16 @@ int ctd::ensure_mh_buffer(ctd_ctx *ctx, ctd_case *cs, uint64_t n) {
   return CTD_OK;
 }
 
-uint64_t ctd::case_footprint(int64_t V, const ctd_geometry *geo, int tally_copies,
-                             uint64_t round_histories) {
-  uint64_t b = (uint64_t)V * (24 + 8 * (uint64_t)tally_copies) + 8 * kAccWords +
-               sizeof(CaseDev) + sizeof(float4) * geo->proj_sc.size() + 65536;
+uint64_t ctd::case_footprint(const ctd_grid &g, const ctd_geometry *geo, const ctd_params &p,
+                             int ne, int tally_copies, uint64_t round_histories) {
+  const uint64_t V = (uint64_t)g.nx * g.ny * g.nz;
+  uint64_t b = V * (24 + 8 * (uint64_t)tally_copies) + 8 * kAccWords + sizeof(CaseDev) +
+               sizeof(float4) * geo->proj_sc.size() + 65536;
+  if (p.tracking == CTD_TRACK_MACRO) {
+    int n[3];
+    const uint64_t cells = (uint64_t)macro_cells(g, macro_edge(g, p.macro_cell), n);
+    b += 2 * cells + 4 * (uint64_t)ne * std::min<uint64_t>(cells, 65536);
+  }
   b += 8 * geo->fl_cdf.size() + 4 * geo->fl_guide.size();
   if (!geo->fl_f.empty())
     b += 4 * geo->fl_f.size() + 4 * (uint64_t)geo->g.fluence_chains + 4 * round_histories;
@@ -826,6 +847,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
                       bool with_log) {
   const int nrc = (int)items.size();
   if (nrc == 0) return CTD_OK;
+  const bool macro = items[0].macro;
   size_t bytes = sizeof(RoundCase) * nrc;
   std::vector<size_t> poff((size_t)nrc);
   for (int i = 0; i < nrc; ++i) {
@@ -874,7 +896,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
   cfg.tally_mode = t.tally_mode;
   if (chunks > 0 &&
       launch_transport((const RoundCase *)d, nrc, chunks, (unsigned long long *)(d + ctr_off),
-                       cfg, with_log, ctx->stream) != 0)
+                       cfg, with_log, macro, ctx->stream) != 0)
     return hip_err(ctx, hipGetLastError(), "transport launch");
   HIPCHK(ctx, hipEventRecord(s.ev, ctx->stream));
   return CTD_OK;
@@ -934,6 +956,7 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     it.cd = cases[i]->d_desc;
     it.h_begin = cases[i]->h_next;
     it.n = n[i];
+    it.macro = cases[i]->mc_cs > 0;
     if (cases[i]->d_mh_state) {
       rc0 = ensure_mh_buffer(ctx, cases[i], n[i]);
       if (rc0 != CTD_OK) return rc0;
@@ -966,7 +989,11 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
                        cs->d_mh_beam, ctx->stream) != 0)
       return hip_err(ctx, hipGetLastError(), "Metropolis-Hastings fill launch");
   }
-  int rc = submit_round(ctx, items, t, with_log);
+  int rc = CTD_OK;
+  std::vector<RoundItem> group[2];
+  for (auto &it : items) group[it.macro ? 1 : 0].push_back(std::move(it));
+  for (int gi = 0; gi < 2 && rc == CTD_OK; ++gi)
+    if (!group[gi].empty()) rc = submit_round(ctx, group[gi], t, with_log);
   if (rc != CTD_OK) return rc;
   if (timed) HIPCHK(ctx, hipEventRecord(tm.b, ctx->stream));
   for (size_t i = 0; i < cases.size(); ++i) {
@@ -1258,6 +1285,7 @@ extern "C" int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out) {
   out->n_batches = cs->batches;
   out->reserved = 0;
   out->n_histories = cs->h_next;
+  out->n_crossings = a[ACC_N_CROSS];
   return CTD_OK;
 }
 

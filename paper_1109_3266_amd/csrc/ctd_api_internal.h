@@ -20,6 +20,7 @@ struct RoundItem {
   uint64_t h_begin, n;
   std::vector<unsigned long long> prefix;
   const int32_t *beamlets = nullptr;   // Alg. A1 beamlets of the round, or null
+  bool macro = false;                  // MACRO tracking case
 };
 
 }  // namespace ctd
@@ -105,6 +106,9 @@ struct ctd_case {
   int32_t *d_mh_state = nullptr;   // Alg. A1: last beamlet of each chain [C]
   int32_t *d_mh_beam = nullptr;    // Alg. A1: beamlets of the current round
   uint64_t mh_cap = 0;
+  uint16_t *d_mc_cls = nullptr;    // MACRO tracking: class of each cell
+  float *d_mc_tab = nullptr;       // MACRO tracking: class majorants [n_class][ne]
+  int mc_cs = 0, mc_n[3] = {0, 0, 0}, mc_classes = 0;
   unsigned long long *d_tally = nullptr;
   int tally_copies = 1;     // 1, or kTallyCopies once tally_mode 1 is selected
   long long *d_s1 = nullptr;
@@ -133,6 +137,7 @@ int hip_err(ctd_ctx *ctx, hipError_t e, const char *what);
 int upload_desc(ctd_ctx *ctx, ctd_case *cs);
 void fill_desc(ctd_case *cs);
 void free_case_buffers(ctd_case *cs);
+// One transport launch over items, which share one tracking mode.
 int submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const ctd_tuning &t,
                  bool with_log);
 ctd_tuning default_tuning(const ctd_ctx *ctx);
@@ -150,9 +155,14 @@ int ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies);
 // Device bytes a case over V voxels allocates (batch tally copies, S1/S2
 // sums, counters, projection and fluence tables, Alg. A1 buffers for rounds
 // of up to round_histories).
-uint64_t case_footprint(int64_t V, const ctd_geometry *geo, int tally_copies,
-                        uint64_t round_histories);
+uint64_t case_footprint(const ctd_grid &g, const ctd_geometry *geo, const ctd_params &p,
+                        int ne, int tally_copies, uint64_t round_histories);
 // Alg. A1 beamlet buffer of at least n entries.
 int ensure_mh_buffer(ctd_ctx *ctx, ctd_case *cs, uint64_t n);
+// MACRO tracking (ctd_macro.cpp): cells per axis for edge cs (returns the
+// cell count) and the per-cell class ids and class majorant table of a case.
+int macro_edge(const ctd_grid &g, int requested);
+int macro_cells(const ctd_grid &g, int cs, int n[3]);
+int build_macro(ctd_ctx *ctx, ctd_case *cs);
 
 }  // namespace ctd

@@ -29,6 +29,7 @@ enum Acc : int {
   ACC_N_CUTOFF,
   ACC_N_REFILLS,
   ACC_STEP_GUARD,    // histories killed by the step guard (must stay 0)
+  ACC_N_CROSS,       // macro-cell boundary crossings (MACRO tracking)
   ACC_COUNT
 };
 
@@ -83,6 +84,12 @@ struct CaseDev {
   double fl_total;             // F = C_{n-1}
   const double *fl_cdf;        // [fl_n] running sums of f
   const int32_t *fl_guide;     // [2^fl_gbits]
+  // MACRO tracking: cells of mc_cs^3 voxels, mc_n[3] per axis; class of each
+  // cell and the class majorants [n_class][ne] (cm^-1); mc_cs = 0: GLOBAL
+  int32_t mc_cs, mc_nx, mc_ny, mc_nz;
+  float mc_fcs, mc_inv_cs, pad11, pad12;
+  const uint16_t *mc_cls;
+  const float *mc_tab;
   // random stream key
   uint32_t key0, key1;
   // tallies
@@ -115,9 +122,10 @@ struct LaunchCfg {
 };
 
 // Kernel launchers (ctd_kernels.hip).  All enqueue on `stream`.
+// macro: every case of rc_dev uses MACRO tracking (else every case GLOBAL).
 int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
-                     void *stream);
+                     bool macro, void *stream);
 // Fold ncopies batch tallies [ncopies][V]: S1 += sum, S2 += sum^2, zero them;
 // fold the batch counters of acc into its 128-bit totals and record the
 // per-voxel maxima of S1 and of S2's high word.
@@ -142,6 +150,10 @@ int launch_microbench(int kind, void *buf_a, void *buf_b, int64_t n, int64_t ops
 int device_cu_count(int device);
 // Alg. A1: advance C logical chains (chain = h mod C) over histories
 // [h_begin, h_begin + n): state[C] in/out, out[n] the beamlet of each history.
+// MACRO tracking: out[cell * M + m] = max float bits of the density of
+// material m over the voxels of each cell of cs^3 voxels (out zeroed).
+int launch_cell_max(const uint2 *vox, int nx, int ny, int nz, int cs, int ncx, int ncy, int M,
+                    unsigned int *out, void *stream);
 int launch_mh_fill(const float *f, int n_f, int C, uint64_t h_begin, uint64_t n, uint32_t key0,
                    uint32_t key1, int32_t *state, int32_t *out, void *stream);
 // Gamma index of ev against ref on an nx*ny*nz grid (ctd_gamma.hip); offs is

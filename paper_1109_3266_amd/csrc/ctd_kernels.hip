@@ -383,34 +383,24 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
   return true;
 }
 
-// One Woodcock step (Sec. 2.1); returns false when the photon is done.
+// The photon leaves the voxel box with its energy.
 template <bool LOG>
-__device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G,
-                                     const LOCAL uint2 *pal, Counters &c) {
-  p.k += 1;
-  const uint32_t k = p.k & ~kScatBit;
-  if (k > kStepGuard) {
-    c.add(ACC_STEP_GUARD, 1);
-    c.add(ACC_N_STEPS, k);
-    return false;
-  }
-  const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
-  const float s = -__log2f(unif(r.x)) * p.sc;  // -ln(u) / mu_max
-  p.px = fmaf(s, p.ux * S.inv_dx, p.px);
-  p.py = fmaf(s, p.uy * S.inv_dy, p.py);
-  p.pz = fmaf(s, p.uz * S.inv_dz, p.pz);
-  const bool inside = (p.px >= 0.0f) & (p.px < S.fnx) & (p.py >= 0.0f) & (p.py < S.fny) &
-                      (p.pz >= 0.0f) & (p.pz < S.fnz);
-  if (!inside) {
-    c.add(ACC_N_STEPS, k);
-    c.add(ACC_N_ESCAPES, 1);
-    if (!(p.k & kScatBit)) c.add(ACC_N_UNSCATTERED, 1);
-    c.add(ACC_Q_ESC, (uint32_t)(p.E * kQScale));
-    log_event<LOG>(G, p, 5, -1, p.E, p.E);
-    return false;
-  }
-  const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)p.pz, (uint32_t)S.ny) + (uint32_t)p.py,
-                                         (uint32_t)S.nx) + (int32_t)p.px;
+__device__ __forceinline__ bool escape(Photon &p, const CaseDev &G, Counters &c, uint32_t k) {
+  c.add(ACC_N_STEPS, k);
+  c.add(ACC_N_ESCAPES, 1);
+  if (!(p.k & kScatBit)) c.add(ACC_N_UNSCATTERED, 1);
+  c.add(ACC_Q_ESC, (uint32_t)(p.E * kQScale));
+  log_event<LOG>(G, p, 5, -1, p.E, p.E);
+  return false;
+}
+
+// Tentative collision at voxel vox against majorant mumax (Sec. 2.1):
+// photoelectric, Compton, Rayleigh or fictitious from xi = u1 * mumax;
+// returns false when the photon is done.
+template <bool LOG>
+__device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const CaseDev &G,
+                                         const LOCAL uint2 *pal, Counters &c, const uint4 &r,
+                                         uint32_t k, int32_t vox, float mumax) {
   uint32_t rbits, m;
   if (S.npal) {  // 1-byte index into the wave's LDS table
     const uint32_t i8 = S.vox8[vox];
@@ -426,7 +416,7 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
   const float4 t0 = t[0], t1 = t[1];
   const float mpe = rho * lerpf(t0.x, t1.x, p.we);
   const float c1 = mpe + rho * lerpf(t0.y, t1.y, p.we);
-  const float xi = unif(r.y) * p.mumax;
+  const float xi = unif(r.y) * mumax;
   if (xi < mpe) {  // photoelectric: absorb, deposit E locally
     c.add(ACC_N_STEPS, k);
     c.add(ACC_N_PHOTO, 1);
@@ -464,6 +454,119 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
     }
   }
   return true;  // fictitious or scattered: keep going
+}
+
+// One Woodcock step (Sec. 2.1) against the global majorant; returns false
+// when the photon is done.
+template <bool LOG>
+__device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G,
+                                     const LOCAL uint2 *pal, Counters &c) {
+  p.k += 1;
+  const uint32_t k = p.k & ~kScatBit;
+  if (k > kStepGuard) {
+    c.add(ACC_STEP_GUARD, 1);
+    c.add(ACC_N_STEPS, k);
+    return false;
+  }
+  const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
+  const float s = -__log2f(unif(r.x)) * p.sc;  // -ln(u) / mu_max
+  p.px = fmaf(s, p.ux * S.inv_dx, p.px);
+  p.py = fmaf(s, p.uy * S.inv_dy, p.py);
+  p.pz = fmaf(s, p.uz * S.inv_dz, p.pz);
+  const bool inside = (p.px >= 0.0f) & (p.px < S.fnx) & (p.py >= 0.0f) & (p.py < S.fny) &
+                      (p.pz >= 0.0f) & (p.pz < S.fnz);
+  if (!inside) return escape<LOG>(p, G, c, k);
+  const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)p.pz, (uint32_t)S.ny) + (uint32_t)p.py,
+                                         (uint32_t)S.nx) + (int32_t)p.px;
+  return interact<LOG>(p, S, G, pal, c, r, k, vox, p.mumax);
+}
+
+// Distance (cm) along D (voxel units per cm) from x to the cell face ahead on
+// one axis; infinite when the ray is parallel to it.
+__device__ __forceinline__ float face_dist(float x, float D, float lo, float hi) {
+  if (D == 0.0f) return INFINITY;
+  const float b = D > 0.0f ? hi : lo;
+  return fmaxf((b - x) * __builtin_amdgcn_rcpf(D), 0.0f);
+}
+
+// One Woodcock step with the macro-cell majorant (MACRO tracking): the
+// optical depth tau = -ln(u0) is spent cell by cell along the ray; a
+// boundary crossing draws no random number.  The number of crossings of one
+// step is bounded by the cells per axis summed (each moves one cell along the
+// direction of travel), and the guard below enforces it.
+template <bool LOG>
+__device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const CaseDev &G,
+                                           const LOCAL uint2 *pal, Counters &c) {
+  p.k += 1;
+  const uint32_t k = p.k & ~kScatBit;
+  if (k > kStepGuard) {
+    c.add(ACC_STEP_GUARD, 1);
+    c.add(ACC_N_STEPS, k);
+    return false;
+  }
+  const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
+  float tau = -__log2f(unif(r.x)) * 0.69314718055994531f;
+  const int ncx = G.mc_nx, ncy = G.mc_ny, ncz = G.mc_nz;
+  const float fcs = G.mc_fcs;
+  const float Dx = p.ux * S.inv_dx, Dy = p.uy * S.inv_dy, Dz = p.uz * S.inv_dz;
+  int cx = min((int)(p.px * G.mc_inv_cs), ncx - 1);
+  int cy = min((int)(p.py * G.mc_inv_cs), ncy - 1);
+  int cz = min((int)(p.pz * G.mc_inv_cs), ncz - 1);
+  const GLOBAL uint16_t *cls = (const GLOBAL uint16_t *)G.mc_cls;
+  const GLOBAL float *tab = (const GLOBAL float *)G.mc_tab + p.je;
+  int guard = ncx + ncy + ncz + 2;
+  uint32_t crossings = 0;
+  float mu_c;
+  for (;;) {
+    const int id = cls[(cz * ncy + cy) * ncx + cx];
+    const GLOBAL float *row = tab + (size_t)id * (size_t)S.ne;
+    mu_c = lerpf(row[0], row[1], p.we);
+    const float x0 = (float)cx * fcs, y0 = (float)cy * fcs, z0 = (float)cz * fcs;
+    const float tx = face_dist(p.px, Dx, x0, fminf(x0 + fcs, S.fnx));
+    const float ty = face_dist(p.py, Dy, y0, fminf(y0 + fcs, S.fny));
+    const float tz = face_dist(p.pz, Dz, z0, fminf(z0 + fcs, S.fnz));
+    const float d = fminf(tx, fminf(ty, tz));
+    if (tau < mu_c * d) break;  // tentative collision inside this cell
+    tau -= mu_c * d;
+    p.px = fmaf(d, Dx, p.px);
+    p.py = fmaf(d, Dy, p.py);
+    p.pz = fmaf(d, Dz, p.pz);
+    ++crossings;
+    bool out;
+    if (tx <= ty && tx <= tz) {
+      cx += Dx > 0.0f ? 1 : -1;
+      out = (unsigned)cx >= (unsigned)ncx;
+    } else if (ty <= tz) {
+      cy += Dy > 0.0f ? 1 : -1;
+      out = (unsigned)cy >= (unsigned)ncy;
+    } else {
+      cz += Dz > 0.0f ? 1 : -1;
+      out = (unsigned)cz >= (unsigned)ncz;
+    }
+    if (out) {
+      c.add(ACC_N_CROSS, crossings);
+      return escape<LOG>(p, G, c, k);
+    }
+    if (--guard < 0) {
+      c.add(ACC_STEP_GUARD, 1);
+      c.add(ACC_N_STEPS, k);
+      c.add(ACC_N_CROSS, crossings);
+      return false;
+    }
+  }
+  if (crossings) c.add(ACC_N_CROSS, crossings);
+  const float s = tau * __builtin_amdgcn_rcpf(mu_c);
+  p.px = fmaf(s, Dx, p.px);
+  p.py = fmaf(s, Dy, p.py);
+  p.pz = fmaf(s, Dz, p.pz);
+  // the voxel is taken inside the current cell, whose majorant bounds it
+  const int cs = G.mc_cs;
+  const int ix = min(max((int)p.px, cx * cs), min(cx * cs + cs, S.nx) - 1);
+  const int iy = min(max((int)p.py, cy * cs), min(cy * cs + cs, S.ny) - 1);
+  const int iz = min(max((int)p.pz, cz * cs), min(cz * cs + cs, (int)S.fnz) - 1);
+  const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)iz, (uint32_t)S.ny) + (uint32_t)iy,
+                                         (uint32_t)S.nx) + ix;
+  return interact<LOG>(p, S, G, pal, c, r, k, vox, mu_c);
 }
 
 // ------------------------------------------------------- transport kernel
@@ -505,7 +608,10 @@ __device__ __forceinline__ void stage_case(CaseDev *dst, uint2 *pal, const CaseD
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool LOG>
+// MACRO selects the macro-cell step for every case of the launch (a round
+// with both tracking modes is split into one launch per mode), so each
+// instance carries only its own step's registers.
+template <bool LOG, bool MACRO>
 __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__ rcs, int nrc,
                                                    uint64_t total_chunks,
                                                    unsigned long long *chunk_ctr, int refill_min,
@@ -604,9 +710,31 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
       if (queue_done && pend < 0 && pool_next >= pool_end) break;
       continue;
     }
-    if (alive) alive = step<LOG>(p, S, G, pal_lds, cnt);
+    if (alive) {
+      if constexpr (MACRO)
+        alive = step_macro<LOG>(p, S, G, pal_lds, cnt);
+      else
+        alive = step<LOG>(p, S, G, pal_lds, cnt);
+    }
   }
   if (cur >= 0) flush(cnt, G.acc, lane, refills);
+}
+
+// MACRO tracking set-up: per cell of cs^3 voxels and material, the largest
+// density (float bits; densities are >= 0 so their bits order like values).
+__global__ void __launch_bounds__(256) k_cell_max(const uint2 *__restrict__ vox, int nx, int ny,
+                                                  int64_t V, int cs, int ncx, int ncy, int M,
+                                                  unsigned int *__restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += stride) {
+    const uint2 rec = vox[v];
+    if (rec.x == 0u || (int)rec.y >= M) continue;
+    const int x = (int)(v % nx);
+    const int64_t t = v / nx;
+    const int y = (int)(t % ny), z = (int)(t / ny);
+    const int64_t cell = ((int64_t)(z / cs) * ncy + y / cs) * ncx + x / cs;
+    atomicMax(out + cell * M + rec.y, rec.x);
+  }
 }
 
 // Alg. A1 (Metropolis-Hastings) on logical chains: lane c advances chain c
@@ -889,14 +1017,12 @@ static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
 int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
-                     void *stream) {
+                     bool macro, void *stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (with_log)
-    hipLaunchKernelGGL(k_transport<true>, dim3(cfg.grid), dim3(cfg.block), 0, s, rc_dev, nrc,
-                       total_chunks, chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode);
-  else
-    hipLaunchKernelGGL(k_transport<false>, dim3(cfg.grid), dim3(cfg.block), 0, s, rc_dev, nrc,
-                       total_chunks, chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode);
+  auto kern = with_log ? (macro ? k_transport<true, true> : k_transport<true, false>)
+                       : (macro ? k_transport<false, true> : k_transport<false, false>);
+  hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.block), 0, s, rc_dev, nrc, total_chunks,
+                     chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode);
   return check_launch();
 }
 
@@ -923,6 +1049,15 @@ int launch_pack(const uint8_t *mat, const float *rho, uint2 *vox, int64_t V,
                 unsigned int *stats, void *stream) {
   hipLaunchKernelGGL(k_pack, dim3(grid_for(V, 256, 2048)), dim3(256), 0, (hipStream_t)stream,
                      mat, rho, vox, V, stats);
+  return check_launch();
+}
+
+int launch_cell_max(const uint2 *vox, int nx, int ny, int nz, int cs, int ncx, int ncy, int M,
+                    unsigned int *out, void *stream) {
+  const int64_t V = (int64_t)nx * ny * nz;
+  if (V <= 0) return 0;
+  hipLaunchKernelGGL(k_cell_max, dim3(grid_for(V, 256, 8192)), dim3(256), 0, (hipStream_t)stream,
+                     vox, nx, ny, V, cs, ncx, ncy, M, out);
   return check_launch();
 }
 

@@ -160,7 +160,8 @@ static void admit(ctd_server *sv) {
     PhantomEntry &e = it->second;
     const int64_t V = (int64_t)e.g.nx * e.g.ny * e.g.nz;
     const int copies = sv->cfg.tuning.block && sv->cfg.tuning.tally_mode == 1 ? kTallyCopies : 1;
-    const uint64_t case_bytes = case_footprint(V, r->geo, copies, sv->cfg.batch_histories);
+    const uint64_t case_bytes = case_footprint(e.g, r->geo, r->p, r->ms->eg.ne, copies,
+                                               sv->cfg.batch_histories);
     const uint64_t ph_bytes = e.dev ? 0 : (uint64_t)V * 9 + 4096;
     const uint64_t need = case_bytes + ph_bytes;
     if (need > sv->cfg.hbm_budget_bytes) {  // can never fit

@@ -27,6 +27,8 @@ CTD_MEM_HOST = 0
 CTD_MEM_DEVICE = 1
 CTD_GEOM_PENCIL = 0
 CTD_GEOM_CONE = 1
+CTD_TRACK_GLOBAL = 0
+CTD_TRACK_MACRO = 1
 CTD_SIGMA_LOCAL = 0
 CTD_SIGMA_PAPER = 1
 
@@ -57,7 +59,8 @@ class ctd_geom(C.Structure):
 
 class ctd_params(C.Structure):
     _fields_ = [("e_cut_kev", C.c_double), ("seed", C.c_uint64), ("n_batches", C.c_int32),
-                ("rayleigh", C.c_int32), ("sigma_rho_min", C.c_double)]
+                ("rayleigh", C.c_int32), ("sigma_rho_min", C.c_double), ("tracking", C.c_int32),
+                ("macro_cell", C.c_int32)]
 
 
 class ctd_balance(C.Structure):
@@ -88,7 +91,7 @@ class ctd_stats(C.Structure):
                 ("n_deposits", C.c_uint64), ("n_escapes", C.c_uint64), ("n_refills", C.c_uint64),
                 ("transport_ms", C.c_double), ("fold_ms", C.c_double),
                 ("n_batches", C.c_uint32), ("reserved", C.c_uint32),
-                ("n_histories", C.c_uint64)]
+                ("n_histories", C.c_uint64), ("n_crossings", C.c_uint64)]
 
 
 class ctd_tuning(C.Structure):

@@ -99,13 +99,18 @@ class Inputs:
             self.ms = None
 
 
-def params(wl, seed=None, n_batches=None, rho_min=0.05) -> L.ctd_params:
+def params(wl, seed=None, n_batches=None, rho_min=0.05, tracking=None,
+           macro_cell=0) -> L.ctd_params:
+    """ctd_params of a workload; tracking defaults to the workload's own
+    (attribute ``tracking``, else the paper's global majorant)."""
     p = L.ctd_params()
     p.e_cut_kev = wl.e_cut
     p.seed = wl.seed if seed is None else seed
     p.n_batches = wl.n_batches if n_batches is None else n_batches
     p.rayleigh = int(wl.rayleigh)
     p.sigma_rho_min = rho_min
+    p.tracking = getattr(wl, "tracking", L.CTD_TRACK_GLOBAL) if tracking is None else tracking
+    p.macro_cell = getattr(wl, "macro_cell", 0) if not macro_cell else macro_cell
     return p
 
 
@@ -118,7 +123,7 @@ class Case:
     geometry, case).  ``close()`` releases everything."""
 
     def __init__(self, ctx, wl, mu_rho=None, seed=None, n_batches=None, rho_min=0.05,
-                 mat=None, rho=None, mem=L.CTD_MEM_HOST):
+                 mat=None, rho=None, mem=L.CTD_MEM_HOST, tracking=None, macro_cell=0):
         self.ctx = ctx
         self.wl = wl
         self.V = int(wl.grid["nx"] * wl.grid["ny"] * wl.grid["nz"])
@@ -135,12 +140,7 @@ class Case:
         self.ms = L.ctd_materials_load(ctx, eg, mu, comp, int(comp.ndim == 3), rayl)
         self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
         self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
-        p = L.ctd_params()
-        p.e_cut_kev = wl.e_cut
-        p.seed = wl.seed if seed is None else seed
-        p.n_batches = wl.n_batches if n_batches is None else n_batches
-        p.rayleigh = int(wl.rayleigh)
-        p.sigma_rho_min = rho_min
+        p = params(wl, seed, n_batches, rho_min, tracking, macro_cell)
         self.params = p
         self.cs = L.ctd_case_create(ctx, self.ph, self.ms, self.sp, self.geo, p)
 
