@@ -26,6 +26,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "photon histories/s + time-to-1%-σ dose; batched serving p50/p99 latency"
+# main-leg workloads (the benchmark is water_cbct; the others serve profiling)
+WORKLOADS = {
+    "water_cbct": "water_cbct_128x128x100_cyl30cm_120kVp_cbct360",
+    "head": "head_256x256x160_0.1cm_100kVp_halffan200",
+    "head_helical": "head_256x256x160_0.1cm_120kVp_helical6turns_pitch1",
+    "water_box_bowtie": "water_box_50cube_0.4cm_125kVp_bowtie128x96",
+}
 BATCH = 100_000_000
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes/clk x 2.4 GHz (non-packed)
 
@@ -337,7 +344,13 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--workload", default="water_cbct", choices=sorted(WORKLOADS),
+                    help="workload of the main leg (profiling; the default is the benchmark)")
+    ap.add_argument("--tracking", default="global", choices=["global", "macro"])
+    ap.add_argument("--legs", default="main,sigma,batched,serving,extensions",
+                    help="comma list of legs to run (--quick = main)")
     args = ap.parse_args()
+    legs = {"main"} if args.quick else set(args.legs.split(","))
     if args.calibrate_copy:
         calibrate_copy()
         return
@@ -361,9 +374,10 @@ def main():
     torch.cuda.set_stream(stream)
     ctx = L.ctd_create(0)
     L.ctd_set_stream(ctx, stream.cuda_stream)
-    log("building water_cbct workload")
-    wl = W.water_cbct()
-    case = Case(ctx, wl)
+    log(f"building {args.workload} workload")
+    wl = W.by_name(args.workload)
+    tracking = L.CTD_TRACK_MACRO if args.tracking == "macro" else L.CTD_TRACK_GLOBAL
+    case = Case(ctx, wl, tracking=tracking)
     tuning = L.ctd_get_tuning(ctx, case.cs)
     if not args.no_tune:
         tuning = L.ctd_autotune(ctx, case.cs, 20_000_000)
@@ -400,7 +414,8 @@ def main():
            OPS_HISTORY * n_timed)
     launch_ms = (st1.transport_ms - st0.transport_ms) / args.steps
     achieved = ops / args.steps / (launch_ms * 1e-3)
-    traffic = load_traffic("water_cbct", BATCH)
+    traffic = (load_traffic(args.workload, BATCH)
+               if tracking == L.CTD_TRACK_GLOBAL else None)
     d_dep = st1.n_deposits - st0.n_deposits
     # algorithmic bytes: 5 B voxel record per Woodcock step + 8 B per tally update
     alg_bytes = 5.0 * d_steps + 8.0 * d_dep
@@ -423,7 +438,8 @@ def main():
     out = dict(metric=METRIC, value=value, unit="histories/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=wall * 1e3 / args.steps, higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload="water_cbct_128x128x100_cyl30cm_120kVp_cbct360",
+               config=dict(workload=WORKLOADS[args.workload] +
+                           ("" if tracking == L.CTD_TRACK_GLOBAL else "_macro_tracking"),
                            histories_per_step=BATCH, histories_total=(args.steps + args.warmup)
                            * BATCH, voxels=wl.n_voxels, tally="int64 fixed point 2^-24 keV",
                            tuning=dict(block=tuning.block, waves_per_simd=tuning.waves_per_simd,
@@ -438,10 +454,10 @@ def main():
                              "D > 20 % D_max), Zubal HN, 2.5e8 histories, Tesla C2050 FP32")
     case.close()
 
-    if not args.quick:
+    if "sigma" in legs:
         # time to 1 % sigma on the same workload, from a fresh case
         log("time to 1% sigma")
-        c2 = Case(ctx, wl)
+        c2 = Case(ctx, wl, tracking=tracking)
         L.ctd_set_tuning(ctx, c2.cs, tuning)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -455,9 +471,11 @@ def main():
                                                                  L.CTD_SIGMA_PAPER, 0.2))
         c2.close()
         log(f"time to 1% sigma {tts:.2f} s ({s2.n_histories:.3g} histories)")
+    if "batched" in legs:
         out["batched"] = batched_leg(ctx, L, W, Case, tuning, torch, args.batched_scale)
-        if args.serving_requests > 0:
-            out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests)
+    if "serving" in legs and args.serving_requests > 0:
+        out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests)
+    if "extensions" in legs:
         out["extensions"] = extensions_leg(ctx, L, W, Case, torch, tuning)
 
     if not args.no_cpu:
