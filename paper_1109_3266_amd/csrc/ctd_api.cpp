@@ -1354,6 +1354,14 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
   tw.d_log = nullptr;
   tw.d_log_n = nullptr;
   tw.log_cap = 0;
+  // the twin starts at history 0 with chains and buffers of its own (the
+  // case's Metropolis-Hastings chains must only advance with its own runs)
+  tw.h_next = 0;
+  tw.batches = 0;
+  tw.batch_sizes.clear();
+  tw.d_mh_state = nullptr;
+  tw.d_mh_beam = nullptr;
+  tw.mh_cap = 0;
   const int64_t V = cs->ph->V;
   auto release = [&]() {
     dfree(tw.d_tally);
@@ -1361,9 +1369,17 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
     dfree(tw.d_s2);
     dfree(tw.d_acc);
     dfree(tw.d_desc);
+    dfree(tw.d_mh_state);
+    dfree(tw.d_mh_beam);
   };
   hipError_t e;
   tw.tally_copies = kTallyCopies;
+  if (cs->d_mh_state &&
+      (e = hipMalloc(&tw.d_mh_state, sizeof(int32_t) * (size_t)cs->geo->g.fluence_chains)) !=
+          hipSuccess) {
+    release();
+    return hip_err(ctx, e, "autotune alloc");
+  }
   if ((e = hipMalloc(&tw.d_tally, 8 * V * kTallyCopies)) != hipSuccess ||
       (e = hipMalloc(&tw.d_s1, 8 * V)) != hipSuccess ||
       (e = hipMalloc(&tw.d_s2, 16 * V)) != hipSuccess ||

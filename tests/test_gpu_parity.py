@@ -407,3 +407,28 @@ def test_microbenchmarks_report_sane_rates(ctx):
     assert 1e9 < atom < 1e12 and 1e7 < hot < atom and 1e9 < gat < 1e13
     with pytest.raises(L.CtdError):
         L.ctd_microbench(ctx, 7, 1 << 20, 1)
+
+
+@pytest.mark.parametrize("variant", ["chains", "macro"])
+def test_autotune_leaves_results_unchanged(ctx, variant):
+    """Tuning runs on a private twin: a case tuned between two runs ends with
+    the tallies of an untuned case given the same two runs (its
+    Metropolis-Hastings chains continue where they were)."""
+    kw = {}
+    if variant == "chains":
+        wl = W.water_box_bowtie(scale=5)
+        wl.geometry["fluence_chains"] = 128
+    else:
+        wl = W.head(scale=8)
+        kw = dict(tracking=L.CTD_TRACK_MACRO)
+    say(f"autotune on a {variant} case")
+    out = []
+    for tune in (False, True):
+        with Case(ctx, wl, **kw) as c:
+            c.run(20_000)
+            if tune:
+                t = L.ctd_autotune(ctx, c.cs, 200_000)
+                L.ctd_set_tuning(ctx, c.cs, t)
+            c.run(30_000)
+            out.append(c.tally())
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][2], out[1][2])
