@@ -135,9 +135,14 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
     from paper_1109_3266_amd.session import grid
     out = {}
 
-    def timed_run(wl, n, **kw):
+    tuned = {}
+
+    def timed_run(key, wl, n, **kw):
         with Case(ctx, wl, **kw) as c:
-            L.ctd_set_tuning(ctx, c.cs, tuning)
+            # each variant gets its own launch configuration (tally copies pay
+            # off where deposits concentrate); tuning never changes results
+            t = L.ctd_autotune(ctx, c.cs, 10_000_000)
+            tuned[key] = t
             L.ctd_run(ctx, c.cs, 10_000_000)          # warm
             L.ctd_case_reset(ctx, c.cs)
             torch.cuda.synchronize()
@@ -147,6 +152,8 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
             dt = time.perf_counter() - t0
             st = L.ctd_read_stats(ctx, c.cs)
             return dict(histories_per_s=n / dt, steps_per_history=st.n_steps / n,
+                        tuning=dict(waves_per_simd=t.waves_per_simd, refill_min=t.refill_min,
+                                    chunk=t.chunk, tally_mode=t.tally_mode),
                         deposits_per_history=st.n_deposits / n,
                         crossings_per_history=st.n_crossings / n,
                         sigma_paper=L.ctd_sigma(ctx, c.cs, L.CTD_SIGMA_PAPER, 0.2))
@@ -165,15 +172,35 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
                          ("water_box_bowtie", lambda: bow, {}),
                          ("water_box_bowtie_metropolis_hastings", lambda: bow_mh, {})]:
         log(f"extensions: {name}")
-        out[name] = timed_run(mk(), n_hist, **kw)
+        out[name] = timed_run(name, mk(), n_hist, **kw)
+
+    # tally contention: the pencil beam into the 32^3 water cube concentrates
+    # deposits on the beam axis; one shared tally vs one copy per XCD
+    tw = W.tiny(n_histories=n_hist)
+    modes = {}
+    for tm in (0, 1):
+        with Case(ctx, tw) as c:
+            try:
+                L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(256, 4, 16, 1024, tm))
+            except L.CtdError:
+                continue          # no per-XCD tallies on this device
+            L.ctd_run(ctx, c.cs, 10_000_000)
+            L.ctd_case_reset(ctx, c.cs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L.ctd_run(ctx, c.cs, n_hist)
+            torch.cuda.synchronize()
+            modes[f"tally_mode_{tm}"] = n_hist / (time.perf_counter() - t0)
+    out["tiny_pencil_beam_histories_per_s"] = modes
 
     # the head to 1 % sigma (local, D > 0.5 D_max), batches of 1e8, with the
     # paper's global majorant and with macro-cell majorants
-    for name, kw in [("head_time_to_1pct_sigma", {}),
-                     ("head_time_to_1pct_sigma_macro_tracking", macro)]:
+    for name, kw, key in [("head_time_to_1pct_sigma", {}, "head"),
+                          ("head_time_to_1pct_sigma_macro_tracking", macro,
+                           "head_macro_tracking")]:
         log(f"extensions: {name}")
         with Case(ctx, hw, **kw) as c:
-            L.ctd_set_tuning(ctx, c.cs, tuning)
+            L.ctd_set_tuning(ctx, c.cs, tuned.get(key, tuning))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sig = L.ctd_run_to_sigma(ctx, c.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, 100_000_000,
@@ -188,7 +215,7 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with Case(ctx, wl) as c:
-        L.ctd_set_tuning(ctx, c.cs, tuning)
+        L.ctd_set_tuning(ctx, c.cs, tuned.get("water_box_bowtie", tuning))
         L.ctd_run(ctx, c.cs, wl.n_histories)
         dose, _ = c.dose()
         T = time.perf_counter() - t0

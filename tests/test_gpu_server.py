@@ -56,6 +56,13 @@ def _solo(ctx, wl):
 def test_server_results_identical_to_solo(ctx):
     say("server vs solo")
     wls = _requests(5)
+    # model variants ride the same rounds: macro-cell tracking, an Alg. A1
+    # fluence map, bound-electron Compton
+    wls[1].tracking = L.CTD_TRACK_MACRO
+    g = wls[2].geometry
+    g["fluence"] = W.bowtie_fluence(32, 24, (g["a1"] - g["a0"]) / 2, (g["b1"] - g["b0"]) / 2)
+    g["fluence_chains"] = 64
+    wls[3].compton = "wh"
     solo = [_solo(ctx, wl) for wl in wls]
     sv = L.ctd_server_start(0, _cfg())
     inputs = [Inputs(ctx, wl) for wl in wls]
