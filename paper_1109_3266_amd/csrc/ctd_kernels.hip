@@ -199,6 +199,11 @@ struct Photon {
   uint32_t hlo, hhi;  // history id
   uint32_t k;         // Woodcock step counter; bit 31 = has scattered
   uint32_t seq;       // event sequence (debug log only)
+  // MACRO tracking: a flight (optical depth tau to spend) may span several
+  // calls; its random words for the collision and its current cell persist
+  float tau;            // < 0: no flight in progress
+  uint32_t ry, rz, rw;
+  uint32_t cell;        // x | y << 10 | z << 20; all ones: take it from the position
 };
 
 constexpr uint32_t kScatBit = 0x80000000u;
@@ -289,6 +294,7 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
   p.hhi = (uint32_t)(h >> 32);
   p.k = 0;
   p.seq = 0;
+  p.tau = -1.0f;
   const uint4 r = philox10(0u, p.hlo, p.hhi, 0u, S.key0, S.key1);
   const float E = fmaf(unif(r.x), G.bin_width, G.bin_lo[j]);
   float sx, sy, sz, dx, dy, dz;
@@ -489,35 +495,57 @@ __device__ __forceinline__ float face_dist(float x, float D, float lo, float hi)
   return fmaxf((b - x) * __builtin_amdgcn_rcpf(D), 0.0f);
 }
 
-// One Woodcock step with the macro-cell majorant (MACRO tracking): the
-// optical depth tau = -ln(u0) is spent cell by cell along the ray; a
-// boundary crossing draws no random number.  The number of crossings of one
-// step is bounded by the cells per axis summed (each moves one cell along the
-// direction of travel), and the guard below enforces it.
+// Woodcock tracking with the macro-cell majorant (MACRO tracking).  A flight
+// draws its random block (step k) and spends the optical depth tau = -ln(u0)
+// cell by cell along the ray; a boundary crossing draws no random number.  A
+// call takes at most kMacroCrossings cells and then hands the flight on to
+// the next call (tau, the block's remaining words and the cell are kept in
+// the photon), so the lanes of a wave advance in similar strides instead of
+// all waiting for the longest flight.  Termination: a flight's cell index
+// moves one cell per crossing along the direction of travel, so it leaves the
+// grid or collides within the cells per axis summed; every call takes at
+// least one crossing or ends the flight.
+constexpr int kMacroCrossings = 4;
+
 template <bool LOG>
 __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const CaseDev &G,
                                            const LOCAL uint2 *pal, Counters &c) {
-  p.k += 1;
-  const uint32_t k = p.k & ~kScatBit;
-  if (k > kStepGuard) {
-    c.add(ACC_STEP_GUARD, 1);
-    c.add(ACC_N_STEPS, k);
-    return false;
+  if (p.tau < 0.0f) {  // a new flight
+    p.k += 1;
+    const uint32_t k0 = p.k & ~kScatBit;
+    if (k0 > kStepGuard) {
+      c.add(ACC_STEP_GUARD, 1);
+      c.add(ACC_N_STEPS, k0);
+      return false;
+    }
+    const uint4 r = philox10(k0, p.hlo, p.hhi, 0u, S.key0, S.key1);
+    p.tau = -__log2f(unif(r.x)) * 0.69314718055994531f;
+    p.ry = r.y;
+    p.rz = r.z;
+    p.rw = r.w;
+    p.cell = 0xFFFFFFFFu;
   }
-  const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
-  float tau = -__log2f(unif(r.x)) * 0.69314718055994531f;
+  const uint32_t k = p.k & ~kScatBit;
+  float tau = p.tau;
   const int ncx = G.mc_nx, ncy = G.mc_ny, ncz = G.mc_nz;
   const float fcs = G.mc_fcs;
   const float Dx = p.ux * S.inv_dx, Dy = p.uy * S.inv_dy, Dz = p.uz * S.inv_dz;
-  int cx = min((int)(p.px * G.mc_inv_cs), ncx - 1);
-  int cy = min((int)(p.py * G.mc_inv_cs), ncy - 1);
-  int cz = min((int)(p.pz * G.mc_inv_cs), ncz - 1);
+  int cx, cy, cz;
+  if (p.cell == 0xFFFFFFFFu) {
+    cx = min(max((int)(p.px * G.mc_inv_cs), 0), ncx - 1);
+    cy = min(max((int)(p.py * G.mc_inv_cs), 0), ncy - 1);
+    cz = min(max((int)(p.pz * G.mc_inv_cs), 0), ncz - 1);
+  } else {
+    cx = (int)(p.cell & 1023u);
+    cy = (int)((p.cell >> 10) & 1023u);
+    cz = (int)(p.cell >> 20);
+  }
   const GLOBAL uint16_t *cls = (const GLOBAL uint16_t *)G.mc_cls;
   const GLOBAL float *tab = (const GLOBAL float *)G.mc_tab + p.je;
-  int guard = ncx + ncy + ncz + 2;
   uint32_t crossings = 0;
-  float mu_c;
-  for (;;) {
+  float mu_c = 0.0f;
+  bool hit = false;
+  for (int it = 0; it < kMacroCrossings; ++it) {
     const int id = cls[(cz * ncy + cy) * ncx + cx];
     const GLOBAL float *row = tab + (size_t)id * (size_t)S.ne;
     mu_c = lerpf(row[0], row[1], p.we);
@@ -526,7 +554,10 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
     const float ty = face_dist(p.py, Dy, y0, fminf(y0 + fcs, S.fny));
     const float tz = face_dist(p.pz, Dz, z0, fminf(z0 + fcs, S.fnz));
     const float d = fminf(tx, fminf(ty, tz));
-    if (tau < mu_c * d) break;  // tentative collision inside this cell
+    if (tau < mu_c * d) {  // tentative collision inside this cell
+      hit = true;
+      break;
+    }
     tau -= mu_c * d;
     p.px = fmaf(d, Dx, p.px);
     p.py = fmaf(d, Dy, p.py);
@@ -545,16 +576,17 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
     }
     if (out) {
       c.add(ACC_N_CROSS, crossings);
+      p.tau = -1.0f;
       return escape<LOG>(p, G, c, k);
-    }
-    if (--guard < 0) {
-      c.add(ACC_STEP_GUARD, 1);
-      c.add(ACC_N_STEPS, k);
-      c.add(ACC_N_CROSS, crossings);
-      return false;
     }
   }
   if (crossings) c.add(ACC_N_CROSS, crossings);
+  if (!hit) {  // the flight goes on in the next call, from this cell
+    p.tau = tau;
+    p.cell = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
+    return true;
+  }
+  p.tau = -1.0f;
   const float s = tau * __builtin_amdgcn_rcpf(mu_c);
   p.px = fmaf(s, Dx, p.px);
   p.py = fmaf(s, Dy, p.py);
@@ -566,7 +598,7 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
   const int iz = min(max((int)p.pz, cz * cs), min(cz * cs + cs, (int)S.fnz) - 1);
   const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)iz, (uint32_t)S.ny) + (uint32_t)iy,
                                          (uint32_t)S.nx) + ix;
-  return interact<LOG>(p, S, G, pal, c, r, k, vox, mu_c);
+  return interact<LOG>(p, S, G, pal, c, make_uint4(0u, p.ry, p.rz, p.rw), k, vox, mu_c);
 }
 
 // ------------------------------------------------------- transport kernel

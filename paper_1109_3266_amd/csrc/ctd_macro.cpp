@@ -58,8 +58,10 @@ int ctd::build_macro(ctd_ctx *ctx, ctd_case *cs) {
   int n[3];
   const int64_t cells = macro_cells(g, cell, n);
   const int M = cs->ms->M;
-  if (n[0] > 65535 || n[1] > 65535 || n[2] > 65535 || cells * M > ((int64_t)1 << 31))
-    return set_err(ctx, CTD_EINVAL, "too many macro cells: raise macro_cell");
+  // the transport packs a cell index as x | y << 10 | z << 20
+  if (n[0] > 1023 || n[1] > 1023 || n[2] > 4095 || cells * M > ((int64_t)1 << 31))
+    return set_err(ctx, CTD_EINVAL, "too many macro cells (%d x %d x %d): raise macro_cell",
+                   n[0], n[1], n[2]);
   unsigned int *d_max = nullptr;
   // whole 8-byte words, so the clearing kernel covers every entry
   const size_t bytes = (sizeof(unsigned int) * (size_t)(cells * M) + 7) & ~(size_t)7;
