@@ -80,3 +80,27 @@ def test_server_start_without_device_fails_cleanly():
     bad = L.ctd_server_config()   # zero batch size
     h = ctypes.c_void_p()
     assert L.lib().ctd_server_start(0, ctypes.byref(bad), ctypes.byref(h)) == L.CTD_EINVAL
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    """Every ctypes mirror has the size and field offsets gcc gives the C
+    struct of include/ctd.h (a drifted mirror would corrupt calls silently)."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = tmp_path / "abi_layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"),
+                    os.path.join(root, "tests", "native", "abi_layout.c"), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    n = 0
+    for line in out.splitlines():
+        name, val = line.rsplit(" ", 1)
+        if name.endswith(" size"):
+            cls = getattr(L, name[:-5])
+            assert ctypes.sizeof(cls) == int(val), name
+        else:
+            struct, field = name.split(".")
+            assert getattr(getattr(L, struct), field).offset == int(val), name
+        n += 1
+    assert n > 40
