@@ -54,17 +54,23 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(workload: str, launch_histories: int):
-    """HBM bytes per transport launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def load_counters(workload: str):
+    """The committed rocprofv3 counter summary of the transport kernel on
+    this workload, if it was taken on the current kernel source; else None."""
     p = os.path.join(ROOT, "profiles", f"k_transport_{workload}_pmc.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_sha") != kernel_source_hash():
+    return d if d.get("kernel_sha") == kernel_source_hash() else None
+
+
+def load_traffic(workload: str, launch_histories: int):
+    """HBM bytes per transport launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed counter summary, or None."""
+    d = load_counters(workload)
+    if d is None:
         return None
-    per_hist = d["hbm_bytes_per_launch"] / d["histories_per_launch"]
-    return per_hist * launch_histories
+    return d["hbm_bytes_per_launch"] / d["histories_per_launch"] * launch_histories
 
 
 def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
@@ -448,6 +454,16 @@ def main():
     alg_bytes = 5.0 * d_steps + 8.0 * d_dep
     atom_rate = d_dep / args.steps / (launch_ms * 1e-3)
     atom_peak, _ = L.ctd_microbench(ctx, 1, wl.n_voxels * 8, 1 << 28)
+    counters = load_counters(args.workload) if tracking == L.CTD_TRACK_GLOBAL else None
+    valu = None
+    if counters is not None and "valu" in counters:
+        v = counters["valu"]
+        # issue-bound time: a wave64 VALU instruction occupies a SIMD 4 cycles
+        t_issue = v["sq_insts_valu_per_launch"] * 4 / (256 * 4 * 2.4e9)
+        valu = dict(busy_pct=v["valu_busy_pct"], utilization_pct=v["valu_utilization_pct"],
+                    insts_per_history=v["sq_insts_valu_per_launch"] / counters["histories_per_launch"],
+                    issue_bound_ms=t_issue * 1e3, frac=t_issue / (launch_ms * 1e-3),
+                    source="rocprofv3 VALUBusy, VALUUtilization, SQ_INSTS_VALU (profiles/)")
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_LANE_OPS / 1e12,
                 unit="T lane-ops/s", frac=achieved / PEAK_LANE_OPS, traffic=traffic,
                 kernel="k_transport", launch_ms=launch_ms,
@@ -458,6 +474,7 @@ def main():
                          peak=8000.0, unit="GB/s",
                          frac=alg_bytes / args.steps / (launch_ms * 1e-3) / 8e12,
                          bytes_per_history=alg_bytes / n_timed),
+                valu=valu,
                 atomic=dict(achieved=atom_rate, peak=atom_peak, unit="int64 atomics/s",
                             frac=atom_rate / atom_peak,
                             peak_source="ctd_microbench random 64-bit atomics into a "
