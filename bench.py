@@ -93,9 +93,23 @@ def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
         if not adaptive or dt >= 0.5 * target_s:
             break
         n_hist = int(min(n_hist * target_s / dt, 4e8)) // 10 * 10
+    # one thread on a small sample, for the per-core rate
+    n1 = max(10, int(r["n_hist"] / dt / threads * 1.0) // 10 * 10)
+    t0 = time.perf_counter()
+    O.run(O.OracleCase(wl), n_histories=n1, n_batches=10, threads=1)
+    rate1 = n1 / (time.perf_counter() - t0)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return dict(value=r["n_hist"] / dt, unit="histories/s", cores=threads, kind="oracle",
                 sample=f"{n_hist:.0e} histories of the same workload, 10 batches, "
-                       f"FP64 CPU oracle, {threads} threads, {dt:.1f} s"), r
+                       f"FP64 CPU oracle, {threads} threads, {dt:.1f} s",
+                single_thread_histories_per_s=rate1, host_cpus=os.cpu_count(),
+                cpu_model=model), r
 
 
 def batched_leg(ctx, L, W, Case, tuning, torch, hist_scale):
@@ -525,6 +539,9 @@ def main():
     if not args.no_cpu:
         log("cpu baseline")
         cb, _ = cpu_baseline(wl, args.cpu_histories)
+        tts = out.get("time_to_1pct_sigma")
+        if tts:   # the oracle would need the same histories to reach 1 % sigma
+            cb["time_to_1pct_sigma_s_extrapolated"] = tts["histories"] / cb["value"]
         out["cpu_baseline"] = cb
     L.ctd_destroy(ctx)
     print(json.dumps(out), flush=True)
