@@ -36,7 +36,8 @@ WORKLOADS = {
 BATCH = 100_000_000
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes/clk x 2.4 GHz (non-packed)
 
-# Algorithmic 32-bit lane operations per unit of work:
+# Algorithmic 32-bit lane operations per unit of work (counted from the kernel's
+# arithmetic; the roofline figure divides their sum by the launch time):
 OPS_STEP = 132       # Philox block 100, 2 uniforms 6, free path 2, move 3, inside 6,
                      # voxel index 5, two table lerps + cumulative 7, selection 3
 OPS_SCATTER = 46     # 2 uniforms 6, bilinear surface 12, rotation 28
