@@ -89,3 +89,36 @@ def test_gamma_gpu_dose_vs_oracle_dose(ctx):
     assert nr == nr_o and abs(npass - np_o) <= 1
     say(f"  P_gamma {npass / nr:.4f} over {nr} voxels")
     assert npass / nr >= 0.95
+
+
+def test_fig6_profiles_gpu_vs_oracle(ctx):
+    """The Fig. 6 presentation of the bow-tie water case: depth dose and the
+    two lateral profiles at 3 cm depth from the GPU agree with the oracle's
+    within their 2-sigma bands, the bow-tie profile falls off towards the
+    field edge faster than the profile along the other field direction, and
+    the report's gamma pass rate matches the direct call."""
+    from paper_1109_3266_amd import dose_report as R
+    wl = W.water_box_bowtie(scale=2, n_histories=4_000_000)
+    say("Fig. 6 profiles, water box bow-tie /2")
+    with Case(ctx, wl) as c:
+        c.run(wl.n_histories)
+        dg, vg = c.dose()
+    oc = O.OracleCase(wl)
+    r = O.run(oc, threads=8)
+    do, so = O.dose_and_sigma(r, oc, wl.n_histories)
+    shape = wl.rho.shape
+    pg = R.fig6_profiles(dg.reshape(shape), np.sqrt(vg).reshape(shape), wl.grid, wl.geometry)
+    po = R.fig6_profiles(do.reshape(shape), so.reshape(shape), wl.grid, wl.geometry)
+    for key in ("depth", "lateral_a", "lateral_b"):
+        _, a, sa = pg[key]
+        _, b, sb = po[key]
+        m = b > 0.2
+        ok = np.abs(a - b)[m] <= np.hypot(sa, sb)[m] + 1e-12
+        say(f"  {key}: {ok.mean():.3f} of {m.sum()} points within 2 sigma")
+        assert ok.mean() >= 0.95
+    t, va, _ = pg["lateral_a"]
+    tb, vb, _ = pg["lateral_b"]
+    ia, ib = np.argmin(np.abs(t - 8.0)), np.argmin(np.abs(tb - 8.0))
+    assert va[ia] / va[len(t) // 2] < vb[ib] / vb[len(tb) // 2]
+    rate, nr = R.gamma_pass_rate(ctx, wl.grid, do.reshape(shape), dg.reshape(shape))
+    assert nr > 0 and rate >= 0.95
