@@ -397,6 +397,36 @@ def test_full_size_head_grid_sampled(ctx):
     assert frac >= 0.99
 
 
+@pytest.mark.parametrize("variant", ["head_helical", "head_bound_compton", "water_box_bowtie",
+                                     "water_box_bowtie_chains"])
+def test_full_size_variants_sampled(ctx, variant):
+    """The model variants at their full benchmark sizes: exact balance and
+    1000 logged histories paired one by one with the oracle."""
+    h0, nh = 77_777_777, 1000
+    if variant == "head_helical":
+        wl = W.head_helical(n_histories=200_000_000)
+    elif variant == "head_bound_compton":
+        wl = W.head(n_histories=200_000_000)
+        wl.compton = "wh"
+    else:
+        wl = W.water_box_bowtie()                 # 2.5e8 histories, as in Table 1
+        if variant.endswith("chains"):
+            wl.geometry["fluence_chains"] = 1 << 16
+            h0 = 3_000_000                        # the oracle advances the chains to it
+    say(f"full-size {variant} {wl.n_histories:.2e}")
+    g = gpu_run(ctx, wl, log=(h0, nh, 100_000))
+    check_balance(g, wl.n_histories)
+    oc = O.OracleCase(wl)
+    if variant.endswith("chains"):
+        O.mh_advance(oc, h0 + nh)
+    bs = O.batch_sizes(wl.n_histories, 10)
+    hs = range(h0, h0 + nh)
+    by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
+    frac = _pair_histories(g["log"], by_h, hs)
+    say(f"{variant} pairing {frac:.4f}")
+    assert frac >= 0.99
+
+
 def test_microbenchmarks_report_sane_rates(ctx):
     say("microbenchmarks")
     copy, _ = L.ctd_microbench(ctx, 0, 256 << 20)
