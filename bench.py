@@ -51,8 +51,15 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel source's code: comment-only and blank lines and
+    trailing // comments do not count as a change of the kernel."""
     p = os.path.join(ROOT, "paper_1109_3266_amd", "csrc", "ctd_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    code = []
+    for line in open(p, encoding="utf-8"):
+        s = line.split("//", 1)[0].rstrip()
+        if s:
+            code.append(s)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
 def load_counters(workload: str):

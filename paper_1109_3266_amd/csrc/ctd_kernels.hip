@@ -1,7 +1,10 @@
 // HIP kernels for gfx950 (MI355X): Woodcock photon transport (Jia et al.,
-// arXiv 1109.3266, Sec. 2.1-2.2), batch fold and sigma-bar reduction.
+// arXiv 1109.3266, Sec. 2.1-2.2), batch fold and sigma-bar reduction,
+// Metropolis-Hastings beamlet chains (Alg. A1), macro-cell set-up and
+// microbenchmarks.
 //
-// Execution model.  One persistent launch per round.  A round is, for each
+// Execution model.  One persistent launch per round (per tracking mode: the
+// global-majorant and macro-cell steps are separate instantiations).  A round is, for each
 // participating case, one batch of histories laid out bin-major over the
 // spectrum (Sec. 2.2.5), split into chunks of consecutive history ids.  Each
 // 64-lane wave owns one case at a time and a pool of history ids claimed one
@@ -17,7 +20,10 @@
 // exactly and incident = deposited + escaped holds exactly in q units.
 // Random numbers: Philox4x32-10 keyed by the case seed, counter (step k,
 // history id lo, hi, 0); k = 0 draws the source, step k >= 1 draws
-// (free path, interaction type, polar zeta, azimuth).
+// (free path, interaction type, polar zeta, azimuth).  Two more streams use
+// the fourth counter word: (0, h lo, h hi, 1) the fluence-map beamlet of
+// history h (inverse CDF, or trial and acceptance of Alg. A1), and
+// (0, c, 0, 2) the starting beamlet of Metropolis-Hastings chain c.
 #include <hip/hip_runtime.h>
 
 #include "ctd_internal.h"
