@@ -12,6 +12,13 @@
  * locally; histories run in batches whose spread gives the per-voxel
  * statistical uncertainty (Sec. 2.2.1).
  *
+ * Options beside the plain method: bound-electron Compton (one C surface per
+ * material, Eq. 2 with S), a helical CT trajectory, a fluence map over the
+ * field (Sec. 2.2.4: exact inverse CDF, or Alg. A1 Metropolis-Hastings
+ * chains), macro-cell majorants for Woodcock tracking (CTD_TRACK_MACRO), a
+ * batched multi-case engine, a continuous-batching dose server, and the
+ * gamma-index comparison of Sec. 3.1.
+ *
  * Conventions
  *   - Every call returns an int32 status (CTD_OK or a negative CTD_E* code);
  *     ctd_last_error() gives a message for the last failing call on a ctx.
