@@ -658,3 +658,34 @@ def test_metropolis_hastings_transport_and_guards():
         O.sample_source(O.OracleCase(wl), 0, 0)  # chains not advanced
     with pytest.raises(ValueError):
         _mh_case([[1.0, 0.0]], chains=4)
+
+
+# ---------------- P13: readout (dose units, sigma-bar) ----------------
+
+def test_dose_units_and_standard_error_by_hand():
+    """One voxel of 1 g receiving 3, 5, 4, 8 keV in four batches of 10
+    histories each: dose per history = (20 keV / 40) in J/kg, and its standard
+    error = sd of the four batch means / sqrt(4)."""
+    wl = slab_workload([("water", 1.0, 1)], nxy=1, dz=1.0, dxy=1.0, n_hist=40)
+    c = O.OracleCase(wl)
+    q = 2 ** 24
+    batches = np.array([3, 5, 4, 8])
+    tallies = batches * q
+    res = dict(n_batches=4, s1=np.array([tallies.sum()], np.int64),
+               s2_hi=np.array([0], np.uint64),
+               s2_lo=np.array([int((tallies.astype(object) ** 2).sum())], np.uint64))
+    dose, sd = O.dose_and_sigma(res, c, 40)
+    kev = 1.602176634e-16
+    assert dose[0] == pytest.approx(20.0 / 40 * kev / 1e-3, rel=1e-14)
+    per_hist = batches / 10.0                     # keV per history in each batch
+    assert sd[0] == pytest.approx(np.std(per_hist, ddof=1) / 2 * kev / 1e-3, rel=1e-12)
+
+
+def test_sigma_bar_definitions_by_hand():
+    dose = np.array([10.0, 6.0, 1.0, 4.0, 12.0])
+    sd = np.array([1.0, 1.5, 0.5, 1.0, 3.0])
+    rho = np.array([1.0, 1.0, 1.0, 1.0, 0.01])      # the last voxel is air: not inside
+    # inside: D_max = 10; paper: D > 2 -> {10, 6, 4}: mean(1, 1.5, 1) / 10
+    assert O.sigma_bar(dose, sd, rho, "paper") == pytest.approx((1 + 1.5 + 1) / 3 / 10)
+    # local: D > 5 -> {10, 6}: mean(1/10, 1.5/6)
+    assert O.sigma_bar(dose, sd, rho, "local") == pytest.approx((0.1 + 0.25) / 2)
