@@ -201,12 +201,15 @@ typedef struct {
 
 /* Create a context on HIP device `device`.  CTD_EDEVICE if it does not exist. */
 int32_t ctd_create(ctd_ctx **out, int32_t device);
-/* Destroy the context (waits for its stream, frees what it owns). */
+/* Destroy the context (waits for its stream, frees its own buffers).  Cases,
+ * phantoms, material sets, spectra and geometries created on it must be
+ * released first. */
 int32_t ctd_destroy(ctd_ctx *ctx);
 /* Message of the last failing call on ctx (valid until the next call). */
 const char *ctd_last_error(const ctd_ctx *ctx);
 /* Enqueue all further work on the caller's hipStream_t (borrowed, never
- * destroyed); NULL restores the context's own stream. */
+ * destroyed); NULL restores the context's own stream.  Waits for the work
+ * already enqueued on the current stream first. */
 int32_t ctd_set_stream(ctd_ctx *ctx, void *hip_stream);
 
 /* ---------------- inputs ----------------

@@ -121,6 +121,9 @@ extern "C" const char *ctd_last_error(const ctd_ctx *ctx) {
 
 extern "C" int32_t ctd_set_stream(ctd_ctx *ctx, void *hip_stream) {
   if (!ctx) return CTD_EINVAL;
+  // work already enqueued finishes before anything goes to the new stream
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ctx->stream = hip_stream ? (hipStream_t)hip_stream : ctx->own;
   return CTD_OK;
 }
