@@ -203,10 +203,11 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
         out[name] = timed_run(name, mk(), n_hist, **kw)
 
     # tally contention: the pencil beam into the 32^3 water cube concentrates
-    # deposits on the beam axis; one shared tally vs one copy per XCD
+    # deposits on the beam axis; one shared tally, one copy per XCD, and the
+    # copies behind per-wave LDS sub-tallies
     tw = W.tiny(n_histories=n_hist)
     modes = {}
-    for tm in (0, 1):
+    for tm in (0, 1, 2):
         with Case(ctx, tw) as c:
             try:
                 L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(256, 4, 16, 1024, tm))

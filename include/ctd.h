@@ -183,7 +183,14 @@ typedef struct {
   int32_t tally_mode;    /* 0: one batch tally, device-scope atomics;
                             1: one batch tally per XCD, updated with L2-resident
                             atomics by the waves of that XCD and summed by the
-                            fold (only where every XCD id is < 8) */
+                            fold (only where every XCD id is < 8);
+                            2: as 1, behind a 512-slot LDS sub-tally per wave
+                            (a voxel's slot is kept by the first voxel that
+                            takes it until the wave changes case; the rest go
+                            to the XCD tally); 6 KB of LDS per wave, rejected
+                            where the workgroup would exceed the LDS limit.
+                            Tallies are integer sums: every mode gives the
+                            same bits. */
 } ctd_tuning;
 
 /* Deposit/event record of the debug log (test use). type: 0 source, 1

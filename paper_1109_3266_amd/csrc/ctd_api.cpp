@@ -772,7 +772,7 @@ static bool tuning_ok(const ctd_tuning &t) {
   return (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
          t.waves_per_simd >= 1 && t.waves_per_simd <= 8 && t.refill_min >= 1 &&
          t.refill_min <= 64 && t.chunk >= 64 && t.chunk <= 65536 &&
-         (t.tally_mode == 0 || t.tally_mode == 1);
+         t.tally_mode >= 0 && t.tally_mode <= 2;
 }
 
 int ctd::ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies) {
@@ -828,7 +828,9 @@ extern "C" int32_t ctd_set_tuning(ctd_ctx *ctx, ctd_case *cs, const ctd_tuning *
   NEED(ctx, t->tally_mode == 0 || ctx->xcd_tally_ok,
        "per-XCD tallies unavailable: XCC id %u >= %d", ctx->max_xcc, kTallyCopies);
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  if (t->tally_mode == 1) {
+  NEED(ctx, transport_lds_fits(t->block, t->tally_mode, ctx->device),
+       "tally_mode %d with %d-thread workgroups exceeds the LDS limit", t->tally_mode, t->block);
+  if (t->tally_mode != 0) {
     int rc = ensure_tally_copies(ctx, cs, kTallyCopies);
     if (rc != CTD_OK) return rc;
   }
@@ -951,7 +953,7 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     if (n[i] == 0) continue;
     int rc0 = check_headroom(ctx, cases[i], n[i]);
     if (rc0 != CTD_OK) return rc0;
-    if (t.tally_mode == 1 && cases[i]->tally_copies < kTallyCopies) {
+    if (t.tally_mode != 0 && cases[i]->tally_copies < kTallyCopies) {
       rc0 = ensure_tally_copies(ctx, cases[i], kTallyCopies);
       if (rc0 != CTD_OK) return rc0;
     }
@@ -1403,7 +1405,8 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
     return rc;
   }
   std::vector<ctd_tuning> cand;
-  for (int tm = ctx->xcd_tally_ok ? 1 : 0; tm >= 0; --tm)
+  for (int tm = ctx->xcd_tally_ok ? 2 : 0; tm >= 0; --tm) {
+    if (!transport_lds_fits(256, tm, ctx->device)) continue;
     for (int wps : {2, 4, 8})
       for (int rm : {8, 16, 32})
         for (int ch : {256, 1024}) {
@@ -1415,6 +1418,7 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
           t.tally_mode = tm;
           cand.push_back(t);
         }
+  }
   hipEvent_t a, b;
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
@@ -1445,7 +1449,7 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
   (void)hipStreamSynchronize(ctx->stream);
   release();
   if (rc != CTD_OK) return rc;
-  if (best_t.tally_mode == 1 && (rc = ensure_tally_copies(ctx, cs, kTallyCopies)) != CTD_OK)
+  if (best_t.tally_mode != 0 && (rc = ensure_tally_copies(ctx, cs, kTallyCopies)) != CTD_OK)
     return rc;
   cs->tune = best_t;
   if (best) *best = best_t;

@@ -126,6 +126,9 @@ struct LaunchCfg {
 int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
                      bool macro, void *stream);
+// Whether a transport workgroup of `block` threads in tally_mode fits the
+// device's LDS limit (mode 2 adds a sub-tally per wave).
+bool transport_lds_fits(int block, int tally_mode, int device);
 // Fold ncopies batch tallies [ncopies][V]: S1 += sum, S2 += sum^2, zero them;
 // fold the batch counters of acc into its 128-bit totals and record the
 // per-voxel maxima of S1 and of S2's high word.

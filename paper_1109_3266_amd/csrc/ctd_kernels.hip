@@ -43,6 +43,12 @@ namespace ctd {
 
 // ---------------------------------------------------------------- helpers
 
+// Tally mode 2: per-wave LDS sub-tally of 2^kCacheBits slots (int32 key +
+// uint64 value each, 6 KB per wave), in dynamic shared memory.
+constexpr int kCacheBits = 9;
+constexpr int kCacheSlots = 1 << kCacheBits;
+constexpr int kCacheBytesPerWave = kCacheSlots * (8 + 4);
+
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
   uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
@@ -112,7 +118,10 @@ struct StepCase {
   GLOBAL unsigned long long *tally;
   float fnx, fny, fnz, inv_dx, inv_dy, inv_dz, e0, inv_de, e_cut;
   int32_t nx, ny, ne, nzc, nzr, rayleigh, comp_per_mat, npal;
-  int32_t tally_l2;  // 1: this XCD's private tally, atomics performed in its L2
+  // tally mode 2: the wave's LDS sub-tally (slot keys = voxel or -1, values);
+  // null in modes 0 and 1
+  LOCAL int32_t *ckeys;
+  LOCAL unsigned long long *cvals;
   uint32_t key0, key1;
 };
 
@@ -136,7 +145,10 @@ __device__ __forceinline__ int32_t uniform_i(int32_t x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
-__device__ __forceinline__ StepCase make_step_case(const CaseDev &c, int tally_mode) {
+// tally_mode 0: the case's tally; 1, 2: this XCD's copy of it; cache: the
+// wave's LDS sub-tally (mode 2) or null.
+__device__ __forceinline__ StepCase make_step_case(const CaseDev &c, int tally_mode,
+                                                   LOCAL unsigned char *cache) {
   StepCase s;
   s.vox = uniform_ptr(c.vox);
   s.vox8 = uniform_ptr(c.vox8);
@@ -146,8 +158,9 @@ __device__ __forceinline__ StepCase make_step_case(const CaseDev &c, int tally_m
   s.comp_quad = uniform_ptr(c.comp_quad);
   s.rayl_quad = uniform_ptr(c.rayl_quad);
   s.tally = uniform_ptr(c.tally);
-  s.tally_l2 = tally_mode;
   if (tally_mode) s.tally += (size_t)xcc_id() * (size_t)uniform_i((int32_t)c.V);
+  s.cvals = (LOCAL unsigned long long *)cache;
+  s.ckeys = cache ? (LOCAL int32_t *)(cache + kCacheSlots * 8) : nullptr;
   s.fnx = uniform_f(c.fnx);
   s.fny = uniform_f(c.fny);
   s.fnz = uniform_f(c.fnz);
@@ -192,6 +205,42 @@ __device__ void flush(Counters &c, unsigned long long *acc, int lane, uint32_t r
     const unsigned long long v = atomicExch(c.s + lane, 0ull);
     if (v) atomic_add_u64(acc + lane, v);
   }
+}
+
+// Device scope in every tally mode: a per-XCD copy is only updated by waves of
+// its XCD, but those belong to many workgroups (on gfx950 both scopes give the
+// same atomic instruction, performed at the memory side).
+__device__ __forceinline__ void tally_add(const StepCase &S, int32_t vox, unsigned long long q) {
+  __hip_atomic_fetch_add(S.tally + vox, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tally mode 2: add the wave's LDS sub-tally to the case's tally and empty it
+// (called by the whole wave, before it changes case and at exit).
+__device__ void flush_cache(const StepCase &S, int lane) {
+  if (!S.ckeys) return;
+  for (int i = lane; i < kCacheSlots; i += 64) {
+    const int32_t key = S.ckeys[i];
+    if (key >= 0) {
+      const unsigned long long v = S.cvals[i];
+      if (v) tally_add(S, key, v);
+      S.ckeys[i] = -1;
+      S.cvals[i] = 0ull;
+    }
+  }
+  // the wave's later deposits (any lane) must see the emptied slots
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ void clear_cache(LOCAL unsigned char *cache, int lane) {
+  LOCAL unsigned long long *v = (LOCAL unsigned long long *)cache;
+  LOCAL int32_t *k = (LOCAL int32_t *)(cache + kCacheSlots * 8);
+  for (int i = lane; i < kCacheSlots; i += 64) {
+    v[i] = 0ull;
+    k[i] = -1;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 struct Photon {
@@ -277,14 +326,25 @@ __device__ __forceinline__ void deposit(const StepCase &S, const CaseDev &G, Pho
                                         float Eafter) {
   const uint32_t q = (uint32_t)(e * kQScale);
   if (q) {
-    // Per-XCD tallies are only touched by waves of one XCD; the single
-    // shared tally needs device scope.
-    if (S.tally_l2)
-      __hip_atomic_fetch_add(S.tally + vox, (unsigned long long)q, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
-    else
-      __hip_atomic_fetch_add(S.tally + vox, (unsigned long long)q, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    bool cached = false;
+    if (S.ckeys) {
+      // LDS sub-tally: the slot of vox belongs to the first voxel that took
+      // it during this wave's case; other voxels go straight to the tally
+      const uint32_t slot = ((uint32_t)vox * 2654435761u) >> (32 - kCacheBits);
+      int32_t owner = S.ckeys[slot];
+      if (owner == -1) {
+        int32_t expected = -1;
+        __hip_atomic_compare_exchange_strong(S.ckeys + slot, &expected, vox, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        owner = expected == -1 ? vox : expected;
+      }
+      if (owner == vox) {
+        __hip_atomic_fetch_add(S.cvals + slot, (unsigned long long)q, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+        cached = true;
+      }
+    }
+    if (!cached) tally_add(S, vox, q);
     c.add(ACC_Q_DEP, q);
   }
   c.add(ACC_N_DEPOSITS, 1);
@@ -657,6 +717,7 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
   __shared__ unsigned long long wave_acc[8][ACC_COUNT];
   __shared__ CaseDev wave_case[8];
   __shared__ uint2 wave_pal[8][256];
+  extern __shared__ unsigned long long cache_lds[];   // tally mode 2: kCacheBytesPerWave per wave
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -677,6 +738,9 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
   Counters cnt;
   cnt.s = wave_acc[w];
   if (lane < ACC_COUNT) cnt.s[lane] = 0ull;
+  LOCAL unsigned char *cache =
+      tally_mode == 2 ? (LOCAL unsigned char *)cache_lds + w * kCacheBytesPerWave : nullptr;
+  if (cache) clear_cache(cache, lane);
   Photon p;
   bool alive = false;
 
@@ -686,12 +750,15 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
     if (ndead == 64 || ndead >= refill_min) {
       // switch to the pending case once the wave has drained
       if (pend >= 0 && ndead == 64 && pool_next >= pool_end) {
-        if (cur >= 0) flush(cnt, G.acc, lane, refills);
+        if (cur >= 0) {
+          flush(cnt, G.acc, lane, refills);
+          flush_cache(S, lane);
+        }
         refills = 0;
         cur = pend;
         pend = -1;
         stage_case(&G, pal, rcs[cur].cd, lane);
-        S = make_step_case(G, tally_mode);
+        S = make_step_case(G, tally_mode, cache);
         pool_next = pend_lo;
         pool_end = pend_hi;
         wbin = find_bin(rcs[cur].prefix, G.nbins, pool_next);
@@ -710,11 +777,14 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
         const uint64_t hi = min(lo + (uint64_t)chunk, rcs[rc].n);
         if (rc == cur || cur < 0 || ndead == 64) {
           if (rc != cur) {
-            if (cur >= 0) flush(cnt, G.acc, lane, refills);
+            if (cur >= 0) {
+              flush(cnt, G.acc, lane, refills);
+              flush_cache(S, lane);
+            }
             refills = 0;
             cur = rc;
             stage_case(&G, pal, rcs[cur].cd, lane);
-            S = make_step_case(G, tally_mode);
+            S = make_step_case(G, tally_mode, cache);
             wbin = find_bin(rcs[cur].prefix, G.nbins, lo);
           }
           pool_next = lo;
@@ -755,7 +825,10 @@ __global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__
         alive = step<LOG>(p, S, G, pal_lds, cnt);
     }
   }
-  if (cur >= 0) flush(cnt, G.acc, lane, refills);
+  if (cur >= 0) {
+    flush(cnt, G.acc, lane, refills);
+    flush_cache(S, lane);
+  }
 }
 
 // MACRO tracking set-up: per cell of cs^3 voxels and material, the largest
@@ -1059,9 +1132,22 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
   hipStream_t s = (hipStream_t)stream;
   auto kern = with_log ? (macro ? k_transport<true, true> : k_transport<true, false>)
                        : (macro ? k_transport<false, true> : k_transport<false, false>);
-  hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.block), 0, s, rc_dev, nrc, total_chunks,
+  const size_t lds = cfg.tally_mode == 2 ? (size_t)(cfg.block / 64) * kCacheBytesPerWave : 0;
+  hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.block), lds, s, rc_dev, nrc, total_chunks,
                      chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode);
   return check_launch();
+}
+
+bool transport_lds_fits(int block, int tally_mode, int device) {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_transport<false, false>)) !=
+      hipSuccess)
+    return false;
+  int lim = 0;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+    return false;
+  const size_t dyn = tally_mode == 2 ? (size_t)(block / 64) * kCacheBytesPerWave : 0;
+  return a.sharedSizeBytes + dyn <= (size_t)lim;
 }
 
 static int grid_for(int64_t n, int block, int cap) {

@@ -159,7 +159,7 @@ static void admit(ctd_server *sv) {
     auto it = sv->phantoms.find(r->phantom_key);
     PhantomEntry &e = it->second;
     const int64_t V = (int64_t)e.g.nx * e.g.ny * e.g.nz;
-    const int copies = sv->cfg.tuning.block && sv->cfg.tuning.tally_mode == 1 ? kTallyCopies : 1;
+    const int copies = sv->cfg.tuning.block && sv->cfg.tuning.tally_mode != 0 ? kTallyCopies : 1;
     const uint64_t case_bytes = case_footprint(e.g, r->geo, r->p, r->ms->eg.ne, copies,
                                                sv->cfg.batch_histories);
     const uint64_t ph_bytes = e.dev ? 0 : (uint64_t)V * 9 + 4096;

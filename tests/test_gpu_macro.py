@@ -111,7 +111,8 @@ def test_macro_deposit_log_replay_and_bit_identity(ctx):
     ends = ev[np.isin(ev["type"], [1, 4, 5, 6])]
     assert np.array_equal(np.sort(ends["h"]), np.arange(20_000))
     outs = [run(ctx, wl, 20_000, tuning=L.ctd_tuning(*t), tracking=MACRO, macro_cell=3)
-            for t in [(256, 4, 16, 256, 0), (512, 2, 64, 4096, 1), (64, 1, 1, 64, 0)]]
+            for t in [(256, 4, 16, 256, 0), (512, 2, 64, 4096, 1), (64, 1, 1, 64, 0),
+                      (256, 4, 16, 1024, 2), (64, 2, 8, 64, 2)]]
     for o in outs:
         assert np.array_equal(o["s1"], g["s1"])
         assert np.array_equal(o["s2_lo"], g["s2_lo"])

@@ -207,6 +207,7 @@ def test_tuning_and_repeat_bit_identity(ctx):
     outs = []
     for blk, wps, rm, ch, tm in [(256, 4, 16, 256, 0), (256, 8, 1, 64, 1), (512, 2, 64, 4096, 1),
                                  (64, 1, 32, 1024, 0), (256, 4, 16, 1024, 1),
+                                 (256, 4, 16, 1024, 2), (128, 8, 8, 64, 2),
                                  (256, 4, 16, 256, 0)]:
         t = L.ctd_tuning(blk, wps, rm, ch, tm)
         outs.append(gpu_run(ctx, wl, tuning=t))
@@ -227,6 +228,46 @@ def test_per_xcd_tallies_available(ctx):
         c.run(100_000)
         b = c.balance()
         assert int(c.tally()[0].sum()) == b.q_deposited
+
+
+def test_lds_sub_tally_identity(ctx):
+    """Tally mode 2 (per-wave LDS sub-tally in front of the per-XCD tallies)
+    gives the same integer tallies as the shared tally: on the pencil beam
+    (deposits concentrated on the axis, slots shared by many lanes), on the
+    cone beam, and in a batched run where waves change case and flush."""
+    say("LDS sub-tally identity")
+    for wl in (W.tiny(n_histories=300_000), W.water_cbct(scale=4, n_histories=200_000)):
+        ref = gpu_run(ctx, wl, tuning=L.ctd_tuning(256, 4, 16, 1024, 0))
+        for t in [(256, 4, 16, 1024, 2), (64, 8, 1, 64, 2)]:
+            g = gpu_run(ctx, wl, tuning=L.ctd_tuning(*t))
+            assert np.array_equal(g["s1"], ref["s1"])
+            assert np.array_equal(g["s2_hi"], ref["s2_hi"])
+            assert np.array_equal(g["s2_lo"], ref["s2_lo"])
+            check_balance(g, wl.n_histories)
+    cases = W.batched(n_cases=5, size_scale=0.2, hist_scale=1e-3)
+    solo = [gpu_run(ctx, wl) for wl in cases]
+    objs = [Case(ctx, wl) for wl in cases]
+    try:
+        for o in objs:
+            L.ctd_set_tuning(ctx, o.cs, L.ctd_tuning(128, 4, 16, 256, 2))
+        L.ctd_run_many(ctx, [o.cs for o in objs], [wl.n_histories for wl in cases])
+        for o, s in zip(objs, solo):
+            s1, hi, lo, nb = o.tally()
+            assert np.array_equal(s1, s["s1"]) and np.array_equal(lo, s["s2_lo"])
+            assert np.array_equal(hi, s["s2_hi"])
+    finally:
+        for o in objs:
+            o.close()
+    # 512-thread workgroups need 48 KB of sub-tallies: accepted or refused by
+    # the LDS limit, never launched beyond it
+    wl = W.tiny(n_histories=50_000)
+    ref = gpu_run(ctx, wl)
+    try:
+        g = gpu_run(ctx, wl, tuning=L.ctd_tuning(512, 2, 16, 1024, 2))
+    except L.CtdError as e:
+        assert "LDS" in str(e)
+    else:
+        assert np.array_equal(g["s1"], ref["s1"])
 
 
 def test_run_many_matches_solo(ctx):
