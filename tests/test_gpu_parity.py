@@ -352,7 +352,7 @@ def test_error_paths(ctx):
         with pytest.raises(L.CtdError):
             L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(100, 4, 16, 256, 0))
         with pytest.raises(L.CtdError):
-            L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(256, 4, 16, 256, 2))
+            L.ctd_set_tuning(ctx, c.cs, L.ctd_tuning(256, 4, 16, 256, 3))
         with pytest.raises(L.CtdError):
             L.ctd_read_dose(ctx, c.cs, c.V)      # no batches folded yet
         c.run(1000)
