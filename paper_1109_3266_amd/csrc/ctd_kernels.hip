@@ -553,14 +553,6 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
   return interact<LOG>(p, S, G, pal, c, r, k, vox, p.mumax);
 }
 
-// Distance (cm) along D (voxel units per cm) from x to the cell face ahead on
-// one axis; infinite when the ray is parallel to it.
-__device__ __forceinline__ float face_dist(float x, float D, float lo, float hi) {
-  if (D == 0.0f) return INFINITY;
-  const float b = D > 0.0f ? hi : lo;
-  return fmaxf((b - x) * __builtin_amdgcn_rcpf(D), 0.0f);
-}
-
 // Woodcock tracking with the macro-cell majorant (MACRO tracking).  A flight
 // draws its random block (step k) and spends the optical depth tau = -ln(u0)
 // cell by cell along the ray; a boundary crossing draws no random number.  A
@@ -608,17 +600,27 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
   }
   const GLOBAL uint16_t *cls = (const GLOBAL uint16_t *)G.mc_cls;
   const GLOBAL float *tab = (const GLOBAL float *)G.mc_tab + p.je;
+  // per axis, fixed for the call: the face the ray leaves a cell by, the
+  // index step, 1/D, and whether the ray moves along the axis at all
+  const bool fx = Dx > 0.0f, fy = Dy > 0.0f, fz = Dz > 0.0f;
+  const bool mx = Dx != 0.0f, my = Dy != 0.0f, mz = Dz != 0.0f;
+  const float rx = __builtin_amdgcn_rcpf(Dx), ry = __builtin_amdgcn_rcpf(Dy),
+              rz = __builtin_amdgcn_rcpf(Dz);
   uint32_t crossings = 0;
   float mu_c = 0.0f;
-  bool hit = false;
+  bool hit = false, out = false;
+#pragma unroll
   for (int it = 0; it < kMacroCrossings; ++it) {
     const int id = cls[(cz * ncy + cy) * ncx + cx];
     const GLOBAL float *row = tab + (size_t)id * (size_t)S.ne;
     mu_c = lerpf(row[0], row[1], p.we);
     const float x0 = (float)cx * fcs, y0 = (float)cy * fcs, z0 = (float)cz * fcs;
-    const float tx = face_dist(p.px, Dx, x0, fminf(x0 + fcs, S.fnx));
-    const float ty = face_dist(p.py, Dy, y0, fminf(y0 + fcs, S.fny));
-    const float tz = face_dist(p.pz, Dz, z0, fminf(z0 + fcs, S.fnz));
+    const float bx = fx ? fminf(x0 + fcs, S.fnx) : x0;
+    const float by = fy ? fminf(y0 + fcs, S.fny) : y0;
+    const float bz = fz ? fminf(z0 + fcs, S.fnz) : z0;
+    const float tx = mx ? fmaxf((bx - p.px) * rx, 0.0f) : INFINITY;
+    const float ty = my ? fmaxf((by - p.py) * ry, 0.0f) : INFINITY;
+    const float tz = mz ? fmaxf((bz - p.pz) * rz, 0.0f) : INFINITY;
     const float d = fminf(tx, fminf(ty, tz));
     if (tau < mu_c * d) {  // tentative collision inside this cell
       hit = true;
@@ -629,24 +631,21 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
     p.py = fmaf(d, Dy, p.py);
     p.pz = fmaf(d, Dz, p.pz);
     ++crossings;
-    bool out;
-    if (tx <= ty && tx <= tz) {
-      cx += Dx > 0.0f ? 1 : -1;
-      out = (unsigned)cx >= (unsigned)ncx;
-    } else if (ty <= tz) {
-      cy += Dy > 0.0f ? 1 : -1;
-      out = (unsigned)cy >= (unsigned)ncy;
-    } else {
-      cz += Dz > 0.0f ? 1 : -1;
-      out = (unsigned)cz >= (unsigned)ncz;
-    }
-    if (out) {
-      c.add(ACC_N_CROSS, crossings);
-      p.tau = -1.0f;
-      return escape<LOG>(p, G, c, k);
-    }
+    // the nearest face, ties to x then y (no branches: one index moves)
+    const bool ax = tx <= ty && tx <= tz;
+    const bool ay = !ax && ty <= tz;
+    cx += ax ? (fx ? 1 : -1) : 0;
+    cy += ay ? (fy ? 1 : -1) : 0;
+    cz += (!ax && !ay) ? (fz ? 1 : -1) : 0;
+    out = (unsigned)cx >= (unsigned)ncx || (unsigned)cy >= (unsigned)ncy ||
+          (unsigned)cz >= (unsigned)ncz;
+    if (out) break;
   }
   if (crossings) c.add(ACC_N_CROSS, crossings);
+  if (out) {
+    p.tau = -1.0f;
+    return escape<LOG>(p, G, c, k);
+  }
   if (!hit) {  // the flight goes on in the next call, from this cell
     p.tau = tau;
     p.cell = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);

@@ -141,11 +141,15 @@ def test_fluence_map_beamlets_bit_exact(ctx, f, chains):
     paired_compare(g, r)
 
 
-@pytest.mark.parametrize("shape,seed", [((2, 2, 2), 3), ((4, 4, 4), 5), ((3, 5, 7), 8)])
-def test_deposit_log_replay_bit_exact(ctx, shape, seed):
-    say(f"log replay {shape}")
+@pytest.mark.parametrize("shape,seed,tally_mode", [((2, 2, 2), 3, 2), ((4, 4, 4), 5, 0),
+                                                   ((3, 5, 7), 8, 1)])
+def test_deposit_log_replay_bit_exact(ctx, shape, seed, tally_mode):
+    """The tally equals the replay of the logged deposits, in each tally mode
+    (the 8-voxel phantom with LDS sub-tallies: every lane shares few slots)."""
+    say(f"log replay {shape} tally_mode {tally_mode}")
     wl = random_phantom(shape, 3, seed=seed, n_hist=10_000)
-    g = gpu_run(ctx, wl, n_batches=2, log=(0, 10_000, 200_000))
+    g = gpu_run(ctx, wl, n_batches=2, log=(0, 10_000, 200_000),
+                tuning=L.ctd_tuning(256, 4, 16, 256, tally_mode))
     ev = g["log"]
     dep = ev[np.isin(ev["type"], [1, 2, 4])]
     T = O.tally_replay(dep["vox"], dep["e"], int(wl.mat.size))
