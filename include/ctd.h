@@ -392,7 +392,8 @@ int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out, uint64_t 
  * round.  Every request follows the batch schedule of ctd_run_to_sigma with
  * the same batch size, so its result is identical alone or among others.
  * Material sets, spectra and geometries may come from any context on the same
- * device and must stay alive until their requests finish. */
+ * device; a request holds them from submission until it finishes (releasing
+ * one earlier returns CTD_EBUSY). */
 typedef struct {
   uint64_t hbm_budget_bytes;  /* device memory for request tallies + resident phantoms */
   uint64_t batch_histories;   /* histories per batch, every request */

@@ -201,6 +201,8 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
     dfree(drho);
     dfree(dstat);
     dfree(ph->vox);
+    dfree(ph->vox8);
+    dfree(ph->palette);
     delete ph;
     return code;
   };

@@ -1138,15 +1138,17 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
 }
 
 bool transport_lds_fits(int block, int tally_mode, int device) {
+  if (tally_mode != 2) return true;  // static LDS only, sized for 512-thread workgroups
   hipFuncAttributes a;
-  if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_transport<false, false>)) !=
-      hipSuccess)
-    return false;
   int lim = 0;
-  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+  if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_transport<false, false>)) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+          hipSuccess) {
+    (void)hipGetLastError();  // not a launch error: leave nothing for check_launch
     return false;
-  const size_t dyn = tally_mode == 2 ? (size_t)(block / 64) * kCacheBytesPerWave : 0;
-  return a.sharedSizeBytes + dyn <= (size_t)lim;
+  }
+  return a.sharedSizeBytes + (size_t)(block / 64) * kCacheBytesPerWave <= (size_t)lim;
 }
 
 static int grid_for(int64_t n, int block, int cap) {

@@ -51,6 +51,7 @@ struct Request {
   ctd_geometry *geo = nullptr;
   ctd_params p{};
   double target = 0.0;
+  bool held = false;  // holds a reference on ms, sp and geo until finished
   int state = 0;   // 0 queued, 1 running, 2 done, 3 cancelled, 4 failed
   int status = CTD_OK;
   bool cancel = false;
@@ -59,6 +60,8 @@ struct Request {
   ctd_case *cs = nullptr;
   uint64_t planned = 0;      // batches the current plan runs to
   uint64_t footprint = 0;    // device bytes of the case
+  // progress, updated by the server thread under the lock (poll reads these,
+  // never the case, which the thread updates unlocked during a round)
   uint64_t histories = 0;
   uint32_t batches = 0;
   // results kept on the host after completion
@@ -143,6 +146,12 @@ static void finish(ctd_server *sv, Request *r, int state, int status) {
     sv->used_bytes -= r->footprint;
     auto it = sv->phantoms.find(r->phantom_key);
     if (it != sv->phantoms.end()) it->second.users--;
+  }
+  if (r->held) {
+    r->ms->refs--;
+    r->sp->refs--;
+    r->geo->refs--;
+    r->held = false;
   }
   if (r->state == 2) sv->stats.completed++;
 }
@@ -263,6 +272,10 @@ static void server_loop(ctd_server *sv) {
       }
     }
     lk.lock();
+    for (Request *r : reqs) {
+      r->histories = r->cs->h_next;
+      r->batches = r->cs->batches;
+    }
     sv->stats.rounds++;
     sv->stats.histories += (uint64_t)cases.size() * bh;
     if (rc != CTD_OK) {
@@ -362,6 +375,10 @@ extern "C" int32_t ctd_server_submit(ctd_server *sv, uint64_t phantom_key, ctd_m
   r->p = *p;
   r->target = sigma_target;
   r->t_submit = sv->now();
+  ms->refs++;
+  sp->refs++;
+  geo->refs++;
+  r->held = true;
   *ticket = r->ticket;
   sv->queue.push_back(r.get());
   sv->all.emplace(r->ticket, std::move(r));
@@ -374,8 +391,8 @@ static void fill_info(const Request *r, ctd_request_info *info) {
   info->state = r->state;
   info->status = r->status;
   info->sigma = r->sigma;
-  info->histories = r->cs ? r->cs->h_next : r->histories;
-  info->batches = r->cs ? r->cs->batches : r->batches;
+  info->histories = r->histories;
+  info->batches = r->batches;
   info->reserved = 0;
   info->t_submit = r->t_submit;
   info->t_admit = r->t_admit;

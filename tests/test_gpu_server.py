@@ -141,6 +141,12 @@ def test_server_cancel_and_errors(ctx):
         t = L.ctd_server_submit(sv, 1, inp.ms, inp.sp, inp.geo, params(wl), 1e-9)
         time.sleep(0.2)
         assert L.ctd_server_poll(sv, t).state == 1   # running: the target is out of reach
+        # the request holds its inputs until it finishes
+        for release, h in [(L.ctd_materials_release, inp.ms), (L.ctd_spectrum_release, inp.sp),
+                           (L.ctd_geometry_release, inp.geo)]:
+            with pytest.raises(L.CtdError) as e:
+                release(ctx, h)
+            assert e.value.code == L.CTD_EBUSY
         L.ctd_server_cancel(sv, t)
         rc, info = L.ctd_server_wait(sv, t)
         assert rc == L.CTD_ECANCELLED and info.state == 3
