@@ -707,9 +707,13 @@ __device__ __forceinline__ void stage_case(CaseDev *dst, uint2 *pal, const CaseD
 
 // MACRO selects the macro-cell step for every case of the launch (a round
 // with both tracking modes is split into one launch per mode), so each
-// instance carries only its own step's registers.
+// instance carries only its own step's registers.  Every instance is held to
+// 96 VGPRs (5 waves per SIMD): the global step fits without spilling, the
+// macro-cell step spills a few words outside its cell walk and gains more
+// from the fifth wave hiding its dependent cell/majorant loads than the
+// spills cost.
 template <bool LOG, bool MACRO>
-__global__ void __launch_bounds__(512) k_transport(const RoundCase *__restrict__ rcs, int nrc,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k_transport(const RoundCase *__restrict__ rcs, int nrc,
                                                    uint64_t total_chunks,
                                                    unsigned long long *chunk_ctr, int refill_min,
                                                    int chunk, int tally_mode) {
