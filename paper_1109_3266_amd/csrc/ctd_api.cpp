@@ -680,8 +680,9 @@ void ctd::fill_desc(ctd_case *cs) {
   d.mc_nz = cs->mc_n[2];
   d.mc_fcs = (float)cs->mc_cs;
   d.mc_inv_cs = cs->mc_cs ? 1.0f / (float)cs->mc_cs : 0.0f;
-  d.mc_cls = cs->d_mc_cls;
-  d.mc_tab = cs->d_mc_tab;
+  d.mc_shift = cs->mc_shift;
+  d.mc_ncell = cs->mc_n[0] * cs->mc_n[1] * cs->mc_n[2];
+  d.mc_f = cs->d_mc_f;
   d.key0 = (uint32_t)cs->p.seed;
   d.key1 = (uint32_t)(cs->p.seed >> 32);
   d.tally = cs->d_tally;
@@ -709,8 +710,7 @@ void ctd::free_case_buffers(ctd_case *cs) {
   dfree(cs->d_fl_f);
   dfree(cs->d_mh_state);
   dfree(cs->d_mh_beam);
-  dfree(cs->d_mc_cls);
-  dfree(cs->d_mc_tab);
+  dfree(cs->d_mc_f);
   dfree(cs->d_log);
   dfree(cs->d_log_n);
   for (auto &t : cs->timing) {
@@ -816,7 +816,8 @@ uint64_t ctd::case_footprint(const ctd_grid &g, const ctd_geometry *geo, const c
   if (p.tracking == CTD_TRACK_MACRO) {
     int n[3];
     const uint64_t cells = (uint64_t)macro_cells(g, macro_edge(g, p.macro_cell), n);
-    b += 2 * cells + 4 * (uint64_t)ne * std::min<uint64_t>(cells, 65536);
+    b += 4 * (uint64_t)kMacroBands * cells;
+    (void)ne;
   }
   b += 8 * geo->fl_cdf.size() + 4 * geo->fl_guide.size();
   if (!geo->fl_f.empty())

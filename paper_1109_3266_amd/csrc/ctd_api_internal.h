@@ -106,9 +106,8 @@ struct ctd_case {
   int32_t *d_mh_state = nullptr;   // Alg. A1: last beamlet of each chain [C]
   int32_t *d_mh_beam = nullptr;    // Alg. A1: beamlets of the current round
   uint64_t mh_cap = 0;
-  uint16_t *d_mc_cls = nullptr;    // MACRO tracking: class of each cell
-  float *d_mc_tab = nullptr;       // MACRO tracking: class majorants [n_class][ne]
-  int mc_cs = 0, mc_n[3] = {0, 0, 0}, mc_classes = 0;
+  float *d_mc_f = nullptr;         // MACRO tracking: majorant factors [n_band][cells]
+  int mc_cs = 0, mc_n[3] = {0, 0, 0}, mc_classes = 0, mc_shift = 0, mc_bands = 0;
   unsigned long long *d_tally = nullptr;
   int tally_copies = 1;     // 1, or kTallyCopies once tally_mode 1 is selected
   long long *d_s1 = nullptr;
@@ -160,7 +159,7 @@ uint64_t case_footprint(const ctd_grid &g, const ctd_geometry *geo, const ctd_pa
 // Alg. A1 beamlet buffer of at least n entries.
 int ensure_mh_buffer(ctd_ctx *ctx, ctd_case *cs, uint64_t n);
 // MACRO tracking (ctd_macro.cpp): cells per axis for edge cs (returns the
-// cell count) and the per-cell class ids and class majorant table of a case.
+// cell count) and the per-band, per-cell majorant factors of a case.
 int macro_edge(const ctd_grid &g, int requested);
 int macro_cells(const ctd_grid &g, int cs, int n[3]);
 int build_macro(ctd_ctx *ctx, ctd_case *cs);

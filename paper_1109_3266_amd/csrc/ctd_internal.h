@@ -44,6 +44,7 @@ constexpr int kAccWords = 3 * ACC_COUNT + 4;
 
 constexpr float kQScale = 16777216.0f;  // 2^24: tally unit q = 2^-24 keV
 constexpr int kTallyCopies = 8;         // one batch tally per XCD of an MI355X
+constexpr int kMacroBands = 16;         // MACRO tracking: most energy bands
 constexpr uint32_t kStepGuard = 1000000u;
 constexpr float kInvMeC2 = (float)(1.0 / 510.99895);
 
@@ -84,12 +85,13 @@ struct CaseDev {
   double fl_total;             // F = C_{n-1}
   const double *fl_cdf;        // [fl_n] running sums of f
   const int32_t *fl_guide;     // [2^fl_gbits]
-  // MACRO tracking: cells of mc_cs^3 voxels, mc_n[3] per axis; class of each
-  // cell and the class majorants [n_class][ne] (cm^-1); mc_cs = 0: GLOBAL
+  // MACRO tracking: cells of mc_cs^3 voxels, mc_n[3] per axis (mc_cs = 0:
+  // GLOBAL).  Energy-grid cell j lies in band j >> mc_shift; the majorant of
+  // a cell in band b is mc_f[b * mc_ncell + cell] * mu_max(E).
   int32_t mc_cs, mc_nx, mc_ny, mc_nz;
-  float mc_fcs, mc_inv_cs, pad11, pad12;
-  const uint16_t *mc_cls;
-  const float *mc_tab;
+  float mc_fcs, mc_inv_cs;
+  int32_t mc_shift, mc_ncell;
+  const float *mc_f;
   // random stream key
   uint32_t key0, key1;
   // tallies

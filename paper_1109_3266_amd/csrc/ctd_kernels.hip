@@ -598,8 +598,9 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
     cy = (int)((p.cell >> 10) & 1023u);
     cz = (int)(p.cell >> 20);
   }
-  const GLOBAL uint16_t *cls = (const GLOBAL uint16_t *)G.mc_cls;
-  const GLOBAL float *tab = (const GLOBAL float *)G.mc_tab + p.je;
+  // the cell majorant factors of the photon's energy band
+  const GLOBAL float *fband =
+      (const GLOBAL float *)G.mc_f + (size_t)(p.je >> G.mc_shift) * (size_t)G.mc_ncell;
   // per axis, fixed for the call: the face the ray leaves a cell by, the
   // index step, 1/D, and whether the ray moves along the axis at all
   const bool fx = Dx > 0.0f, fy = Dy > 0.0f, fz = Dz > 0.0f;
@@ -611,9 +612,7 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
   bool hit = false, out = false;
 #pragma unroll
   for (int it = 0; it < kMacroCrossings; ++it) {
-    const int id = cls[(cz * ncy + cy) * ncx + cx];
-    const GLOBAL float *row = tab + (size_t)id * (size_t)S.ne;
-    mu_c = lerpf(row[0], row[1], p.we);
+    mu_c = fband[(cz * ncy + cy) * ncx + cx] * p.mumax;
     const float x0 = (float)cx * fcs, y0 = (float)cy * fcs, z0 = (float)cz * fcs;
     const float bx = fx ? fminf(x0 + fcs, S.fnx) : x0;
     const float by = fy ? fminf(y0 + fcs, S.fny) : y0;

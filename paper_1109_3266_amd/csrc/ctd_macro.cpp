@@ -3,12 +3,18 @@
 //
 // The phantom is cut into cubic cells of cs^3 voxels.  For each cell and
 // material the largest density present is found on the device; on the host
-// it is rounded up to 6 significant mantissa bits (so that cells group into a
-// few classes), and each distinct vector of rounded densities becomes a class
+// it is rounded up to 10 significant mantissa bits (so that cells group into
+// classes), and each distinct vector of rounded densities becomes a class
 // whose majorant at every energy node is formed exactly like the global one
 // (largest rho * (mu_pe + mu_C [+ mu_R]) / rho over the materials, FP64,
-// 2^-20 margin, rounded up to float).  Interpolated linearly in energy it
-// bounds every voxel of every cell of the class.
+// 2^-20 margin, rounded up to float).  The transport reads one number per
+// cell crossing: the energy grid is cut into at most 16 bands of 2^shift grid
+// cells, and per band and cell it stores the factor f with f * mu_max >= the
+// class majorant at every node the band's grid cells interpolate between
+// (largest ratio, widened by 2^-18 for the float lerps and the product,
+// rounded up, at most 1).  Both majorants are linear between nodes, so
+// f * mu_max(E) bounds every voxel of the cell at every energy of the band,
+// and f = 1 gives the global majorant, which bounds every voxel anywhere.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -23,11 +29,11 @@ using namespace ctd;
 
 namespace {
 
-// Round a non-negative float up to 6 significant mantissa bits.
-float round_up_6bits(float v) {
+// Round a non-negative float up to 10 significant mantissa bits.
+float round_up_10bits(float v) {
   uint32_t b;
   std::memcpy(&b, &v, 4);
-  const uint32_t low = (1u << 17) - 1u;
+  const uint32_t low = (1u << 13) - 1u;
   if (b & low) b = (b | low) + 1u;
   float r;
   std::memcpy(&r, &b, 4);
@@ -83,7 +89,7 @@ int ctd::build_macro(ctd_ctx *ctx, ctd_case *cs) {
 
   const int ne = cs->ms->eg.ne;
   std::map<std::vector<uint32_t>, int> classes;
-  std::vector<uint16_t> cls((size_t)cells);
+  std::vector<int32_t> cls((size_t)cells);
   std::vector<float> tab;
   std::vector<double> rmax((size_t)M);
   bool pres[256];
@@ -92,13 +98,12 @@ int ctd::build_macro(ctd_ctx *ctx, ctd_case *cs) {
     for (int m = 0; m < M; ++m) {
       float v;
       std::memcpy(&v, &hmax[(size_t)(c * M + m)], 4);
-      v = round_up_6bits(v);
+      v = round_up_10bits(v);
       std::memcpy(&key[(size_t)m], &v, 4);
     }
     auto it = classes.find(key);
     if (it == classes.end()) {
       const int id = (int)classes.size();
-      if (id > 65535) return set_err(ctx, CTD_EINVAL, "more than 65536 macro classes");
       it = classes.emplace(key, id).first;
       for (int m = 0; m < M; ++m) {
         float v;
@@ -110,15 +115,39 @@ int ctd::build_macro(ctd_ctx *ctx, ctd_case *cs) {
       majorant_fp64(ne, M, cs->ms->mu_rho.data(), rmax.data(), pres, cs->p.rayleigh != 0,
                     tab.data() + (size_t)id * ne);
     }
-    cls[(size_t)c] = (uint16_t)it->second;
+    cls[(size_t)c] = it->second;
   }
-  if ((e = hipMalloc(&cs->d_mc_cls, sizeof(uint16_t) * cls.size())) != hipSuccess ||
-      (e = hipMalloc(&cs->d_mc_tab, sizeof(float) * tab.size())) != hipSuccess ||
-      (e = hipMemcpy(cs->d_mc_cls, cls.data(), sizeof(uint16_t) * cls.size(),
-                     hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(cs->d_mc_tab, tab.data(), sizeof(float) * tab.size(),
+  // energy bands: grid cell j (nodes j, j + 1) lies in band j >> shift
+  int shift = 0;
+  while (((ne - 2) >> shift) >= kMacroBands) ++shift;
+  const int nb = ((ne - 2) >> shift) + 1;
+  const int ncls = (int)classes.size();
+  const std::vector<float> &gmaj = cs->mu_max;  // the case's global majorant
+  std::vector<float> fcls((size_t)ncls * nb);
+  for (int k = 0; k < ncls; ++k)
+    for (int b = 0; b < nb; ++b) {
+      const int j0 = b << shift, j1 = std::min((b + 1) << shift, ne - 1);
+      double r = 0.0;
+      for (int j = j0; j <= j1; ++j) {
+        const double c = (double)tab[(size_t)k * ne + j];
+        if (c > 0.0) r = std::max(r, gmaj[j] > 0.0f ? c / (double)gmaj[j] : INFINITY);
+      }
+      r *= 1.0 + 0x1p-18;
+      float f = (float)r;
+      if ((double)f < r) f = std::nextafter(f, INFINITY);
+      // mu_max itself bounds every voxel: a cell never needs more
+      fcls[(size_t)k * nb + b] = std::min(f, 1.0f);
+    }
+  std::vector<float> fac((size_t)nb * cells);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t c = 0; c < cells; ++c)
+      fac[(size_t)b * cells + c] = fcls[(size_t)cls[(size_t)c] * nb + b];
+  if ((e = hipMalloc(&cs->d_mc_f, sizeof(float) * fac.size())) != hipSuccess ||
+      (e = hipMemcpy(cs->d_mc_f, fac.data(), sizeof(float) * fac.size(),
                      hipMemcpyHostToDevice)) != hipSuccess)
     return hip_err(ctx, e, "macro-cell upload");
+  cs->mc_shift = shift;
+  cs->mc_bands = nb;
   cs->mc_cs = cell;
   for (int a = 0; a < 3; ++a) cs->mc_n[a] = n[a];
   cs->mc_classes = (int)classes.size();
