@@ -1410,7 +1410,7 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
   std::vector<ctd_tuning> cand;
   for (int tm = ctx->xcd_tally_ok ? 2 : 0; tm >= 0; --tm) {
     if (!transport_lds_fits(256, tm, ctx->device)) continue;
-    for (int wps : {2, 4, 8})
+    for (int wps : {2, 4, 5, 8})  // 5: the resident waves per SIMD
       for (int rm : {8, 16, 32})
         for (int ch : {256, 1024}) {
           ctd_tuning t;
