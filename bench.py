@@ -120,13 +120,15 @@ def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
                 cpu_model=model), r
 
 
-def batched_leg(ctx, L, W, Case, tuning, torch, hist_scale):
+def batched_leg(ctx, L, W, Case, tuning, torch, hist_scale, tracking=None):
     """48 uneven cases: each run alone back to back (plain per-case launches)
-    vs one batched launch per round over all cases; results must match."""
+    vs one batched launch per round over all cases; results must match.
+    tracking: None (each case's own, the global majorant) or a CTD_TRACK_*
+    mode for every case on both sides."""
     import numpy as np
     log("batched: generating 48 cases")
     cases = W.batched(hist_scale=hist_scale)
-    objs = [Case(ctx, wl) for wl in cases]
+    objs = [Case(ctx, wl, tracking=tracking) for wl in cases]
     ns = [wl.n_histories for wl in cases]
     total = float(sum(ns))
     for o in objs:
@@ -287,11 +289,12 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
 
 
 def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
-                batch: int = 10_000_000, max_h: int = 300_000_000_000):
+                batch: int = 10_000_000, max_h: int = 300_000_000_000, tracking=None):
     """Poisson stream of run-to-1%-sigma requests from the batched case
     distribution.  Baseline: the same requests run one at a time in arrival
     order (FIFO), latencies from the measured service times and the trace.
-    Served: the continuous-batching server fed in real time."""
+    Served: the continuous-batching server fed in real time.  tracking as in
+    batched_leg, for the solo runs and the served requests alike."""
     import threading
 
     import numpy as np
@@ -304,7 +307,7 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
     wls = [W.serving_request(seeds[i], i) for i in range(n_req)]
     service, hist_plain, ref = [], 0, {}
     for i, wl in enumerate(wls):
-        with Case(ctx, wl) as c:
+        with Case(ctx, wl, tracking=tracking) as c:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             L.ctd_run_to_sigma(ctx, c.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, batch, max_h)
@@ -340,7 +343,8 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
                 while L.ctd_server_now(sv) < t_base + arrivals[i]:
                     time.sleep(0.001)
                 tickets[i] = L.ctd_server_submit(sv, i, inputs[i].ms, inputs[i].sp,
-                                                 inputs[i].geo, params(wls[i]), 0.01)
+                                                 inputs[i].geo,
+                                                 params(wls[i], tracking=tracking), 0.01)
 
         th = threading.Thread(target=feed)
         th.start()
@@ -538,8 +542,13 @@ def main():
                                                                  L.CTD_SIGMA_PAPER, 0.2))
         c2.close()
         log(f"time to 1% sigma {tts:.2f} s ({s2.n_histories:.3g} histories)")
+    # the batched leg with the paper's global majorant, then the same cases
+    # with macro-cell majorants (both sides of the comparison use the same
+    # tracking); serving keeps each request's own (global) tracking
     if "batched" in legs:
         out["batched"] = batched_leg(ctx, L, W, Case, tuning, torch, args.batched_scale)
+        out["batched_macro_tracking"] = batched_leg(ctx, L, W, Case, tuning, torch,
+                                                    args.batched_scale, L.CTD_TRACK_MACRO)
     if "serving" in legs and args.serving_requests > 0:
         out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests)
     if "extensions" in legs:
