@@ -762,7 +762,7 @@ extern "C" int32_t ctd_case_reset(ctd_ctx *ctx, ctd_case *cs) {
 ctd_tuning ctd::default_tuning(const ctd_ctx *ctx) {
   ctd_tuning t;
   t.block = 256;
-  t.waves_per_simd = 4;
+  t.waves_per_simd = 5;  // the resident waves per SIMD of the 96-VGPR kernel
   t.refill_min = 16;
   t.chunk = 1024;
   t.tally_mode = 0;  // per-XCD copies measured no faster on MI355X; 8x the fold traffic
