@@ -289,7 +289,8 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
 
 
 def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
-                batch: int = 10_000_000, max_h: int = 300_000_000_000, tracking=None):
+                batch: int = 10_000_000, max_h: int = 300_000_000_000, tracking=None,
+                max_active: int = 64):
     """Poisson stream of run-to-1%-sigma requests from the batched case
     distribution.  Baseline: the same requests run one at a time in arrival
     order (FIFO), latencies from the measured service times and the trace.
@@ -329,7 +330,7 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
     cfg.max_histories = max_h
     cfg.dose_frac = 0.5
     cfg.sigma_kind = L.CTD_SIGMA_LOCAL
-    cfg.max_active = 64
+    cfg.max_active = max_active
     sv = L.ctd_server_start(0, cfg)
     inputs = [Inputs(ctx, wl) for wl in wls]
     try:
@@ -364,7 +365,7 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
     service_rate = n_req / sum(service)
     log(f"serving: served p50 {np.percentile(lat, 50):.2f} s, {hist / makespan:.4g} hist/s")
     return dict(requests=n_req, arrival_rate_hz=rate_hz, sigma_target=0.01,
-                batch_histories=batch,
+                batch_histories=batch, max_active=max_active,
                 p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                 histories_per_s=hist / makespan,
                 plain_fifo_p50_s=float(np.percentile(lat_plain, 50)),
