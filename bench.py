@@ -543,15 +543,17 @@ def main():
                                                                  L.CTD_SIGMA_PAPER, 0.2))
         c2.close()
         log(f"time to 1% sigma {tts:.2f} s ({s2.n_histories:.3g} histories)")
-    # the batched leg with the paper's global majorant, then the same cases
-    # with macro-cell majorants (both sides of the comparison use the same
-    # tracking); serving keeps each request's own (global) tracking
+    # the batched and serving legs with the paper's global majorant, then the
+    # same cases with the library's automatic choice between global and
+    # macro-cell majorants (both sides of each comparison use the same mode)
     if "batched" in legs:
         out["batched"] = batched_leg(ctx, L, W, Case, tuning, torch, args.batched_scale)
-        out["batched_macro_tracking"] = batched_leg(ctx, L, W, Case, tuning, torch,
-                                                    args.batched_scale, L.CTD_TRACK_MACRO)
+        out["batched_auto_tracking"] = batched_leg(ctx, L, W, Case, tuning, torch,
+                                                   args.batched_scale, L.CTD_TRACK_AUTO)
     if "serving" in legs and args.serving_requests > 0:
         out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests)
+        out["serving_auto_tracking"] = serving_leg(ctx, L, W, torch, args.serving_requests,
+                                                   tracking=L.CTD_TRACK_AUTO)
     if "extensions" in legs:
         out["extensions"] = extensions_leg(ctx, L, W, Case, torch, tuning)
 

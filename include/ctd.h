@@ -143,6 +143,13 @@ typedef struct {
  * (a bone-dominated global majorant). */
 #define CTD_TRACK_GLOBAL 0
 #define CTD_TRACK_MACRO 1
+/* AUTO: MACRO where, at the spectrum's mean energy, the largest rho_max *
+ * mu/rho over the phantom's materials exceeds 1.5 times that of its most
+ * frequent material denser than 0.05 g/cm^3 (a dense minority such as bone
+ * sets the global majorant), else GLOBAL.  Decided from the inputs at case
+ * creation (ctd_stats.tracking reports it), so results do not depend on the
+ * machine. */
+#define CTD_TRACK_AUTO 2
 
 typedef struct {
   double e_cut_kev;      /* photon absorption energy (Sec. 3.1 uses 1 keV) */
@@ -150,7 +157,7 @@ typedef struct {
   int32_t n_batches;     /* batches per ctd_run (Sec. 2.2.1 uses 10), >= 2 */
   int32_t rayleigh;      /* 1 = Rayleigh scattering on */
   double sigma_rho_min;  /* voxels with rho >= this count as "inside" for sigma-bar */
-  int32_t tracking;      /* CTD_TRACK_GLOBAL (default) or CTD_TRACK_MACRO */
+  int32_t tracking;      /* CTD_TRACK_GLOBAL (default), CTD_TRACK_MACRO or CTD_TRACK_AUTO */
   int32_t macro_cell;    /* MACRO cell edge in voxels, 1..64 (0: about 1.6 cm) */
 } ctd_params;
 
@@ -169,7 +176,7 @@ typedef struct {
   double transport_ms;   /* GPU time of the transport launches (HIP events) */
   double fold_ms;        /* GPU time of the batch folds */
   uint32_t n_batches;    /* batches folded so far */
-  uint32_t reserved;
+  int32_t tracking;      /* CTD_TRACK_GLOBAL or CTD_TRACK_MACRO: the mode in use */
   uint64_t n_histories;  /* histories run so far */
   uint64_t n_crossings;  /* MACRO tracking: macro-cell boundary crossings */
 } ctd_stats;

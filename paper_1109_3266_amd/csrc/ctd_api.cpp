@@ -240,6 +240,7 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
     std::memcpy(&f, &hstat[m], 4);
     ph->rho_max[m] = (double)f;
     ph->present[m] = hstat[256 + m] != 0;
+    ph->count[m] = hstat[256 + m];
   }
   dfree(dmat);
   dfree(drho);
@@ -490,6 +491,37 @@ static double e_max_of(const ctd_spectrum *sp) {
   return m;
 }
 
+// CTD_TRACK_AUTO: macro-cell majorants pay where one material's attenuation
+// sets the global majorant well above that of the material filling most of
+// the phantom (bone in tissue): at the spectrum's mean energy, the largest
+// rho_max * mu/rho over the present materials against that of the most
+// frequent material denser than 0.05 g/cm^3; MACRO above 1.5.  Depends on
+// the inputs only, so a case's histories do not depend on the machine.
+int ctd::auto_tracking(const ctd_phantom *ph, const ctd_matset *ms, const ctd_spectrum *sp,
+                       bool rayleigh) {
+  double wsum = 0.0, emean = 0.0;
+  for (size_t i = 0; i < sp->lo.size(); ++i) {
+    wsum += sp->w[i];
+    emean += sp->w[i] * (sp->lo[i] + 0.5 * sp->width);
+  }
+  emean /= wsum;
+  const ctd_egrid &eg = ms->eg;
+  const int j = std::min(std::max((int)std::lround((emean - eg.e0) / eg.de), 0), eg.ne - 1);
+  double top = 0.0, bulk = 0.0;
+  uint32_t bulk_n = 0;
+  for (int m = 0; m < ms->M; ++m) {
+    if (!ph->present[m]) continue;
+    const float *r = ms->mu_rho.data() + ((size_t)m * eg.ne + j) * 3;
+    const double mu = ph->rho_max[m] * ((double)r[0] + r[1] + (rayleigh ? r[2] : 0.0f));
+    top = std::max(top, mu);
+    if (ph->rho_max[m] > 0.05 && ph->count[m] > bulk_n) {
+      bulk_n = ph->count[m];
+      bulk = mu;
+    }
+  }
+  return bulk > 0.0 && top > 1.5 * bulk ? CTD_TRACK_MACRO : CTD_TRACK_GLOBAL;
+}
+
 int ctd::upload_desc(ctd_ctx *ctx, ctd_case *cs) {
   HIPCHK(ctx, hipMemcpyAsync(cs->d_desc, &cs->desc, sizeof(CaseDev), hipMemcpyHostToDevice,
                              ctx->stream));
@@ -514,7 +546,8 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
   NEED(ctx, emax <= etop, "spectrum reaches %.6g keV beyond the energy grid (%.6g)", emax, etop);
   NEED(ctx, emax < 255.0, "spectrum energies must stay below 255 keV");
   NEED(ctx, !p->rayleigh || ms->d_rayl, "Rayleigh on but no Rayleigh surfaces loaded");
-  NEED(ctx, p->tracking == CTD_TRACK_GLOBAL || p->tracking == CTD_TRACK_MACRO,
+  NEED(ctx, p->tracking == CTD_TRACK_GLOBAL || p->tracking == CTD_TRACK_MACRO ||
+                p->tracking == CTD_TRACK_AUTO,
        "unknown tracking mode %d", p->tracking);
   NEED(ctx, p->macro_cell >= 0 && p->macro_cell <= 64, "macro_cell must be 0..64");
   HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -526,6 +559,7 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
   cs->sp = sp;
   cs->geo = geo;
   cs->p = *p;
+  if (p->tracking == CTD_TRACK_AUTO) cs->p.tracking = auto_tracking(ph, ms, sp, p->rayleigh != 0);
   cs->e_max = emax;
   cs->tune = default_tuning(ctx);
   // majorant from per-material maximum density (Sec. 2.1)
@@ -588,7 +622,7 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
                                     sizeof(float4) * geo->proj_sc.size(),
                                     hipMemcpyHostToDevice)) != hipSuccess))
     return cleanup(hip_err(ctx, e, "case upload"));
-  if (p->tracking == CTD_TRACK_MACRO && (rc = build_macro(ctx, cs)) != CTD_OK)
+  if (cs->p.tracking == CTD_TRACK_MACRO && (rc = build_macro(ctx, cs)) != CTD_OK)
     return cleanup(rc);
   if (launch_zero(cs->d_tally, 8 * V, ctx->stream) || launch_zero(cs->d_s1, 8 * V, ctx->stream) ||
       launch_zero(cs->d_s2, 16 * V, ctx->stream) ||
@@ -813,7 +847,7 @@ uint64_t ctd::case_footprint(const ctd_grid &g, const ctd_geometry *geo, const c
   const uint64_t V = (uint64_t)g.nx * g.ny * g.nz;
   uint64_t b = V * (24 + 8 * (uint64_t)tally_copies) + 8 * kAccWords + sizeof(CaseDev) +
                sizeof(float4) * geo->proj_sc.size() + 65536;
-  if (p.tracking == CTD_TRACK_MACRO) {
+  if (p.tracking != CTD_TRACK_GLOBAL) {  // MACRO, or AUTO that may choose it
     int n[3];
     const uint64_t cells = (uint64_t)macro_cells(g, macro_edge(g, p.macro_cell), n);
     b += 4 * (uint64_t)kMacroBands * cells;
@@ -1291,7 +1325,7 @@ extern "C" int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out) {
   out->transport_ms = cs->transport_ms;
   out->fold_ms = cs->fold_ms;
   out->n_batches = cs->batches;
-  out->reserved = 0;
+  out->tracking = cs->mc_cs > 0 ? CTD_TRACK_MACRO : CTD_TRACK_GLOBAL;
   out->n_histories = cs->h_next;
   out->n_crossings = a[ACC_N_CROSS];
   return CTD_OK;

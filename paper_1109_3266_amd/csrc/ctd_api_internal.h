@@ -55,6 +55,7 @@ struct ctd_phantom {
   int npal = 0;
   double rho_max[256] = {};
   bool present[256] = {};
+  uint32_t count[256] = {};   // voxels of each material
   int max_mat = 0;
   std::atomic<int> refs{0};
 };
@@ -163,5 +164,8 @@ int ensure_mh_buffer(ctd_ctx *ctx, ctd_case *cs, uint64_t n);
 int macro_edge(const ctd_grid &g, int requested);
 int macro_cells(const ctd_grid &g, int cs, int n[3]);
 int build_macro(ctd_ctx *ctx, ctd_case *cs);
+// The tracking mode CTD_TRACK_AUTO resolves to for these inputs.
+int auto_tracking(const ctd_phantom *ph, const ctd_matset *ms, const ctd_spectrum *sp,
+                  bool rayleigh);
 
 }  // namespace ctd

@@ -138,8 +138,8 @@ int launch_fold(unsigned long long *tally, int ncopies, long long *s1, unsigned 
                 int64_t V, unsigned long long *acc, void *stream);
 // Largest XCC id seen by `blocks` workgroups (written to *out, device).
 int launch_xcc_probe(unsigned int *out, int blocks, void *stream);
-// stats[514]: [0,256) max density bits per material, [256,512) presence,
-// [512] largest material id, [513] voxels with a bad density.
+// stats[514]: [0,256) max density bits per material, [256,512) voxel count
+// per material, [512] largest material id, [513] voxels with a bad density.
 int launch_pack(const uint8_t *mat, const float *rho, uint2 *vox, int64_t V, unsigned int *stats,
                 void *stream);
 int launch_zero(void *ptr, size_t bytes, void *stream);

@@ -961,9 +961,9 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t *__restrict__ mat,
                                               const float *__restrict__ rho,
                                               uint2 *__restrict__ vox, int64_t V,
                                               unsigned int *stats) {
-  __shared__ unsigned int lmax[256], lpres[256];
+  __shared__ unsigned int lmax[256], lcnt[256];
   __shared__ unsigned int lmat, lbad;
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) { lmax[i] = 0u; lpres[i] = 0u; }
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) { lmax[i] = 0u; lcnt[i] = 0u; }
   if (threadIdx.x == 0) { lmat = 0u; lbad = 0u; }
   __syncthreads();
   unsigned int mymat = 0u, mybad = 0u;
@@ -974,7 +974,7 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t *__restrict__ mat,
     const bool ok = (r >= 0.0f) && (r <= 3.4e38f);
     vox[i] = make_uint2(__float_as_uint(r), m);
     mymat = max(mymat, m);
-    if (lpres[m] == 0u) lpres[m] = 1u;  // benign race: every writer stores 1
+    atomicAdd(&lcnt[m], 1u);
     if (ok) atomicMax(&lmax[m], __float_as_uint(r)); else mybad += 1u;
   }
   atomicMax(&lmat, mymat);
@@ -982,7 +982,7 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t *__restrict__ mat,
   __syncthreads();
   for (int i = threadIdx.x; i < 256; i += blockDim.x) {
     if (lmax[i]) atomicMax(&stats[i], lmax[i]);
-    if (lpres[i]) atomicMax(&stats[256 + i], 1u);
+    if (lcnt[i]) atomicAdd(&stats[256 + i], lcnt[i]);
   }
   if (threadIdx.x == 0) {
     atomicMax(&stats[512], lmat);

@@ -29,6 +29,7 @@ CTD_GEOM_PENCIL = 0
 CTD_GEOM_CONE = 1
 CTD_TRACK_GLOBAL = 0
 CTD_TRACK_MACRO = 1
+CTD_TRACK_AUTO = 2
 CTD_SIGMA_LOCAL = 0
 CTD_SIGMA_PAPER = 1
 
@@ -90,7 +91,7 @@ class ctd_stats(C.Structure):
                 ("n_compton", C.c_uint64), ("n_rayleigh", C.c_uint64),
                 ("n_deposits", C.c_uint64), ("n_escapes", C.c_uint64), ("n_refills", C.c_uint64),
                 ("transport_ms", C.c_double), ("fold_ms", C.c_double),
-                ("n_batches", C.c_uint32), ("reserved", C.c_uint32),
+                ("n_batches", C.c_uint32), ("tracking", C.c_int32),
                 ("n_histories", C.c_uint64), ("n_crossings", C.c_uint64)]
 
 

@@ -158,3 +158,26 @@ def test_macro_full_size_head_matches_global(ctx):
     rel = abs(g["bal"].q_deposited - r["bal"].q_deposited) / r["bal"].q_deposited
     say(f"  3-sigma {frac:.4f} over {mask.sum()} voxels, dE/E {rel:.2e}")
     assert frac >= 0.99 and rel < 1e-3
+
+
+def test_auto_tracking_choice_and_identity(ctx):
+    """CTD_TRACK_AUTO picks macro cells where a dense minority material sets
+    the majorant (the head's bone, a bone-bearing request phantom) and the
+    global majorant otherwise (water cylinder, tissue-only phantom), and then
+    runs exactly that mode: tallies equal the explicit mode's bit for bit."""
+    say("AUTO tracking")
+    arrivals, seeds = W.serving_trace(200, 2.0, 5005)
+    req = {i: W.serving_request(seeds[i], i, size_scale=0.3) for i in (2, 8)}
+    cases = [("head", W.head(scale=4, n_histories=200_000), MACRO),
+             ("water_cbct", W.water_cbct(scale=4, n_histories=200_000), L.CTD_TRACK_GLOBAL),
+             ("tissue-only request", req[2], L.CTD_TRACK_GLOBAL),
+             ("bone-bearing request", req[8], MACRO)]
+    for name, wl, want in cases:
+        assert "cortical_bone" in wl.materials or want == L.CTD_TRACK_GLOBAL, name
+        a = run(ctx, wl, 200_000, tracking=L.CTD_TRACK_AUTO)
+        b = run(ctx, wl, 200_000, tracking=want)
+        assert a["st"].tracking == want, name
+        assert b["st"].tracking == want, name
+        assert np.array_equal(a["s1"], b["s1"]), name
+        assert np.array_equal(a["s2_lo"], b["s2_lo"]), name
+        assert (a["st"].n_crossings > 0) == (want == MACRO), name
