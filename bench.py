@@ -293,30 +293,41 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
                 max_active: int = 64):
     """Poisson stream of run-to-1%-sigma requests from the batched case
     distribution.  Baseline: the same requests run one at a time in arrival
-    order (FIFO), latencies from the measured service times and the trace.
-    Served: the continuous-batching server fed in real time.  tracking as in
-    batched_leg, for the solo runs and the served requests alike."""
+    order (FIFO), latencies from the measured service times and the trace; a
+    service time covers what the server does per request (phantom load from
+    host arrays, case creation, the run, the exact sums back to the host,
+    freeing), the material set, spectrum and geometry being built beforehand
+    in both.  Served: the continuous-batching server fed in real time.
+    tracking as in batched_leg, for the solo runs and the served requests."""
     import threading
 
     import numpy as np
 
-    from paper_1109_3266_amd.session import Case, Inputs, grid, params
+    from paper_1109_3266_amd.session import Inputs, grid, params
 
     arrivals, seeds = W.serving_trace(200, rate_hz, 5005)
     arrivals = arrivals[:n_req]
     log(f"serving: generating {n_req} requests")
     wls = [W.serving_request(seeds[i], i) for i in range(n_req)]
     service, hist_plain, ref = [], 0, {}
+    inputs = [Inputs(ctx, wl) for wl in wls]
     for i, wl in enumerate(wls):
-        with Case(ctx, wl, tracking=tracking) as c:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            L.ctd_run_to_sigma(ctx, c.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, batch, max_h)
-            torch.cuda.synchronize()
-            service.append(time.perf_counter() - t0)
-            hist_plain += L.ctd_read_stats(ctx, c.cs).n_histories
-            if i < 3:
-                ref[i] = c.tally()[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ph = L.ctd_phantom_load(ctx, grid(wl), wl.mat, wl.rho)
+        cs = L.ctd_case_create(ctx, ph, inputs[i].ms, inputs[i].sp, inputs[i].geo,
+                               params(wl, tracking=tracking))
+        L.ctd_run_to_sigma(ctx, cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, batch, max_h)
+        s1 = L.ctd_read_tally(ctx, cs, wl.n_voxels)[0]
+        t1 = time.perf_counter()
+        hist_plain += L.ctd_read_stats(ctx, cs).n_histories   # not timed
+        t2 = time.perf_counter()
+        L.ctd_case_destroy(ctx, cs)
+        L.ctd_phantom_release(ctx, ph)
+        torch.cuda.synchronize()
+        service.append((t1 - t0) + (time.perf_counter() - t2))
+        if i < 3:
+            ref[i] = s1
     end, lat_plain = 0.0, []
     for a, sv_t in zip(arrivals, service):
         end = max(end, a) + sv_t
@@ -332,7 +343,6 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
     cfg.sigma_kind = L.CTD_SIGMA_LOCAL
     cfg.max_active = max_active
     sv = L.ctd_server_start(0, cfg)
-    inputs = [Inputs(ctx, wl) for wl in wls]
     try:
         for i, wl in enumerate(wls):
             L.ctd_server_add_phantom(sv, i, grid(wl), wl.mat, wl.rho)
