@@ -15,9 +15,10 @@
  * Options beside the plain method: bound-electron Compton (one C surface per
  * material, Eq. 2 with S), a helical CT trajectory, a fluence map over the
  * field (Sec. 2.2.4: exact inverse CDF, or Alg. A1 Metropolis-Hastings
- * chains), macro-cell majorants for Woodcock tracking (CTD_TRACK_MACRO), a
- * batched multi-case engine, a continuous-batching dose server, and the
- * gamma-index comparison of Sec. 3.1.
+ * chains), macro-cell majorants for Woodcock tracking (CTD_TRACK_MACRO, or
+ * chosen per case by CTD_TRACK_AUTO), a tally contention strategy chosen per
+ * case (ctd_tuning.tally_mode), a batched multi-case engine, a
+ * continuous-batching dose server, and the gamma-index comparison of Sec. 3.1.
  *
  * Conventions
  *   - Every call returns an int32 status (CTD_OK or a negative CTD_E* code);
