@@ -290,7 +290,7 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
 
 def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
                 batch: int = 10_000_000, max_h: int = 300_000_000_000, tracking=None,
-                max_active: int = 64):
+                max_active: int = 64, detail: bool = False):
     """Poisson stream of run-to-1%-sigma requests from the batched case
     distribution.  Baseline: the same requests run one at a time in arrival
     order (FIFO), latencies from the measured service times and the trace; a
@@ -371,6 +371,9 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
             inp.close()
     lat = [x.t_done - x.t_submit for x in infos]
     hist = sum(x.histories for x in infos)
+    per_request = dict(arrival_s=[float(a) for a in arrivals], service_s=service,
+                       fifo_latency_s=lat_plain, served_latency_s=lat,
+                       served_admit_s=[x.t_admit - x.t_submit for x in infos]) if detail else None
     makespan = max(x.t_done for x in infos) - min(x.t_submit for x in infos)
     service_rate = n_req / sum(service)
     log(f"serving: served p50 {np.percentile(lat, 50):.2f} s, {hist / makespan:.4g} hist/s")
@@ -388,7 +391,8 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
                       "is unstable; latencies are for this finite trace, not a steady state")
                 if service_rate <= rate_hz else "",
                 identical_to_plain=bool(same), rounds=st.rounds,
-                phantom_loads=st.phantom_loads)
+                phantom_loads=st.phantom_loads,
+                **({"per_request": per_request} if detail else {}))
 
 
 def calibrate_copy():
