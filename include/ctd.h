@@ -189,8 +189,9 @@ typedef struct {
   int32_t refill_min;    /* refill a wave when >= this many lanes idle (1..64) */
   int32_t chunk;         /* histories a wave claims per counter atomic (64..65536) */
   int32_t tally_mode;    /* 0: one batch tally, device-scope atomics;
-                            1: one batch tally per XCD, updated with L2-resident
-                            atomics by the waves of that XCD and summed by the
+                            1: one batch tally per XCD, updated only by the
+                            waves of that XCD (fewer atomics on one address
+                            where deposits concentrate) and summed by the
                             fold (only where every XCD id is < 8);
                             2: as 1, behind a 512-slot LDS sub-tally per wave
                             (a voxel's slot is kept by the first voxel that
@@ -310,8 +311,10 @@ int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, double dose_
                          double *achieved);
 
 /* Batched engine: run n[i] histories of each case i in ONE persistent launch
- * per batch round over a (case, history-chunk) task queue.  Per-case
- * results equal ctd_run(cs[i], n[i]) bit for bit.  Async. */
+ * per batch round over a (case, history-chunk) task queue (one launch per
+ * tracking mode when the cases mix GLOBAL and MACRO), with the launch
+ * configuration of cs[0].  Per-case results equal ctd_run(cs[i], n[i]) bit
+ * for bit.  CTD_EINVAL if a case is listed twice.  Async. */
 int32_t ctd_run_many(ctd_ctx *ctx, ctd_case *const *cs, const uint64_t *n, int32_t count);
 
 /* Wait until all work enqueued for the case (its stream) is complete. */
