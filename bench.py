@@ -120,6 +120,29 @@ def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
                 cpu_model=model), r
 
 
+def other_oracle_rates(threads: int, ext: dict):
+    """Oracle histories/s on the 32^3 pencil-beam cube (1e5 histories in 10
+    batches, the whole case) and on 4e6 histories of the synthetic head in 2
+    batches (each batch costs the oracle a pass over per-thread tallies of the
+    10.5 M voxels, about a second), with the head's time to 1 % sigma
+    extrapolated from the GPU run's history count."""
+    from oracle import oracle as O
+    from synth import workloads as W
+    out = {}
+    for name, wl, n, nb in [("tiny_pencil_beam", W.tiny(n_histories=100_000), 100_000, 10),
+                            ("head", W.head(n_histories=4_000_000), 4_000_000, 2)]:
+        c = O.OracleCase(wl)
+        t0 = time.perf_counter()
+        O.run(c, n_histories=n, n_batches=nb, threads=threads)
+        dt = time.perf_counter() - t0
+        out[name] = dict(histories=n, batches=nb, seconds=dt, histories_per_s=n / dt)
+    h = ext.get("head_time_to_1pct_sigma")
+    if h:
+        out["head"]["time_to_1pct_sigma_s_extrapolated"] = (
+            h["histories"] / out["head"]["histories_per_s"])
+    return out
+
+
 def batched_leg(ctx, L, W, Case, tuning, torch, hist_scale, tracking=None):
     """48 uneven cases: each run alone back to back (plain per-case launches)
     vs one batched launch per round over all cases; results must match.
@@ -577,6 +600,8 @@ def main():
         tts = out.get("time_to_1pct_sigma")
         if tts:   # the oracle would need the same histories to reach 1 % sigma
             cb["time_to_1pct_sigma_s_extrapolated"] = tts["histories"] / cb["value"]
+        # the oracle on the pencil-beam cube in full and on a sample of the head
+        cb["other_workloads"] = other_oracle_rates(cb["cores"], out.get("extensions", {}))
         out["cpu_baseline"] = cb
     L.ctd_destroy(ctx)
     print(json.dumps(out), flush=True)
