@@ -123,8 +123,8 @@ def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
 def other_oracle_rates(threads: int, ext: dict):
     """Oracle histories/s on the 32^3 pencil-beam cube (1e5 histories in 10
     batches, the whole case) and on 4e6 histories of the synthetic head in 2
-    batches (each batch costs the oracle a pass over per-thread tallies of the
-    10.5 M voxels, about a second), with the head's time to 1 % sigma
+    batches (each batch costs the oracle passes over per-thread tallies of the
+    10.5 M voxels, seconds on 8 threads), with the head's time to 1 % sigma
     extrapolated from the GPU run's history count."""
     from oracle import oracle as O
     from synth import workloads as W
