@@ -1131,12 +1131,15 @@ extern "C" int32_t ctd_sigma(ctd_ctx *ctx, ctd_case *cs, int32_t sigma_kind, dou
   return sigma_now(ctx, cs, sigma_kind, dose_frac, out);
 }
 
-// sigma ~ batches^-1/2 at a fixed batch size: aim 2 % past the target.
+// sigma ~ batches^-1/2 at a fixed batch size: aim 2 % past the target.  No
+// dose in the region yet (sigma-bar infinite): run to the cap.
 uint64_t ctd::sigma_plan(uint64_t have, double sig, double target, uint64_t max_batches) {
   if (sig <= target || have >= max_batches) return 0;
+  const uint64_t room = max_batches - have;
+  if (!(sig < INFINITY)) return room;
   const double want = std::ceil((double)have * (sig / target) * (sig / target) * 1.02);
-  uint64_t more = (uint64_t)std::max(1.0, want - (double)have);
-  return std::min(more, max_batches - have);
+  const double more = std::min(std::max(1.0, want - (double)have), (double)room);
+  return (uint64_t)more;
 }
 
 int ctd::run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count) {

@@ -321,6 +321,11 @@ def test_all_histories_miss(ctx):
     b = g["bal"]
     assert b.n_missed == 1000 and b.q_deposited == 0 and np.all(g["s1"] == 0)
     assert b.q_escaped == b.q_incident == 1000 * 60 * 2**24
+    # no dose anywhere: sigma-bar is infinite and run-to-sigma stops at its cap
+    with Case(ctx, wl) as c:
+        sig = L.ctd_run_to_sigma(ctx, c.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, 1000, 20_000)
+        assert sig == float("inf")
+        assert c.stats().n_histories == 20_000
 
 
 def test_error_paths(ctx):
