@@ -47,8 +47,7 @@ int ctd::macro_edge(const ctd_grid &g, int requested) {
   // about 1.6 cm: long enough that a crossing is rarer than a fictitious
   // step would be, short enough to separate bone from soft tissue
   const double h = std::min(g.dx, std::min(g.dy, g.dz));
-  const int e = (int)std::lround(1.6 / h);
-  return std::max(1, std::min(64, e));
+  return std::max(1, (int)std::lround(std::min(1.6 / h, 64.0)));
 }
 
 int ctd::macro_cells(const ctd_grid &g, int cs, int n[3]) {
