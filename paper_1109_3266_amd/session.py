@@ -83,20 +83,26 @@ class Inputs:
 
     def __init__(self, ctx, wl, mu_rho=None):
         self.ctx = ctx
-        eg = L.ctd_egrid()
-        eg.e0, eg.de, eg.ne = wl.e0, wl.de, wl.ne
-        comp, rayl = surfaces(wl)
-        self.ms = L.ctd_materials_load(ctx, eg, wl.mu_rho() if mu_rho is None else mu_rho,
-                                       comp, int(comp.ndim == 3), rayl)
-        self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
-        self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
+        self.ms = self.sp = self.geo = None
+        try:
+            eg = L.ctd_egrid()
+            eg.e0, eg.de, eg.ne = wl.e0, wl.de, wl.ne
+            comp, rayl = surfaces(wl)
+            self.ms = L.ctd_materials_load(ctx, eg, wl.mu_rho() if mu_rho is None else mu_rho,
+                                           comp, int(comp.ndim == 3), rayl)
+            self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
+            self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
+        except BaseException:
+            self.close()
+            raise
 
     def close(self):
-        if self.ms is not None:
-            L.ctd_geometry_release(self.ctx, self.geo)
-            L.ctd_spectrum_release(self.ctx, self.sp)
-            L.ctd_materials_release(self.ctx, self.ms)
-            self.ms = None
+        for release, name in [(L.ctd_geometry_release, "geo"), (L.ctd_spectrum_release, "sp"),
+                              (L.ctd_materials_release, "ms")]:
+            h = getattr(self, name)
+            if h is not None:
+                release(self.ctx, h)
+                setattr(self, name, None)
 
 
 def params(wl, seed=None, n_batches=None, rho_min=0.05, tracking=None,
@@ -132,17 +138,22 @@ class Case:
         if mem == L.CTD_MEM_HOST:
             m = np.ascontiguousarray(m, dtype=np.uint8)
             r = np.ascontiguousarray(r, dtype=np.float32)
-        self.ph = L.ctd_phantom_load(ctx, _grid(wl.grid), m, r, mem)
-        eg = L.ctd_egrid()
-        eg.e0, eg.de, eg.ne = wl.e0, wl.de, wl.ne
-        comp, rayl = surfaces(wl)
-        mu = wl.mu_rho() if mu_rho is None else mu_rho
-        self.ms = L.ctd_materials_load(ctx, eg, mu, comp, int(comp.ndim == 3), rayl)
-        self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
-        self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
-        p = params(wl, seed, n_batches, rho_min, tracking, macro_cell)
-        self.params = p
-        self.cs = L.ctd_case_create(ctx, self.ph, self.ms, self.sp, self.geo, p)
+        self.cs = self.ph = self.ms = self.sp = self.geo = None
+        try:
+            self.ph = L.ctd_phantom_load(ctx, _grid(wl.grid), m, r, mem)
+            eg = L.ctd_egrid()
+            eg.e0, eg.de, eg.ne = wl.e0, wl.de, wl.ne
+            comp, rayl = surfaces(wl)
+            mu = wl.mu_rho() if mu_rho is None else mu_rho
+            self.ms = L.ctd_materials_load(ctx, eg, mu, comp, int(comp.ndim == 3), rayl)
+            self.sp = L.ctd_spectrum_set(ctx, wl.spectrum_lo, wl.spectrum_width, wl.spectrum_w)
+            self.geo = L.ctd_geometry_set(ctx, _geom(wl.geometry))
+            p = params(wl, seed, n_batches, rho_min, tracking, macro_cell)
+            self.params = p
+            self.cs = L.ctd_case_create(ctx, self.ph, self.ms, self.sp, self.geo, p)
+        except BaseException:
+            self._release_inputs()   # what was created before the failing call
+            raise
 
     # convenience pass-throughs
     def run(self, n):
@@ -160,14 +171,19 @@ class Case:
     def stats(self):
         return L.ctd_read_stats(self.ctx, self.cs)
 
+    def _release_inputs(self):
+        for release, name in [(L.ctd_geometry_release, "geo"), (L.ctd_spectrum_release, "sp"),
+                              (L.ctd_materials_release, "ms"), (L.ctd_phantom_release, "ph")]:
+            h = getattr(self, name)
+            if h is not None:
+                release(self.ctx, h)
+                setattr(self, name, None)
+
     def close(self):
         if self.cs is not None:
             L.ctd_case_destroy(self.ctx, self.cs)
-            L.ctd_geometry_release(self.ctx, self.geo)
-            L.ctd_spectrum_release(self.ctx, self.sp)
-            L.ctd_materials_release(self.ctx, self.ms)
-            L.ctd_phantom_release(self.ctx, self.ph)
             self.cs = None
+            self._release_inputs()
 
     def __enter__(self):
         return self
