@@ -53,18 +53,25 @@ def _solo(ctx, wl):
     return sig, s1, hi, lo, nb
 
 
-def test_server_results_identical_to_solo(ctx):
-    say("server vs solo")
+@pytest.mark.parametrize("tally_mode", [None, 2])
+def test_server_results_identical_to_solo(ctx, tally_mode):
+    """Each request's sums equal its solo run's; the rounds may use another
+    launch configuration (here the LDS sub-tally) than the solo runs."""
+    say(f"server vs solo, tally mode {tally_mode}")
     wls = _requests(5)
     # model variants ride the same rounds: macro-cell tracking, an Alg. A1
-    # fluence map, bound-electron Compton
+    # fluence map, bound-electron Compton, the automatic tracking choice
     wls[1].tracking = L.CTD_TRACK_MACRO
     g = wls[2].geometry
     g["fluence"] = W.bowtie_fluence(32, 24, (g["a1"] - g["a0"]) / 2, (g["b1"] - g["b0"]) / 2)
     g["fluence_chains"] = 64
     wls[3].compton = "wh"
+    wls[4].tracking = L.CTD_TRACK_AUTO
     solo = [_solo(ctx, wl) for wl in wls]
-    sv = L.ctd_server_start(0, _cfg())
+    cfg = _cfg()
+    if tally_mode is not None:
+        cfg.tuning = L.ctd_tuning(256, 5, 16, 1024, tally_mode)
+    sv = L.ctd_server_start(0, cfg)
     inputs = [Inputs(ctx, wl) for wl in wls]
     try:
         tickets = []
