@@ -29,6 +29,7 @@ METRIC = "photon histories/s + time-to-1%-σ dose; batched serving p50/p99 laten
 # main-leg workloads (the benchmark is water_cbct; the others serve profiling)
 WORKLOADS = {
     "water_cbct": "water_cbct_128x128x100_cyl30cm_120kVp_cbct360",
+    "tiny": "water_cube_32cube_0.5cm_60keV_pencil",
     "head": "head_256x256x160_0.1cm_100kVp_halffan200",
     "head_helical": "head_256x256x160_0.1cm_120kVp_helical6turns_pitch1",
     "water_box_bowtie": "water_box_50cube_0.4cm_125kVp_bowtie128x96",
@@ -445,6 +446,8 @@ def main():
     ap.add_argument("--workload", default="water_cbct", choices=sorted(WORKLOADS),
                     help="workload of the main leg (profiling; the default is the benchmark)")
     ap.add_argument("--tracking", default="global", choices=["global", "macro"])
+    ap.add_argument("--tally-mode", type=int, default=None, choices=[0, 1, 2],
+                    help="force the launch's tally mode (profiling the contention strategy)")
     ap.add_argument("--legs", default="main,sigma,batched,serving,extensions",
                     help="comma list of legs to run (--quick = main)")
     args = ap.parse_args()
@@ -479,6 +482,9 @@ def main():
     tuning = L.ctd_get_tuning(ctx, case.cs)
     if not args.no_tune:
         tuning = L.ctd_autotune(ctx, case.cs, 20_000_000)
+    if args.tally_mode is not None:
+        tuning.tally_mode = args.tally_mode
+        L.ctd_set_tuning(ctx, case.cs, tuning)
     log(f"tuning block={tuning.block} waves/simd={tuning.waves_per_simd} "
         f"refill_min={tuning.refill_min} chunk={tuning.chunk} tally_mode={tuning.tally_mode}")
 
@@ -543,7 +549,9 @@ def main():
                 atomic=dict(achieved=atom_rate, peak=atom_peak, unit="int64 atomics/s",
                             frac=atom_rate / atom_peak,
                             peak_source="ctd_microbench random 64-bit atomics into a "
-                                        "tally-sized array, measured in this run"))
+                                        "tally-sized array, measured in this run",
+                            note="tally updates per second; with tally_mode 2 part of "
+                                 "them are LDS atomics" if tuning.tally_mode == 2 else ""))
     out = dict(metric=METRIC, value=value, unit="histories/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=wall * 1e3 / args.steps, higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
