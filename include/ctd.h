@@ -240,7 +240,8 @@ int32_t ctd_surface_build(int32_t n_e, int32_t n_mu, const double *pdf, int32_t 
 /* Voxel phantom (Sec. 2.2.1 inputs): material id mat[] and density rho[].
  * mem = CTD_MEM_HOST or CTD_MEM_DEVICE; both arrays are read during the call
  * only (the library keeps its own packed copy).  CTD_EINVAL on dims <= 0,
- * spacing <= 0, rho not finite or < 0. */
+ * spacing <= 0, rho not finite or < 0, more than 2^31 - 1 voxels, or
+ * ny * nz > 2^24. */
 int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8_t *mat, const float *rho,
                          int32_t mem, ctd_phantom **out);
 /* CTD_EBUSY while a case refers to it. */

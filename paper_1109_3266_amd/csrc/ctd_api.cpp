@@ -186,6 +186,8 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
   const int64_t V = (int64_t)g->nx * g->ny * g->nz;
   NEED(ctx, V < ((int64_t)1 << 31), "at most 2^31 - 1 voxels");
   NEED(ctx, g->nx < (1 << 24) && g->ny < (1 << 24) && g->nz < (1 << 24), "axis too long");
+  // the transport forms voxel indices with 24-bit multiplies: (z ny + y) nx + x
+  NEED(ctx, (int64_t)g->ny * g->nz <= ((int64_t)1 << 24), "ny * nz must be at most 2^24");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctd_phantom *ph = new (std::nothrow) ctd_phantom();
   if (!ph) return CTD_ENOMEM;

@@ -348,6 +348,13 @@ def test_error_paths(ctx):
     nan.rho[0, 0, 1] = np.nan
     with pytest.raises(L.CtdError):
         Case(ctx, nan)
+    # voxel indices use 24-bit multiplies: ny * nz is capped at 2^24
+    g = L.ctd_grid()
+    g.nx, g.ny, g.nz, g.dx, g.dy, g.dz = 1, 4097, 4097, 0.1, 0.1, 0.1
+    wide = np.zeros(4097 * 4097, np.uint8)
+    with pytest.raises(L.CtdError) as e:
+        L.ctd_phantom_load(ctx, g, wide, wide.astype(np.float32))
+    assert e.value.code == L.CTD_EINVAL and "2^24" in str(e.value)
     with pytest.raises(L.CtdError):
         Case(ctx, wl, n_batches=1)
     hi = W.tiny()
