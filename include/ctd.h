@@ -405,7 +405,9 @@ int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out, uint64_t 
  * the same batch size, so its result is identical alone or among others.
  * Material sets, spectra and geometries may come from any context on the same
  * device; a request holds them from submission until it finishes (releasing
- * one earlier returns CTD_EBUSY). */
+ * one earlier returns CTD_EBUSY).  The calls may come from any host thread,
+ * except ctd_server_stop, which must not overlap another call on the same
+ * server.  An admission never evicts the phantom it is admitting. */
 typedef struct {
   uint64_t hbm_budget_bytes;  /* device memory for request tallies + resident phantoms */
   uint64_t batch_histories;   /* histories per batch, every request */
@@ -445,11 +447,14 @@ int32_t ctd_server_submit(ctd_server *sv, uint64_t phantom_key, ctd_matset *ms,
                           ctd_spectrum *sp, ctd_geometry *geo, const ctd_params *p,
                           double sigma_target, uint64_t *ticket);
 int32_t ctd_server_poll(ctd_server *sv, uint64_t ticket, ctd_request_info *info);
-/* Block until done (CTD_OK), cancelled (CTD_ECANCELLED) or failed. */
+/* Block until done (CTD_OK), cancelled (CTD_ECANCELLED) or failed (its
+ * status); CTD_ENOTFOUND if the ticket is unknown or released meanwhile. */
 int32_t ctd_server_wait(ctd_server *sv, uint64_t ticket, ctd_request_info *info);
-/* Exact sums of a done request (host copies; V-sized caller arrays). */
-int32_t ctd_server_read_tally(ctd_server *sv, uint64_t ticket, int64_t *s1, uint64_t *s2_hi,
-                              uint64_t *s2_lo, uint32_t *n_batches);
+/* Exact sums of a done request, copied from host memory into caller arrays
+ * of n_voxels entries each (any may be null); CTD_EINVAL unless n_voxels is
+ * the phantom's voxel count, CTD_EBUSY before the request is done. */
+int32_t ctd_server_read_tally(ctd_server *sv, uint64_t ticket, uint64_t n_voxels, int64_t *s1,
+                              uint64_t *s2_hi, uint64_t *s2_lo, uint32_t *n_batches);
 /* Forget a finished request (frees its host results). */
 int32_t ctd_server_release(ctd_server *sv, uint64_t ticket);
 int32_t ctd_server_cancel(ctd_server *sv, uint64_t ticket);

@@ -104,13 +104,16 @@ static int sv_err(ctd_server *sv, int code, const char *fmt, ...) {
 // ---------------------------------------------------------- server thread
 
 // Evict unused resident phantoms (least recently used first) until `need`
-// more bytes fit.  Called with the lock held.
-static bool make_room(ctd_server *sv, uint64_t need) {
+// more bytes fit; `keep`, the phantom of the request being admitted, is never
+// evicted (its size is not part of `need` when it is resident).  Called with
+// the lock held.
+static bool make_room(ctd_server *sv, uint64_t need, const PhantomEntry *keep) {
   while (sv->used_bytes + need > sv->cfg.hbm_budget_bytes) {
     PhantomEntry *victim = nullptr;
     for (auto &kv : sv->phantoms) {
       PhantomEntry &e = kv.second;
-      if (e.dev && e.users == 0 && (!victim || e.last_use < victim->last_use)) victim = &e;
+      if (&e != keep && e.dev && e.users == 0 && (!victim || e.last_use < victim->last_use))
+        victim = &e;
     }
     if (!victim) return false;
     ctd_phantom_release(sv->ctx, victim->dev);
@@ -178,7 +181,7 @@ static void admit(ctd_server *sv) {
       finish(sv, r, 4, CTD_ENOMEM);
       continue;
     }
-    if (!make_room(sv, need)) break;  // wait for running requests to finish
+    if (!make_room(sv, need, &e)) break;  // wait for running requests to finish
     int rc = CTD_OK;
     if (!e.dev) {
       rc = ctd_phantom_load(sv->ctx, &e.g, e.mat.data(), e.rho.data(), CTD_MEM_HOST, &e.dev);
@@ -413,8 +416,14 @@ extern "C" int32_t ctd_server_wait(ctd_server *sv, uint64_t ticket, ctd_request_
   std::unique_lock<std::mutex> lk(sv->mu);
   auto it = sv->all.find(ticket);
   if (it == sv->all.end()) return CTD_ENOTFOUND;
-  Request *r = it->second.get();
-  sv->cv_done.wait(lk, [&] { return r->state >= 2; });
+  // look the ticket up again on every wake-up: another thread may release it
+  Request *r = nullptr;
+  sv->cv_done.wait(lk, [&] {
+    it = sv->all.find(ticket);
+    r = it == sv->all.end() ? nullptr : it->second.get();
+    return !r || r->state >= 2;
+  });
+  if (!r) return CTD_ENOTFOUND;
   if (info) fill_info(r, info);
   return r->state == 2 ? CTD_OK : r->status;
 }
@@ -429,8 +438,9 @@ extern "C" int32_t ctd_server_cancel(ctd_server *sv, uint64_t ticket) {
   return CTD_OK;
 }
 
-extern "C" int32_t ctd_server_read_tally(ctd_server *sv, uint64_t ticket, int64_t *s1,
-                                         uint64_t *s2_hi, uint64_t *s2_lo, uint32_t *n_batches) {
+extern "C" int32_t ctd_server_read_tally(ctd_server *sv, uint64_t ticket, uint64_t n_voxels,
+                                         int64_t *s1, uint64_t *s2_hi, uint64_t *s2_lo,
+                                         uint32_t *n_batches) {
   if (!sv) return CTD_EINVAL;
   std::lock_guard<std::mutex> lk(sv->mu);
   auto it = sv->all.find(ticket);
@@ -438,6 +448,9 @@ extern "C" int32_t ctd_server_read_tally(ctd_server *sv, uint64_t ticket, int64_
   const Request *r = it->second.get();
   if (r->state != 2) return sv_err(sv, CTD_EBUSY, "request not done");
   const size_t V = r->s1.size();
+  if (n_voxels != (uint64_t)V)
+    return sv_err(sv, CTD_EINVAL, "arrays of %llu entries for a %llu-voxel phantom",
+                  (unsigned long long)n_voxels, (unsigned long long)V);
   if (s1) std::memcpy(s1, r->s1.data(), 8 * V);
   if (s2_hi) std::memcpy(s2_hi, r->s2_hi.data(), 8 * V);
   if (s2_lo) std::memcpy(s2_lo, r->s2_lo.data(), 8 * V);
@@ -452,6 +465,7 @@ extern "C" int32_t ctd_server_release(ctd_server *sv, uint64_t ticket) {
   if (it == sv->all.end()) return CTD_ENOTFOUND;
   if (it->second->state < 2) return sv_err(sv, CTD_EBUSY, "request still queued or running");
   sv->all.erase(it);
+  sv->cv_done.notify_all();  // waiters on this ticket return CTD_ENOTFOUND
   return CTD_OK;
 }
 

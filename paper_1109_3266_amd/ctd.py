@@ -180,7 +180,7 @@ _SIGS = {
     "ctd_server_submit": (I32, [P, U64, P, P, P, C.POINTER(ctd_params), F64, C.POINTER(U64)]),
     "ctd_server_poll": (I32, [P, U64, C.POINTER(ctd_request_info)]),
     "ctd_server_wait": (I32, [P, U64, C.POINTER(ctd_request_info)]),
-    "ctd_server_read_tally": (I32, [P, U64, P, P, P, C.POINTER(U32)]),
+    "ctd_server_read_tally": (I32, [P, U64, U64, P, P, P, C.POINTER(U32)]),
     "ctd_server_release": (I32, [P, U64]),
     "ctd_server_cancel": (I32, [P, U64]),
     "ctd_server_read_stats": (I32, [P, C.POINTER(ctd_server_stats)]),
@@ -495,7 +495,7 @@ def ctd_server_read_tally(sv, ticket: int, V: int):
     hi = np.zeros(V, np.uint64)
     lo = np.zeros(V, np.uint64)
     nb = C.c_uint32()
-    _scheck(lib().ctd_server_read_tally(sv, int(ticket), ptr(s1), ptr(hi), ptr(lo),
+    _scheck(lib().ctd_server_read_tally(sv, int(ticket), int(V), ptr(s1), ptr(hi), ptr(lo),
                                         C.byref(nb)), sv)
     return s1, hi, lo, nb.value
 

@@ -174,3 +174,70 @@ def test_server_cancel_and_errors(ctx):
     finally:
         L.ctd_server_stop(sv)
         inp.close()
+
+
+def _resident_while_running(ctx, wl, inp):
+    """(phantom bytes, phantom + case bytes) the server counts for `wl`: read
+    while an out-of-reach request runs, then after cancelling it."""
+    sv = L.ctd_server_start(0, _cfg(max_h=10**15))
+    try:
+        L.ctd_server_add_phantom(sv, 0, grid(wl), wl.mat, wl.rho)
+        t = L.ctd_server_submit(sv, 0, inp.ms, inp.sp, inp.geo, params(wl), 1e-9)
+        for _ in range(500):
+            if L.ctd_server_poll(sv, t).state == 1:
+                break
+            time.sleep(0.01)
+        both = L.ctd_server_read_stats(sv).resident_bytes
+        L.ctd_server_cancel(sv, t)
+        rc, _ = L.ctd_server_wait(sv, t)
+        assert rc == L.CTD_ECANCELLED
+        ph = L.ctd_server_read_stats(sv).resident_bytes
+    finally:
+        L.ctd_server_stop(sv)
+    assert 0 < ph < both
+    return ph, both
+
+
+def test_server_admission_keeps_own_phantom(ctx):
+    """A resident phantom is never evicted by the admission of a request on it:
+    with A and B resident and room for A's tallies only once B is gone, a
+    second request on A (the least recently used) evicts B and reuses A."""
+    say("server eviction keeps the admitted phantom")
+    rng = np.random.default_rng(31)
+    wls = [W.batched_case(rng, 9100 + i, f"e{i}", size_scale=0.25) for i in range(6)]
+    wls.sort(key=lambda w: w.n_voxels)
+    a, b = wls[-1], wls[0]
+    assert a.n_voxels > b.n_voxels
+    ia, ib = Inputs(ctx, a), Inputs(ctx, b)
+    try:
+        pa, pca = _resident_while_running(ctx, a, ia)
+        pb, pcb = _resident_while_running(ctx, b, ib)
+        ca, cb = pca - pa, pcb - pb
+        assert ca > cb
+        delta = min(pb, ca - cb) // 2
+        budget = pa + pb + ca - delta   # A + B + B's case fit; A + B + A's case do not
+        assert pa + ca <= budget and pa + pb + cb <= budget < pa + pb + ca
+        sv = L.ctd_server_start(0, _cfg(budget=budget))
+        try:
+            L.ctd_server_add_phantom(sv, 0, grid(a), a.mat, a.rho)
+            L.ctd_server_add_phantom(sv, 1, grid(b), b.mat, b.rho)
+            out = []
+            for key, wl, inp in [(0, a, ia), (1, b, ib), (0, a, ia)]:
+                t = L.ctd_server_submit(sv, key, inp.ms, inp.sp, inp.geo, params(wl), TARGET)
+                rc, info = L.ctd_server_wait(sv, t)
+                assert rc == L.CTD_OK, L.ctd_server_last_error(sv)
+                out.append(L.ctd_server_read_tally(sv, t, wl.n_voxels))
+                if key == 1:
+                    with pytest.raises(L.CtdError) as e:   # arrays of the wrong size
+                        L.ctd_server_read_tally(sv, t, wl.n_voxels + 1)
+                    assert e.value.code == L.CTD_EINVAL
+            st = L.ctd_server_read_stats(sv)
+            assert (st.phantom_loads, st.phantom_hits, st.evictions) == (2, 1, 1)
+            assert st.resident_bytes == pa   # only A stays resident, counted in full
+            for x, y in zip(out[0], out[2]):
+                assert np.array_equal(x, y)
+        finally:
+            L.ctd_server_stop(sv)
+    finally:
+        ia.close()
+        ib.close()
