@@ -982,6 +982,23 @@ static int check_headroom(ctd_ctx *ctx, ctd_case *cs, uint64_t n) {
   return CTD_OK;
 }
 
+// Add the elapsed times of a case's completed rounds to its totals and free
+// their events; rounds still in flight stay queued.
+static void harvest_timing(ctd_case *cs) {
+  size_t done = 0;
+  for (auto &t : cs->timing) {
+    if (hipEventQuery(t.c) != hipSuccess) break;  // rounds complete in order
+    float ms1 = 0.f, ms2 = 0.f;
+    if (hipEventElapsedTime(&ms1, t.a, t.b) == hipSuccess) cs->transport_ms += ms1;
+    if (hipEventElapsedTime(&ms2, t.b, t.c) == hipSuccess) cs->fold_ms += ms2;
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.c);
+    ++done;
+  }
+  cs->timing.erase(cs->timing.begin(), cs->timing.begin() + (long)done);
+}
+
 // Enqueue one round over several cases (each with its own batch size), then
 // fold every participating case.
 int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vector<uint64_t> &n,
@@ -1013,7 +1030,17 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
   }
   if (items.empty()) return CTD_OK;
   ctd_case *first = cases[0];
-  ctd_case::Timing tm{};
+  // the round's timing events; destroyed here unless the round completes
+  struct TimingGuard {
+    ctd_case::Timing tm{};
+    bool keep = false;
+    ~TimingGuard() {
+      if (keep) return;
+      for (hipEvent_t e : {tm.a, tm.b, tm.c})
+        if (e) (void)hipEventDestroy(e);
+    }
+  } guard;
+  ctd_case::Timing &tm = guard.tm;
   const bool timed = cases.size() == 1;
   if (timed) {
     HIPCHK(ctx, hipEventCreate(&tm.a));
@@ -1052,7 +1079,10 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
   }
   if (timed) {
     HIPCHK(ctx, hipEventRecord(tm.c, ctx->stream));
+    // a long run without a stats read keeps only the rounds still in flight
+    if (first->timing.size() >= 64) harvest_timing(first);
     first->timing.push_back(tm);
+    guard.keep = true;
   }
   return CTD_OK;
 }
@@ -1303,15 +1333,7 @@ extern "C" int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out) {
   HIPCHK(ctx, hipMemcpy(w, cs->d_acc, sizeof w, hipMemcpyDeviceToHost));
   uint64_t a[ACC_COUNT];
   for (int i = 0; i < ACC_COUNT; ++i) a[i] = w[kAccTotal + 2 * i];
-  for (auto &t : cs->timing) {
-    float ms1 = 0.f, ms2 = 0.f;
-    if (hipEventElapsedTime(&ms1, t.a, t.b) == hipSuccess) cs->transport_ms += ms1;
-    if (hipEventElapsedTime(&ms2, t.b, t.c) == hipSuccess) cs->fold_ms += ms2;
-    (void)hipEventDestroy(t.a);
-    (void)hipEventDestroy(t.b);
-    (void)hipEventDestroy(t.c);
-  }
-  cs->timing.clear();
+  harvest_timing(cs);
   if (cs->batches >= 2) {
     double s;
     if (sigma_now(ctx, cs, CTD_SIGMA_LOCAL, 0.5, &s) == CTD_OK) cs->sigma_local = s;

@@ -416,6 +416,22 @@ def test_run_to_sigma_and_host_sigma(ctx):
         np.testing.assert_allclose(np.sqrt(var), sd_o, rtol=1e-9, atol=1e-30)
 
 
+def test_long_run_stats_timing(ctx):
+    """Rounds timed in a run of many batches (the case keeps only the rounds
+    still in flight between stats reads) add up to positive totals."""
+    say("timing over 150 batches")
+    wl = W.tiny()
+    with Case(ctx, wl) as c:
+        L.ctd_run_batches(ctx, c.cs, 2000, 150)
+        st = c.stats()
+        assert st.n_batches == 150 and st.n_histories == 300_000
+        assert st.transport_ms > 0 and st.fold_ms > 0
+        t1 = st.transport_ms
+        L.ctd_run_batches(ctx, c.cs, 2000, 70)
+        st = c.stats()
+        assert st.n_batches == 220 and st.transport_ms > t1
+
+
 def test_full_size_water_cbct_sampled(ctx):
     """The benchmark workload at full size (1e9 histories, 10 batches) in the
     default launch configuration: exact balance, incident energy against its
