@@ -276,7 +276,8 @@ int32_t ctd_geometry_release(ctd_ctx *ctx, ctd_geometry *geo);
  * from the phantom's per-material maximum density and allocates the batch
  * tally T_b, S1 = sum_b T_b and S2 = sum_b T_b^2 (128-bit).
  * CTD_EINVAL if a material id >= M, the energy grid does not cover
- * [e_cut, E_max] or n_batches < 2; CTD_ENOMEM. */
+ * [e_cut, E_max], n_batches < 2, or the phantom or material set was loaded
+ * through a context on another device; CTD_ENOMEM. */
 int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms, ctd_spectrum *sp,
                         ctd_geometry *geo, const ctd_params *p, ctd_case **out);
 int32_t ctd_case_destroy(ctd_ctx *ctx, ctd_case *cs);

@@ -191,7 +191,7 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctd_phantom *ph = new (std::nothrow) ctd_phantom();
   if (!ph) return CTD_ENOMEM;
-  ph->ctx = ctx;
+  ph->device = ctx->device;
   ph->g = *g;
   ph->V = V;
   uint8_t *dmat = nullptr;
@@ -323,6 +323,7 @@ extern "C" int32_t ctd_materials_load(ctd_ctx *ctx, const ctd_egrid *eg, int32_t
   HIPCHK(ctx, hipSetDevice(ctx->device));
   ctd_matset *ms = new (std::nothrow) ctd_matset();
   if (!ms) return CTD_ENOMEM;
+  ms->device = ctx->device;
   ms->eg = *eg;
   ms->M = M;
   ms->ncomp = ncomp;
@@ -538,6 +539,9 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
   *out = nullptr;
   NEED(ctx, ph && ms && sp && geo && p, "null argument");
   NEED(ctx, p->n_batches >= 2, "n_batches must be >= 2");
+  NEED(ctx, ph->device == ctx->device && ms->device == ctx->device,
+       "phantom (device %d) and material set (device %d) must be on the context's device %d",
+       ph->device, ms->device, ctx->device);
   NEED(ctx, ph->max_mat < ms->M, "phantom uses material %d but only %d are loaded", ph->max_mat,
        ms->M);
   const double emax = e_max_of(sp);

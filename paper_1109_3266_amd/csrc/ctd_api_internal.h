@@ -46,7 +46,7 @@ struct ctd_ctx {
 };
 
 struct ctd_phantom {
-  ctd_ctx *ctx = nullptr;
+  int device = 0;         // device holding the arrays
   ctd_grid g{};
   int64_t V = 0;
   uint2 *vox = nullptr;   // packed (rho bits, material) records
@@ -61,6 +61,7 @@ struct ctd_phantom {
 };
 
 struct ctd_matset {
+  int device = 0;         // device holding the tables
   ctd_egrid eg{};
   int M = 0, ncomp = 1, nzc = 0, nzr = 0;
   std::vector<float> mu_rho;  // host copy [M][ne][3]
