@@ -433,14 +433,24 @@ def test_long_run_stats_timing(ctx):
 
 
 def test_full_size_water_cbct_sampled(ctx):
-    """The benchmark workload at full size (1e9 histories, 10 batches) in the
-    default launch configuration: exact balance, incident energy against its
-    expectation, and 2000 logged histories paired one by one with the oracle."""
+    """The benchmark workload at full size (1e9 histories, 10 batches): exact
+    balance, incident energy against its expectation, and 2000 logged
+    histories paired one by one with the oracle; the kernel the benchmark
+    times (no event log, launch configuration chosen by the same autotuning)
+    gives the logged run's sums bit for bit."""
     wl = W.water_cbct()
     h0, nh = 500_000_000, 2000
     say("full-size water_cbct 1e9")
     g = gpu_run(ctx, wl, log=(h0, nh, 100_000))
     check_balance(g, wl.n_histories)
+    with Case(ctx, wl) as c:
+        t = L.ctd_autotune(ctx, c.cs, 20_000_000)
+        say(f"benchmark configuration {t.block} {t.waves_per_simd} {t.refill_min} {t.chunk} "
+            f"{t.tally_mode}")
+        c.run(wl.n_histories)
+        s1, hi, lo, nb = c.tally()
+    assert nb == g["nb"] and np.array_equal(s1, g["s1"])
+    assert np.array_equal(hi, g["s2_hi"]) and np.array_equal(lo, g["s2_lo"])
     oc = O.OracleCase(wl)
     bs = O.batch_sizes(wl.n_histories, 10)
     cnt = O.alloc_bins(bs[0], oc.bin_w).astype(np.float64)
