@@ -745,6 +745,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
   if (cache) clear_cache(cache, lane);
   Photon p;
   bool alive = false;
+  const uint32_t first_chunk =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (uint32_t)w);
 
   for (;;) {
     const unsigned long long dead = __ballot(!alive);
@@ -767,9 +769,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
       }
       // claim chunks until the pool has work or the queue is empty
       while (pool_next >= pool_end && pend < 0 && !queue_done) {
-        unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(chunk_ctr, 1ull);
-        t = lane0_u64(t);
+        // a wave's first chunk is its index in the grid (no counter atomic,
+        // so the launch does not start with every wave queueing on one
+        // address); the counter hands out the chunks after those
+        unsigned long long t = first_chunk;
+        if (cur >= 0) {
+          if (lane == 0) t = atomicAdd(chunk_ctr, 1ull);
+          t = lane0_u64(t) + (uint64_t)gridDim.x * (blockDim.x >> 6);
+        }
         if (t >= total_chunks) {
           queue_done = true;
           break;
