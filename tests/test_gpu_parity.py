@@ -470,6 +470,13 @@ def test_full_size_head_grid_sampled(ctx):
     say("full-grid head 2e8")
     g = gpu_run(ctx, wl, log=(h0, nh, 100_000))
     check_balance(g, wl.n_histories)
+    # the unlogged kernel in the configuration the benchmark's tuner picks
+    with Case(ctx, wl) as c:
+        L.ctd_autotune(ctx, c.cs, 10_000_000)
+        c.run(wl.n_histories)
+        s1, hi, lo, nb = c.tally()
+    assert nb == g["nb"] and np.array_equal(s1, g["s1"])
+    assert np.array_equal(hi, g["s2_hi"]) and np.array_equal(lo, g["s2_lo"])
     oc = O.OracleCase(wl)
     assert np.array_equal(g["mu_max"], oc.mu_max)
     bs = O.batch_sizes(wl.n_histories, 10)
