@@ -949,9 +949,14 @@ __global__ void __launch_bounds__(256) k_fold(unsigned long long *__restrict__ T
     }
     __syncthreads();
   }
+  // Atomics on one address serialize at the memory side, so a block whose
+  // maximum does not exceed the recorded one skips its atomic.  The recorded
+  // maxima only grow (until the host clears them between launches), so a
+  // stale read can only add an atomic, never drop a needed one.
   if (threadIdx.x == 0) {
-    if (m1[0]) atomicMax(acc + kAccMaxS1, m1[0]);
-    if (m2[0]) atomicMax(acc + kAccMaxS2Hi, m2[0]);
+    const volatile unsigned long long *rec = acc;
+    if (m1[0] > rec[kAccMaxS1]) atomicMax(acc + kAccMaxS1, m1[0]);
+    if (m2[0] > rec[kAccMaxS2Hi]) atomicMax(acc + kAccMaxS2Hi, m2[0]);
   }
 }
 
