@@ -456,8 +456,9 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs the transport on a single "
-              "MI355X (histories shard across GPUs by id range; not built).", file=sys.stderr)
+        print("bench.py measures one GPU only: the transport runs on a single MI355X "
+              "(histories would shard across GPUs by id range; multi-GPU execution is not "
+              "implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
