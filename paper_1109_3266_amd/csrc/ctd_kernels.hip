@@ -954,9 +954,12 @@ __global__ void __launch_bounds__(256) k_fold(unsigned long long *__restrict__ T
   // maxima only grow (until the host clears them between launches), so a
   // stale read can only add an atomic, never drop a needed one.
   if (threadIdx.x == 0) {
-    const volatile unsigned long long *rec = acc;
-    if (m1[0] > rec[kAccMaxS1]) atomicMax(acc + kAccMaxS1, m1[0]);
-    if (m2[0] > rec[kAccMaxS2Hi]) atomicMax(acc + kAccMaxS2Hi, m2[0]);
+    const unsigned long long r1 =
+        __hip_atomic_load(acc + kAccMaxS1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long r2 =
+        __hip_atomic_load(acc + kAccMaxS2Hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (m1[0] > r1) atomicMax(acc + kAccMaxS1, m1[0]);
+    if (m2[0] > r2) atomicMax(acc + kAccMaxS2Hi, m2[0]);
   }
 }
 
@@ -1175,7 +1178,9 @@ static int grid_for(int64_t n, int block, int cap) {
 
 int launch_fold(unsigned long long *tally, int ncopies, long long *s1, unsigned long long *s2,
                 int64_t V, unsigned long long *acc, void *stream) {
-  hipLaunchKernelGGL(k_fold, dim3(grid_for(V, 256, 4096)), dim3(256), 0, (hipStream_t)stream,
+  // 1024 groups stream the arrays at full rate and keep the per-group
+  // maximum records (two loads, at most two atomics each) few
+  hipLaunchKernelGGL(k_fold, dim3(grid_for(V, 256, 1024)), dim3(256), 0, (hipStream_t)stream,
                      tally, ncopies, s1, s2, V, acc);
   return check_launch();
 }
