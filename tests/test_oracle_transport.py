@@ -243,6 +243,43 @@ def test_source_sampling_uniformity():
     assert stats.kstest((b - geo["b0"]) / (geo["b1"] - geo["b0"]), "uniform").pvalue > 1e-3
 
 
+def test_continuous_source_trajectory():
+    """n_proj = 0 is the paper's own form of Sec. 2.2.6: the source angle is
+    t uniform over the arc (phi0 + u1 * arc), not one of a set of projection
+    angles.  The source stays on the orbit, covers exactly the arc (a 200 deg
+    arc from 30 deg, as in the paper's head scan), is uniform over it, takes
+    its uniform from the second word of the history's source block, and the
+    field crossing at the isocentre stays uniform."""
+    wl = W.water_cbct(scale=8)
+    geo = dict(wl.geometry, nproj=0, phi0_deg=30.0, arc_deg=200.0)
+    wl.geometry = geo
+    c = O.OracleCase(wl)
+    N = 20_000
+    S = np.array([O.sample_source(c, h, 3) for h in range(N)])
+    iso = np.array(geo["iso"])
+    r = np.hypot(S[:, 0] - iso[0], S[:, 1] - iso[1])
+    assert np.allclose(r, geo["sad"], rtol=1e-12)
+    assert np.allclose(S[:, 2], iso[2], atol=1e-12)
+    phi = np.degrees(np.arctan2(S[:, 0] - iso[0], S[:, 1] - iso[1])) % 360.0
+    assert phi.min() >= 30.0 and phi.max() <= 230.0
+    assert stats.kstest((phi - 30.0) / 200.0, "uniform").pvalue > 1e-3
+    # no projection lattice: 20000 draws give ~20000 distinct angles
+    assert len(np.unique(np.round(phi, 9))) > 0.99 * N
+    key = [wl.seed & 0xFFFFFFFF, wl.seed >> 32]
+    for h in range(0, N, 997):
+        u1 = O.uniform(int(O.philox([0, h, 0, 0], key)[1]))
+        assert phi[h] == pytest.approx(30.0 + 200.0 * u1, abs=1e-9)
+    ph_ = np.radians(phi)
+    axis = -np.stack([np.sin(ph_), np.cos(ph_), 0 * ph_], 1)
+    t = -np.einsum("ij,ij->i", S[:, :3] - iso, axis) / np.einsum("ij,ij->i", S[:, 3:6], axis)
+    P = S[:, :3] + t[:, None] * S[:, 3:6] - iso
+    elat = np.stack([np.cos(ph_), -np.sin(ph_), 0 * ph_], 1)
+    a = np.einsum("ij,ij->i", P, elat)
+    assert stats.kstest((a - geo["a0"]) / (geo["a1"] - geo["a0"]), "uniform").pvalue > 1e-3
+    assert stats.kstest((P[:, 2] - geo["b0"]) / (geo["b1"] - geo["b0"]),
+                        "uniform").pvalue > 1e-3
+
+
 def test_history_layout_bin_major():
     wl = W.water_cbct(scale=8, n_histories=1000)
     c = O.OracleCase(wl)
