@@ -52,11 +52,15 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the kernel source's code: comment-only and blank lines and
-    trailing // comments do not count as a change of the kernel."""
+    """Hash of the transport kernel's source: the part of ctd_kernels.hip
+    before the set-up, fold and auxiliary kernels (its helpers, the step
+    functions and k_transport).  Comment-only and blank lines and trailing //
+    comments do not count as a change of the kernel."""
     p = os.path.join(ROOT, "paper_1109_3266_amd", "csrc", "ctd_kernels.hip")
     code = []
     for line in open(p, encoding="utf-8"):
+        if line.startswith("// MACRO tracking set-up"):
+            break
         s = line.split("//", 1)[0].rstrip()
         if s:
             code.append(s)

@@ -180,6 +180,10 @@ typedef struct {
   int32_t tracking;      /* CTD_TRACK_GLOBAL or CTD_TRACK_MACRO: the mode in use */
   uint64_t n_histories;  /* histories run so far */
   uint64_t n_crossings;  /* MACRO tracking: macro-cell boundary crossings */
+  /* Largest S1 and largest high word of S2 over the voxels, as recorded by
+   * the batch folds for the fixed-point headroom check of ctd_run (exact:
+   * equal to max(s1) and max(s2_hi) of ctd_read_tally). */
+  uint64_t max_s1, max_s2_hi;
 } ctd_stats;
 
 /* Launch configuration of the persistent transport kernel. */
@@ -276,8 +280,11 @@ int32_t ctd_geometry_release(ctd_ctx *ctx, ctd_geometry *geo);
  * from the phantom's per-material maximum density and allocates the batch
  * tally T_b, S1 = sum_b T_b and S2 = sum_b T_b^2 (128-bit).
  * CTD_EINVAL if a material id >= M, the energy grid does not cover
- * [e_cut, E_max], n_batches < 2, or the phantom or material set was loaded
- * through a context on another device; CTD_ENOMEM. */
+ * [e_cut, E_max], n_batches < 2, e_cut < 1 keV, a spectrum bin starts below
+ * 1 keV, or the phantom or material set was loaded through a context on
+ * another device; CTD_ENOMEM.  (The 1 keV rules keep the tally exact: a
+ * Compton scatter leaves E' > E/2, so every photon energy stays >= 0.5 keV,
+ * where float32 values are multiples of q.) */
 int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms, ctd_spectrum *sp,
                         ctd_geometry *geo, const ctd_params *p, ctd_case **out);
 int32_t ctd_case_destroy(ctd_ctx *ctx, ctd_case *cs);
@@ -306,8 +313,12 @@ int32_t ctd_run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch_histories, ui
 /* Add batches of batch_histories until sigma-bar (sigma_kind, threshold
  * dose_frac * D_max) <= target with >= n_batches batches, or max_histories
  * is reached: a pilot of n_batches batches, then the estimated remainder
- * (sigma ~ batches^-1/2), re-checked.  Synchronous; *achieved receives the
- * final sigma-bar (may be NULL). */
+ * (sigma ~ batches^-1/2), re-checked.  sigma-bar is the mean relative
+ * standard error of the dose over the high-dose region (Sec. 3.1; the
+ * standard error from the batch spread of Sec. 2.2.1).  Synchronous;
+ * *achieved receives the final sigma-bar (may be NULL).  CTD_EINVAL when the
+ * case already holds batches whose size differs from batch_histories by more
+ * than one history (the batch statistics need equal batches). */
 int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, double dose_frac,
                          int32_t sigma_kind, uint64_t batch_histories, uint64_t max_histories,
                          double *achieved);
@@ -322,7 +333,9 @@ int32_t ctd_run_many(ctd_ctx *ctx, ctd_case *const *cs, const uint64_t *n, int32
 /* Wait until all work enqueued for the case (its stream) is complete. */
 int32_t ctd_sync(ctd_ctx *ctx, ctd_case *cs);
 
-/* Compute sigma-bar on the device over the folded batches.  Synchronous. */
+/* Compute sigma-bar (Sec. 3.1, over the batch statistics of Sec. 2.2.1) on
+ * the device over the folded batches.  Synchronous.  CTD_EINVAL with fewer
+ * than 2 batches or batches whose sizes differ by more than one history. */
 int32_t ctd_sigma(ctd_ctx *ctx, ctd_case *cs, int32_t sigma_kind, double dose_frac,
                   double *out);
 
@@ -333,8 +346,10 @@ int32_t ctd_sigma(ctd_ctx *ctx, ctd_case *cs, int32_t sigma_kind, double dose_fr
 int32_t ctd_read_tally(ctd_ctx *ctx, ctd_case *cs, int64_t *s1, uint64_t *s2_hi,
                        uint64_t *s2_lo, uint32_t *n_batches);
 /* Dose per history [Gy] and the variance of that mean [Gy^2] per voxel, from
- * the exact sums (batch means; numerator formed in 192-bit integers).  Voxels
- * of zero density report 0.  Synchronous; needs >= 2 equal-size batches. */
+ * the exact sums (Sec. 2.2.1: the mean over batches and its uncertainty from
+ * their spread; numerator formed in 192-bit integers).  Voxels of zero
+ * density report 0.  Synchronous; CTD_EINVAL unless >= 2 batches were folded
+ * and their sizes differ by at most one history (ctd_run's remainder). */
 int32_t ctd_read_dose(ctd_ctx *ctx, ctd_case *cs, double *dose, double *var_of_mean);
 /* Device pointers of the case's S1 (int64 [V]) and S2 (uint64 [V][2], lo
  * then hi), valid until the case is destroyed. */

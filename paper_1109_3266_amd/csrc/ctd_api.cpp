@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "ctd_api_internal.h"
+#include "ctd_headroom.h"
 #include "ctd_tables.h"
 
 using namespace ctd;
@@ -549,6 +550,17 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
   const double etop = eg.e0 + (eg.ne - 1) * eg.de;
   NEED(ctx, p->e_cut_kev >= eg.e0 && p->e_cut_kev > 0.0, "e_cut %.6g below the energy grid",
        p->e_cut_kev);
+  // Exact fixed point: a float32 energy >= 0.5 keV is a multiple of q =
+  // 2^-24 keV.  Sources start at >= 1 keV and a Compton scatter keeps
+  // E' > E/2, so a photon that scatters on (E' >= e_cut >= 1 keV) or is cut
+  // off (E' > E/2 >= 0.5 keV) never carries a non-multiple of q.
+  NEED(ctx, p->e_cut_kev >= 1.0, "e_cut %.6g keV: must be >= 1 keV (exact q = 2^-24 keV tally)",
+       p->e_cut_kev);
+  double emin = INFINITY;
+  for (double lo : sp->lo) emin = std::min(emin, lo);
+  NEED(ctx, emin >= 1.0,
+       "spectrum starts at %.6g keV: every bin must start at >= 1 keV (exact q = 2^-24 keV "
+       "tally)", emin);
   NEED(ctx, emax <= etop, "spectrum reaches %.6g keV beyond the energy grid (%.6g)", emax, etop);
   NEED(ctx, emax < 255.0, "spectrum energies must stay below 255 keV");
   NEED(ctx, !p->rayleigh || ms->d_rayl, "Rayleigh on but no Rayleigh surfaces loaded");
@@ -786,7 +798,8 @@ extern "C" int32_t ctd_case_reset(ctd_ctx *ctx, ctd_case *cs) {
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   cs->h_next = 0;
   cs->batches = 0;
-  cs->batch_sizes.clear();
+  cs->batch_min = UINT64_MAX;
+  cs->batch_max = 0;
   cs->s1_bound = cs->s2_bound = 0.0;
   cs->sigma_local = cs->sigma_paper = NAN;
   for (auto &t : cs->timing) {
@@ -889,6 +902,18 @@ extern "C" int32_t ctd_get_tuning(ctd_ctx *ctx, const ctd_case *cs, ctd_tuning *
 
 // ------------------------------------------------------------- launching
 
+// Grid of the persistent transport kernel: waves_per_simd resident waves on
+// each of the 4 SIMDs of every CU.
+static LaunchCfg launch_cfg(const ctd_ctx *ctx, const ctd_tuning &t) {
+  LaunchCfg cfg;
+  cfg.block = t.block;
+  cfg.grid = std::max(1, ctx->n_cu * 4 * t.waves_per_simd / (t.block / 64));
+  cfg.refill_min = t.refill_min;
+  cfg.chunk = t.chunk;
+  cfg.tally_mode = t.tally_mode;
+  return cfg;
+}
+
 // Stage one round (RoundCase table, bin prefixes, chunk counter) through a
 // pinned slot and launch the transport kernel on the ctx stream.
 int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const ctd_tuning &t,
@@ -935,13 +960,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
   }
   std::memset(h + ctr_off, 0, 256);
   HIPCHK(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
-  LaunchCfg cfg;
-  cfg.block = t.block;
-  const int waves_per_wg = t.block / 64;
-  cfg.grid = std::max(1, ctx->n_cu * 4 * t.waves_per_simd / waves_per_wg);
-  cfg.refill_min = t.refill_min;
-  cfg.chunk = t.chunk;
-  cfg.tally_mode = t.tally_mode;
+  const LaunchCfg cfg = launch_cfg(ctx, t);
   if (chunks > 0 &&
       launch_transport((const RoundCase *)d, nrc, chunks, (unsigned long long *)(d + ctr_off),
                        cfg, with_log, macro, ctx->stream) != 0)
@@ -962,23 +981,20 @@ int ctd::batch_prefix(ctd_ctx *ctx, const ctd_case *cs, uint64_t n,
   return CTD_OK;
 }
 
-// Fixed-point headroom before a batch of n histories.  A batch deposits at
-// most n * E_max * 2^24 q in any voxel.  The host keeps pessimistic bounds on
-// the largest S1 and S2 of any voxel and, when they get close to the int64 /
-// 128-bit limits, replaces them by the exact maxima the folds recorded.
+// Fixed-point headroom before a batch of n histories (ctd_headroom.h): the
+// pessimistic bounds first, the exact maxima the folds recorded when those
+// bounds get close to the int64 / 128-bit limits.
 static int check_headroom(ctd_ctx *ctx, ctd_case *cs, uint64_t n) {
-  const double bmax = (double)n * cs->e_max * 16777216.0;
-  if (bmax >= 0x1p62)
+  double s1 = 0.0, s2 = 0.0;
+  int v = headroom_bounds((double)n, cs->e_max, cs->s1_bound, cs->s2_bound, &s1, &s2);
+  if (v == kHeadroomBatch)
     return set_err(ctx, CTD_EOVERFLOW, "a batch of %.3g histories at %.4g keV exceeds 2^62 q",
                    (double)n, cs->e_max);
-  double s1 = cs->s1_bound + bmax, s2 = cs->s2_bound + bmax * bmax;
-  if (s1 >= 0x1p62 || s2 >= 0x1p126) {
+  if (v == kHeadroomNeedExact) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     unsigned long long m[2];
     HIPCHK(ctx, hipMemcpy(m, cs->d_acc + kAccMaxS1, sizeof m, hipMemcpyDeviceToHost));
-    s1 = (double)m[0] + bmax;
-    s2 = ((double)m[1] + 1.0) * 0x1p64 + bmax * bmax;
-    if (s1 >= 0x1p63 || s2 >= 0x1p128)
+    if (headroom_exact((double)n, cs->e_max, m[0], m[1], &s1, &s2) != kHeadroomOk)
       return set_err(ctx, CTD_EOVERFLOW, "a voxel's fixed-point sums would overflow");
   }
   cs->s1_bound = s1;
@@ -1079,7 +1095,8 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
       return hip_err(ctx, hipGetLastError(), "fold launch");
     cs->h_next += n[i];
     cs->batches += 1;
-    cs->batch_sizes.push_back(n[i]);
+    cs->batch_min = std::min(cs->batch_min, n[i]);
+    cs->batch_max = std::max(cs->batch_max, n[i]);
   }
   if (timed) {
     HIPCHK(ctx, hipEventRecord(tm.c, ctx->stream));
@@ -1144,8 +1161,23 @@ extern "C" int32_t ctd_sync(ctd_ctx *ctx, ctd_case *cs) {
   return CTD_OK;
 }
 
+int ctd::check_batch_sizes(ctd_ctx *ctx, const ctd_case *cs, uint64_t next_size) {
+  uint64_t lo = cs->batch_min, hi = cs->batch_max;
+  if (next_size) {
+    lo = std::min(lo, next_size);
+    hi = std::max(hi, next_size);
+  }
+  if (hi > lo + 1)
+    return set_err(ctx, CTD_EINVAL,
+                   "batch statistics need equal batches: sizes %llu .. %llu histories",
+                   (unsigned long long)lo, (unsigned long long)hi);
+  return CTD_OK;
+}
+
 int ctd::sigma_now(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *out) {
   if (cs->batches < 2) return set_err(ctx, CTD_EINVAL, "sigma needs >= 2 folded batches");
+  int rc = check_batch_sizes(ctx, cs, 0);
+  if (rc != CTD_OK) return rc;
   double rho_min = cs->p.sigma_rho_min;
   double *out_dev = ctx->sigma_scratch + 3 * kSigmaBlocks;
   if (launch_sigma(cs->d_s1, cs->d_s2, cs->ph->vox, cs->ph->V, cs->batches, rho_min, frac, kind,
@@ -1204,10 +1236,11 @@ extern "C" int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, d
   NEED(ctx, batch_histories > 0, "batch_histories must be positive");
   NEED(ctx, sigma_kind == CTD_SIGMA_LOCAL || sigma_kind == CTD_SIGMA_PAPER, "bad sigma kind");
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  int rc = check_batch_sizes(ctx, cs, batch_histories);
+  if (rc != CTD_OK) return rc;
   const uint64_t max_b = std::max<uint64_t>(max_histories / batch_histories, 2);
   uint64_t have = cs->batches;
   const uint64_t pilot = (uint64_t)cs->p.n_batches;
-  int rc = CTD_OK;
   if (have < pilot) {
     rc = run_batches(ctx, cs, batch_histories, std::min(pilot - have, max_b - std::min(max_b, have)));
     if (rc != CTD_OK) return rc;
@@ -1273,6 +1306,7 @@ static double var_numerator(int64_t s1, uint64_t hi, uint64_t lo, uint32_t nb) {
 extern "C" int32_t ctd_read_dose(ctd_ctx *ctx, ctd_case *cs, double *dose, double *var_of_mean) {
   if (!ctx || !cs) return CTD_EINVAL;
   NEED(ctx, cs->batches >= 2, "dose needs >= 2 folded batches");
+  if (int rc0 = check_batch_sizes(ctx, cs, 0); rc0 != CTD_OK) return rc0;
   const int64_t V = cs->ph->V;
   std::vector<int64_t> s1((size_t)V);
   std::vector<uint64_t> hi((size_t)V), lo((size_t)V);
@@ -1359,6 +1393,8 @@ extern "C" int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out) {
   out->tracking = cs->mc_cs > 0 ? CTD_TRACK_MACRO : CTD_TRACK_GLOBAL;
   out->n_histories = cs->h_next;
   out->n_crossings = a[ACC_N_CROSS];
+  out->max_s1 = w[kAccMaxS1];
+  out->max_s2_hi = w[kAccMaxS2Hi];
   return CTD_OK;
 }
 
@@ -1431,7 +1467,8 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
   // case's Metropolis-Hastings chains must only advance with its own runs)
   tw.h_next = 0;
   tw.batches = 0;
-  tw.batch_sizes.clear();
+  tw.batch_min = UINT64_MAX;
+  tw.batch_max = 0;
   tw.d_mh_state = nullptr;
   tw.d_mh_beam = nullptr;
   tw.mh_cap = 0;

@@ -120,7 +120,9 @@ struct ctd_case {
   uint64_t log_h0 = 0, log_h1 = 0, log_cap = 0;
   uint64_t h_next = 0;      // next history id
   uint32_t batches = 0;     // batches folded
-  std::vector<uint64_t> batch_sizes;
+  // smallest and largest batch folded so far: the batch statistics need
+  // batches of equal size (ctd_run's remainder makes some one larger)
+  uint64_t batch_min = UINT64_MAX, batch_max = 0;
   struct Timing {
     hipEvent_t a, b, c;
   };
@@ -148,6 +150,10 @@ int run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vector<ui
               const ctd_tuning &t);
 std::vector<uint64_t> split_batches(uint64_t n, int nb);
 int sigma_now(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *out);
+// CTD_OK when the case's folded batches, together with `next` more of
+// next_size histories (none when next_size = 0), differ in size by at most
+// one history; else CTD_EINVAL with a message.
+int check_batch_sizes(ctd_ctx *ctx, const ctd_case *cs, uint64_t next_size);
 int run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch, uint64_t count);
 // Run-to-sigma schedule shared by ctd_run_to_sigma and the server: batches to
 // add after `have` batches at sigma-bar `sig` (0 = stop).

@@ -985,7 +985,10 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t *__restrict__ mat,
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
     const unsigned int m = mat[i];
-    const float r = rho[i];
+    // -0.0 is stored as +0.0: the per-material maxima below (and the cell
+    // maxima of MACRO tracking) order densities by their float bits, which
+    // only match their values for sign-clear floats
+    const float r = rho[i] == 0.0f ? 0.0f : rho[i];
     const bool ok = (r >= 0.0f) && (r <= 3.4e38f);
     vox[i] = make_uint2(__float_as_uint(r), m);
     mymat = max(mymat, m);

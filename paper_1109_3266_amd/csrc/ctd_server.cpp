@@ -75,7 +75,7 @@ struct ctd_server {
   ctd_ctx *ctx = nullptr;
   ctd_server_config cfg{};
   std::thread th;
-  std::mutex mu;
+  mutable std::mutex mu;   // guards everything below, err included
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
   std::vector<Request *> active;
@@ -91,6 +91,7 @@ struct ctd_server {
   }
 };
 
+// Record the message of a failing call.  Lock held.
 static int sv_err(ctd_server *sv, int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -338,8 +339,14 @@ extern "C" int32_t ctd_server_start(int32_t device, const ctd_server_config *cfg
   return CTD_OK;
 }
 
+// The message is copied under the lock into a per-thread buffer, so the
+// pointer stays valid on the calling thread until its next call here.
 extern "C" const char *ctd_server_last_error(const ctd_server *sv) {
-  return sv ? sv->err.c_str() : "null server";
+  thread_local std::string copy;
+  if (!sv) return "null server";
+  std::lock_guard<std::mutex> lk(sv->mu);
+  copy = sv->err;
+  return copy.c_str();
 }
 
 extern "C" double ctd_server_now(const ctd_server *sv) { return sv ? sv->now() : 0.0; }
@@ -347,8 +354,10 @@ extern "C" double ctd_server_now(const ctd_server *sv) { return sv ? sv->now() :
 extern "C" int32_t ctd_server_add_phantom(ctd_server *sv, uint64_t key, const ctd_grid *g,
                                           const uint8_t *mat, const float *rho) {
   if (!sv || !g || !mat || !rho) return CTD_EINVAL;
-  if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || !(g->dx > 0 && g->dy > 0 && g->dz > 0))
+  if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || !(g->dx > 0 && g->dy > 0 && g->dz > 0)) {
+    std::lock_guard<std::mutex> lk(sv->mu);
     return sv_err(sv, CTD_EINVAL, "bad grid");
+  }
   const int64_t V = (int64_t)g->nx * g->ny * g->nz;
   PhantomEntry e;
   e.g = *g;
@@ -364,9 +373,9 @@ extern "C" int32_t ctd_server_submit(ctd_server *sv, uint64_t phantom_key, ctd_m
                                      ctd_spectrum *sp, ctd_geometry *geo, const ctd_params *p,
                                      double sigma_target, uint64_t *ticket) {
   if (!sv || !ms || !sp || !geo || !p || !ticket) return CTD_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
   if (!(sigma_target > 0.0)) return sv_err(sv, CTD_EINVAL, "sigma target must be positive");
   if (p->n_batches < 2) return sv_err(sv, CTD_EINVAL, "n_batches must be >= 2");
-  std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->stop) return sv_err(sv, CTD_EBUSY, "server is stopping");
   if (!sv->phantoms.count(phantom_key)) return sv_err(sv, CTD_ENOTFOUND, "unknown phantom key");
   auto r = std::make_unique<Request>();

@@ -69,25 +69,30 @@ int alloc_bins(uint64_t n, int nbins, const double *w, uint64_t *counts) {
     W += w[j];
   }
   if (!(W > 0.0)) return CTD_EINVAL;
-  std::vector<double> frac((size_t)nbins);
+  // bin j's share n w_j / W, recomputed by the same operations wherever it is
+  // needed (no scratch arrays: the static-table entry point allocates nothing)
+  auto share = [&](int j) { return ((double)n * w[j]) / W; };
   uint64_t used = 0;
   for (int j = 0; j < nbins; ++j) {
-    const double q = ((double)n * w[j]) / W;
-    const double fl = std::floor(q);
-    counts[j] = (uint64_t)fl;
-    frac[j] = q - fl;
+    counts[j] = (uint64_t)std::floor(share(j));
     used += counts[j];
   }
   if (used > n) return CTD_EINVAL;
   uint64_t rem = n - used;
   if (rem > (uint64_t)nbins) return CTD_EINVAL;
-  // the rem largest fractional parts get one more (ties: lower bin first)
-  std::vector<char> taken((size_t)nbins, 0);
+  // the rem largest fractional parts get one more (ties: lower bin first); a
+  // bin already given one has a count above the floor of its share
   for (uint64_t r = 0; r < rem; ++r) {
     int best = -1;
-    for (int j = 0; j < nbins; ++j)
-      if (!taken[j] && (best < 0 || frac[j] > frac[best])) best = j;
-    taken[best] = 1;
+    double best_f = 0.0;
+    for (int j = 0; j < nbins; ++j) {
+      const double q = share(j), fl = std::floor(q);
+      if (counts[j] != (uint64_t)fl) continue;
+      if (best < 0 || q - fl > best_f) {
+        best = j;
+        best_f = q - fl;
+      }
+    }
     counts[best] += 1;
   }
   return CTD_OK;

@@ -92,7 +92,8 @@ class ctd_stats(C.Structure):
                 ("n_deposits", C.c_uint64), ("n_escapes", C.c_uint64), ("n_refills", C.c_uint64),
                 ("transport_ms", C.c_double), ("fold_ms", C.c_double),
                 ("n_batches", C.c_uint32), ("tracking", C.c_int32),
-                ("n_histories", C.c_uint64), ("n_crossings", C.c_uint64)]
+                ("n_histories", C.c_uint64), ("n_crossings", C.c_uint64),
+                ("max_s1", C.c_uint64), ("max_s2_hi", C.c_uint64)]
 
 
 class ctd_tuning(C.Structure):

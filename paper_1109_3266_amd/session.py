@@ -133,8 +133,9 @@ class Case:
         self.ctx = ctx
         self.wl = wl
         self.V = int(wl.grid["nx"] * wl.grid["ny"] * wl.grid["nz"])
-        m = np.ascontiguousarray(wl.mat if mat is None else mat)
-        r = np.ascontiguousarray(wl.rho if rho is None else rho)
+        # device arrays (CTD_MEM_DEVICE: torch tensors or raw pointers) pass as they are
+        m = wl.mat if mat is None else mat
+        r = wl.rho if rho is None else rho
         if mem == L.CTD_MEM_HOST:
             m = np.ascontiguousarray(m, dtype=np.uint8)
             r = np.ascontiguousarray(r, dtype=np.float32)

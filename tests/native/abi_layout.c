@@ -17,7 +17,8 @@ int main(void) {
   F(ctd_params, tracking) F(ctd_params, macro_cell)
   S(ctd_balance) F(ctd_balance, q_incident_hi) F(ctd_balance, n_cutoff)
   S(ctd_stats) F(ctd_stats, n_steps) F(ctd_stats, transport_ms) F(ctd_stats, n_batches)
-  F(ctd_stats, n_histories) F(ctd_stats, n_crossings) F(ctd_stats, tracking)
+  F(ctd_stats, n_histories) F(ctd_stats, n_crossings) F(ctd_stats, tracking) F(ctd_stats, max_s1)
+  F(ctd_stats, max_s2_hi)
   S(ctd_tuning) F(ctd_tuning, tally_mode)
   S(ctd_event) F(ctd_event, vox) F(ctd_event, e) F(ctd_event, E)
   S(ctd_gamma_params) F(ctd_gamma_params, gamma_cap) F(ctd_gamma_params, substeps)

@@ -7,9 +7,11 @@ import time
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_1109_3266_amd import ctd as L
 from paper_1109_3266_amd.session import Case, Inputs, grid, params
 from synth import workloads as W
+from tests.test_gpu_parity import paired_compare
 
 pytestmark = pytest.mark.gpu
 
@@ -89,6 +91,11 @@ def test_server_results_identical_to_solo(ctx, tally_mode):
             assert info.sigma == pytest.approx(sig, rel=0, abs=0)
             assert np.array_equal(s1, r1) and np.array_equal(hi, rhi) and np.array_equal(lo, rlo)
             assert info.t_submit <= info.t_admit <= info.t_done
+            if i in (0, 2, 3):   # the global-majorant requests, against the oracle
+                r = O.run(O.OracleCase(wl), batches=[BATCH] * nb, threads=8)
+                b = {"s1": s1, "s2_hi": hi, "s2_lo": lo, "nb": nb,
+                     "bal": type("B", (), {"q_deposited": int(s1.sum())})}
+                paired_compare(b, r)
             L.ctd_server_release(sv, t)
         st = L.ctd_server_read_stats(sv)
         assert st.completed == 5 and st.rounds >= 10 and st.phantom_loads == 5
