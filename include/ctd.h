@@ -310,6 +310,23 @@ int32_t ctd_run(ctd_ctx *ctx, ctd_case *cs, uint64_t n_histories);
  * as ctd_run), continuing the case's history ids.  Async. */
 int32_t ctd_run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch_histories, uint64_t count);
 
+/* ctd_run_batches for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same batches with the same results bit for bit, but each round's launch
+ * table (its round descriptor, the spectrum's bin prefix sums and the chunk
+ * counter, 2816 B) lives in a static device array that each GPU holds until
+ * the process ends, written by a set-up kernel; the call enqueues only kernels
+ * (no allocation, copy, memset or event).  Limits: at most 256 spectrum bins,
+ * and the fixed-point bounds must admit the batches without the exact maxima
+ * read-back of ctd_run (else CTD_EOVERFLOW; ctd_run_batches then continues);
+ * Alg. A1 cases need a beamlet buffer already sized by a ctd_run_batches call
+ * with the same batch size (else CTD_EINVAL).  Every call on one GPU shares
+ * its array: calls that overlap on one GPU (work on two streams at once)
+ * race, calls in stream order do not.  Kernel times are not added to
+ * ctd_stats.transport_ms.  Async. */
+int32_t ctd_run_batches_static(ctd_ctx *ctx, ctd_case *cs, uint64_t batch_histories,
+                               uint64_t count);
+
 /* Add batches of batch_histories until sigma-bar (sigma_kind, threshold
  * dose_frac * D_max) <= target with >= n_batches batches, or max_histories
  * is reached: a pilot of n_batches batches, then the estimated remainder

@@ -95,6 +95,13 @@ extern "C" int32_t ctd_create(ctd_ctx **out, int32_t device) {
     ctx->xcd_tally_ok = mx < (unsigned)kTallyCopies;
   }
   dfree(probe);
+  // the static round table of ctd_run_batches_static: each device holds its
+  // own copy of the array, at the address this lookup returns (never the
+  // host-side name)
+  if (static_scratch_address(&ctx->static_table) != 0) {
+    (void)hipGetLastError();
+    ctx->static_table = nullptr;
+  }
   *out = ctx;
   return CTD_OK;
 }
@@ -1226,6 +1233,70 @@ extern "C" int32_t ctd_run_batches(ctd_ctx *ctx, ctd_case *cs, uint64_t batch_hi
   HIPCHK(ctx, hipSetDevice(ctx->device));
   if (batch_histories == 0 || count == 0) return CTD_OK;
   return run_batches(ctx, cs, batch_histories, count);
+}
+
+extern "C" int32_t ctd_run_batches_static(ctd_ctx *ctx, ctd_case *cs, uint64_t batch_histories,
+                                          uint64_t count) {
+  if (!ctx || !cs) return CTD_EINVAL;
+  NEED(ctx, ctx->static_table, "no static round table on device %d", ctx->device);
+  const int nb = (int)cs->sp->w.size();
+  NEED(ctx, nb <= kStaticMaxBins, "%d spectrum bins: the static round table holds at most %d",
+       nb, kStaticMaxBins);
+  const ctd_tuning &t = cs->tune;
+  NEED(ctx, t.tally_mode == 0 || cs->tally_copies >= kTallyCopies,
+       "tally mode %d without per-XCD tallies", t.tally_mode);
+  NEED(ctx, !cs->d_mh_state || cs->mh_cap >= batch_histories,
+       "Metropolis-Hastings beamlets for %llu histories; run ctd_run_batches once with batches "
+       "of %llu histories first", (unsigned long long)cs->mh_cap,
+       (unsigned long long)batch_histories);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (batch_histories == 0 || count == 0) return CTD_OK;
+  StaticRoundArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.cd = cs->d_desc;
+  a.beamlets = cs->d_mh_state ? cs->d_mh_beam : nullptr;
+  a.nbins = nb;
+  uint64_t cnt[kStaticMaxBins];
+  if (alloc_bins(batch_histories, nb, cs->sp->w.data(), cnt) != CTD_OK)
+    return set_err(ctx, CTD_EINVAL, "bin allocation failed");
+  for (int j = 0; j < nb; ++j) a.prefix[j + 1] = a.prefix[j] + cnt[j];
+  const LaunchCfg cfg = launch_cfg(ctx, t);
+  const uint64_t chunks = (batch_histories + (uint64_t)t.chunk - 1) / (uint64_t)t.chunk;
+  unsigned char *table = (unsigned char *)ctx->static_table;
+  const bool with_log = cs->log_cap > 0;
+  for (uint64_t b = 0; b < count; ++b) {
+    double s1 = 0.0, s2 = 0.0;
+    const int v = headroom_bounds((double)batch_histories, cs->e_max, cs->s1_bound,
+                                  cs->s2_bound, &s1, &s2);
+    if (v != kHeadroomOk)
+      return set_err(ctx, CTD_EOVERFLOW,
+                     v == kHeadroomBatch
+                         ? "a batch of %.3g histories exceeds 2^62 q"
+                         : "the fixed-point bounds after %.3g more histories need the exact "
+                           "maxima, which only ctd_run_batches reads back",
+                     (double)batch_histories);
+    a.h_begin = cs->h_next;
+    a.n = batch_histories;
+    if (a.beamlets &&
+        launch_mh_fill(cs->d_fl_f, (int)cs->geo->fl_f.size(), cs->geo->g.fluence_chains,
+                       a.h_begin, a.n, cs->desc.key0, cs->desc.key1, cs->d_mh_state,
+                       cs->d_mh_beam, ctx->stream) != 0)
+      return hip_err(ctx, hipGetLastError(), "Metropolis-Hastings fill launch");
+    if (launch_static_round_setup(table, a, ctx->stream) != 0 ||
+        launch_transport((const RoundCase *)table, 1, chunks,
+                         (unsigned long long *)(table + kStaticCounterOff), cfg, with_log,
+                         cs->mc_cs > 0, ctx->stream) != 0 ||
+        launch_fold(cs->d_tally, t.tally_mode ? kTallyCopies : 1, cs->d_s1, cs->d_s2,
+                    cs->ph->V, cs->d_acc, ctx->stream) != 0)
+      return hip_err(ctx, hipGetLastError(), "static round launch");
+    cs->s1_bound = s1;
+    cs->s2_bound = s2;
+    cs->h_next += batch_histories;
+    cs->batches += 1;
+    cs->batch_min = std::min(cs->batch_min, batch_histories);
+    cs->batch_max = std::max(cs->batch_max, batch_histories);
+  }
+  return CTD_OK;
 }
 
 extern "C" int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, double dose_frac,

@@ -43,6 +43,9 @@ struct ctd_ctx {
   double *sigma_host = nullptr;
   bool xcd_tally_ok = false;  // every XCC id < kTallyCopies
   unsigned int max_xcc = 0;
+  // device address of this device's static round table (ctd_run_batches_static),
+  // looked up at creation with the device current; null if the lookup failed
+  void *static_table = nullptr;
 };
 
 struct ctd_phantom {

@@ -115,6 +115,27 @@ struct RoundCase {
   const int32_t *beamlets;     // [n] Alg. A1 beamlet per history, or null
 };
 
+// Entry point that allocates nothing (ctd_run_batches_static): the launch
+// table of one single-case round -- the RoundCase, the spectrum's bin prefix
+// sums and the chunk counter -- lives in a file-scope device array of
+// kStaticScratchBytes, written by a one-block set-up kernel from its
+// arguments (no copy, no memset).  Byte offsets inside the array:
+constexpr int kStaticMaxBins = 256;
+constexpr size_t kStaticPrefixOff = 256;                          // after the RoundCase
+constexpr size_t kStaticCounterOff = 2560;                        // 256-aligned, past the prefix
+constexpr size_t kStaticScratchBytes = kStaticCounterOff + 256;   // 2816 B
+static_assert(kStaticPrefixOff + 8 * (kStaticMaxBins + 1) <= kStaticCounterOff,
+              "static round table layout");
+
+// The round a set-up kernel writes (passed by value: 2.1 KB of arguments).
+struct StaticRoundArgs {
+  const CaseDev *cd;
+  uint64_t h_begin, n;
+  const int32_t *beamlets;
+  int32_t nbins, pad;
+  unsigned long long prefix[kStaticMaxBins + 1];
+};
+
 struct LaunchCfg {
   int block;
   int grid;
@@ -143,6 +164,12 @@ int launch_xcc_probe(unsigned int *out, int blocks, void *stream);
 int launch_pack(const uint8_t *mat, const float *rho, uint2 *vox, int64_t V, unsigned int *stats,
                 void *stream);
 int launch_zero(void *ptr, size_t bytes, void *stream);
+// Device address of this device's static round table (hipGetSymbolAddress
+// with the device current); 0 on success.
+int static_scratch_address(void **out);
+// Write one round's table into the static array at `table` (its device
+// address) and clear its chunk counter; then the transport may run on it.
+int launch_static_round_setup(void *table, const StaticRoundArgs &args, void *stream);
 // sigma-bar over one case: out[0] = sigma, out[1] = voxel count, out[2] =
 // max dose (S1/rho); scratch holds 3 * nblocks doubles.
 int launch_sigma(const long long *s1, const unsigned long long *s2, const uint2 *vox, int64_t V,

@@ -1142,9 +1142,47 @@ __global__ void __launch_bounds__(256) k_mb_gather(const uint2 *__restrict__ v, 
   if (acc == 0x12345678u) out[0] = acc;  // keeps the loads live
 }
 
+// ------------------------------------------------ static round table
+
+// The launch table of ctd_run_batches_static.  Host code never passes this
+// name to a kernel (on the host it is only a stand-in for the symbol): the
+// device address comes from static_scratch_address(), once per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// One block writes the round's RoundCase, the bin prefix sums and a zero
+// chunk counter into the table (all later work on the stream reads them).
+__global__ void __launch_bounds__(256) k_static_round_setup(unsigned char *table,
+                                                            StaticRoundArgs a) {
+  unsigned long long *pre = (unsigned long long *)(table + kStaticPrefixOff);
+  for (int i = threadIdx.x; i <= a.nbins; i += blockDim.x) pre[i] = a.prefix[i];
+  unsigned long long *ctr = (unsigned long long *)(table + kStaticCounterOff);
+  if (threadIdx.x < 32) ctr[threadIdx.x] = 0ull;
+  if (threadIdx.x == 0) {
+    RoundCase *rc = (RoundCase *)table;
+    rc->cd = a.cd;
+    rc->prefix = pre;
+    rc->h_begin = a.h_begin;
+    rc->n = a.n;
+    rc->chunk_begin = 0;
+    rc->beamlets = a.beamlets;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
+
+int static_scratch_address(void **out) {
+  *out = nullptr;
+  return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)) == hipSuccess && *out ? 0 : -1;
+}
+
+int launch_static_round_setup(void *table, const StaticRoundArgs &args, void *stream) {
+  if (args.nbins < 1 || args.nbins > kStaticMaxBins) return -1;
+  hipLaunchKernelGGL(k_static_round_setup, dim3(1), dim3(256), 0, (hipStream_t)stream,
+                     (unsigned char *)table, args);
+  return check_launch();
+}
 
 int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,

@@ -160,6 +160,7 @@ _SIGS = {
     "ctd_autotune": (I32, [P, P, U64, C.POINTER(ctd_tuning)]),
     "ctd_run": (I32, [P, P, U64]),
     "ctd_run_batches": (I32, [P, P, U64, U64]),
+    "ctd_run_batches_static": (I32, [P, P, U64, U64]),
     "ctd_run_to_sigma": (I32, [P, P, F64, F64, I32, U64, U64, C.POINTER(F64)]),
     "ctd_run_many": (I32, [P, P, P, I32]),
     "ctd_sync": (I32, [P, P]),
@@ -341,6 +342,10 @@ def ctd_run(ctx, cs, n: int):
 
 def ctd_run_batches(ctx, cs, batch_histories: int, count: int):
     check(lib().ctd_run_batches(ctx, cs, int(batch_histories), int(count)), ctx)
+
+
+def ctd_run_batches_static(ctx, cs, batch_histories: int, count: int):
+    check(lib().ctd_run_batches_static(ctx, cs, batch_histories, count), ctx)
 
 
 def ctd_run_to_sigma(ctx, cs, target, dose_frac, kind, batch_histories, max_histories) -> float:
