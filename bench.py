@@ -1,17 +1,25 @@
 """Benchmark: photon histories/s of the transport hot path on one MI355X.
 
-Workload (default): the cone-beam water cylinder -- 128x128x100 voxels of
-0.25x0.25x0.2 cm, water cylinder r = 15 cm in air, point source at 100 cm,
-26x20 cm field at the isocentre, 360 projections over 360 deg, 120 kVp
-Kramers spectrum with 2 mm Al in 1 keV bins 20-119 keV, Rayleigh on, 1e9
-histories in 10 batches of 1e8.  One step = one batch: transport launch plus
-the batch fold.  Inputs are resident in device memory before timing.
+Workload (default, the largest single-GPU configuration): the synthetic head
+-- 256x256x160 voxels of 0.1 cm (10.5 M voxels, 8-byte records: the +-2 %
+density noise makes every voxel distinct), nested ellipsoids of soft tissue,
+cortical bone, brain, air sinuses and a lung-like insert in air; half-fan
+cone beam at SAD 100 cm, 200 projections over 360 deg, 100 kVp Kramers
+spectrum with 2 mm Al in 1 keV bins, Rayleigh on; Woodcock tracking against
+the paper's global majorant; batches of 1e8 histories.  One step = one batch:
+transport launch plus the batch fold.  Inputs are resident in device memory
+before timing.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu] [--quick]
 
-Prints one JSON line (rank 0).  Extra legs (time to 1 % sigma, batched
-engine vs per-case runs, serving, the model variants and the gamma tool) are
-included unless --quick.
+Prints one JSON line (rank 0).  Extra legs (the cone-beam water cylinder,
+time to 1 % sigma, batched engine vs per-case runs, serving, the model
+variants and the gamma tool) are included unless --quick.
+
+    python bench.py --summarize-counters [--workload W]
+
+turns the rocprofv3 counter runs listed in the counter summary's "commands"
+(written under gpurun_out/) into profiles/k_transport_<W>_pmc.json.
 """
 from __future__ import annotations
 
@@ -67,28 +75,121 @@ def kernel_source_hash() -> str:
     return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
-def load_counters(workload: str):
+# Launch configuration each workload's main leg times, as (block, waves per
+# SIMD, refill_min, chunk, tally mode, bound-grid block, collision deferral);
+# the committed counter summaries are taken with the same one.
+TUNING_KEYS = ("block", "waves_per_simd", "refill_min", "chunk", "tally_mode", "bound_block",
+               "defer_min")
+PINNED_TUNING = {
+    "head": (256, 5, 16, 1024, 0, 2, 16),
+    "head_helical": (256, 5, 16, 1024, 0, 2, 16),
+    "water_cbct": (256, 5, 16, 1024, 0, 2, 16),
+    "water_box_bowtie": (256, 5, 32, 1024, 1, 2, 16),
+    "tiny": (256, 4, 16, 1024, 2, 2, 16),
+}
+
+
+def counter_commands(workload: str) -> list:
+    """rocprofv3 runs behind profiles/k_transport_<workload>_pmc.json (one
+    counter group per run, repository root, output under gpurun_out/)."""
+    b = (f"python -u bench.py --quick --no-cpu --workload {workload} --steps 2 --warmup 0")
+    return [
+        f"rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_{workload}_fetch -o f -- {b}",
+        f"rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_{workload}_write -o w -- {b}",
+        f"rocprofv3 --pmc VALUBusy VALUUtilization SQ_INSTS_VALU SQ_INSTS_SALU -f csv "
+        f"-d gpurun_out/pmc_{workload}_valu -o v -- {b}",
+        "rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_copy_fetch -o cf -- "
+        "python -u bench.py --calibrate-copy",
+        "rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_copy_write -o cw -- "
+        "python -u bench.py --calibrate-copy",
+    ]
+
+
+def _pmc_rows(d: str):
+    """(kernel name, counter, value) of every dispatch in a rocprofv3 csv run."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(ROOT, d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]),
+                             r.get("Dispatch_Id", "")))
+    if not rows:
+        raise SystemExit(f"no counter rows under {d}")
+    return rows
+
+
+def summarize_counters(workload: str):
+    """Write profiles/k_transport_<workload>_pmc.json from the counter runs."""
+    import statistics
+    kern = "k_transport<false, false>"
+
+    def per_launch(d, name):
+        v = [x for k, n, x, _ in _pmc_rows(d) if kern in k and n == name]
+        return statistics.mean(v), len(v)
+
+    def copy_scale(d, name):
+        v = sorted((x for k, n, x, _ in _pmc_rows(d) if "copy" in k.lower() and n == name),
+                   reverse=True)[:3]
+        return float(1 << 20) / statistics.median(v)   # KiB counted per KiB moved
+
+    fetch, n1 = per_launch(f"gpurun_out/pmc_{workload}_fetch", "FETCH_SIZE")
+    write, n2 = per_launch(f"gpurun_out/pmc_{workload}_write", "WRITE_SIZE")
+    fs = copy_scale("gpurun_out/pmc_copy_fetch", "FETCH_SIZE")
+    ws = copy_scale("gpurun_out/pmc_copy_write", "WRITE_SIZE")
+    valu = {name: per_launch(f"gpurun_out/pmc_{workload}_valu", name)[0]
+            for name in ("VALUBusy", "VALUUtilization", "SQ_INSTS_VALU", "SQ_INSTS_SALU")}
+    t = PINNED_TUNING[workload]
+    out = dict(kernel="k_transport<false, false>", workload=workload,
+               kernel_sha=kernel_source_hash(),
+               kernel_sha_covers="ctd_kernels.hip up to the MACRO set-up kernel (transport "
+                                 "helpers, steps, k_transport)",
+               tuning=dict(zip(TUNING_KEYS, t)),
+               histories_per_launch=BATCH, launches=min(n1, n2),
+               fetch_kib_per_launch=fetch, write_kib_per_launch=write,
+               fetch_scale=fs, write_scale=ws,
+               hbm_bytes_per_launch=(fetch * fs + write * ws) * 1024.0,
+               valu=dict(valu_busy_pct=valu["VALUBusy"],
+                         valu_utilization_pct=valu["VALUUtilization"],
+                         sq_insts_valu_per_launch=valu["SQ_INSTS_VALU"],
+                         sq_insts_salu_per_launch=valu["SQ_INSTS_SALU"]),
+               commands=counter_commands(workload))
+    p = os.path.join(ROOT, "profiles", f"k_transport_{workload}_pmc.json")
+    with open(p, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def load_counters(workload: str, tuning=None):
     """The committed rocprofv3 counter summary of the transport kernel on
-    this workload, if it was taken on the current kernel source; else None."""
+    this workload, if it was taken on the current kernel source and with the
+    launch configuration being timed; else None."""
     p = os.path.join(ROOT, "profiles", f"k_transport_{workload}_pmc.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    return d if d.get("kernel_sha") == kernel_source_hash() else None
+    if d.get("kernel_sha") != kernel_source_hash():
+        return None
+    if tuning is not None and "tuning" in d:
+        if any(getattr(tuning, k) != d["tuning"][k] for k in TUNING_KEYS):
+            return None
+    return d
 
 
-def load_traffic(workload: str, launch_histories: int):
+def load_traffic(workload: str, launch_histories: int, tuning=None):
     """HBM bytes per transport launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
     from the committed counter summary, or None."""
-    d = load_counters(workload)
+    d = load_counters(workload, tuning)
     if d is None:
         return None
     return d["hbm_bytes_per_launch"] / d["histories_per_launch"] * launch_histories
 
 
-def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
-    """The FP64 CPU oracle on the host's cores; with n_hist None a 1e6-history
-    pilot sizes the sample to about target_s seconds."""
+def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0, n_batches: int = 10):
+    """The FP64 CPU oracle on the host's cores; with n_hist None a pilot sizes
+    the sample to about target_s seconds.  Large phantoms take few batches:
+    every batch costs the oracle a pass over its per-thread tallies."""
     from oracle import oracle as O
     try:
         cores = len(os.sched_getaffinity(0))
@@ -98,10 +199,10 @@ def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
     c = O.OracleCase(wl)
     adaptive = n_hist is None
     if adaptive:  # pilot; its per-batch merge makes it underestimate the rate
-        n_hist = 2_000_000
+        n_hist = 1_000_000
     for _ in range(3):
         t0 = time.perf_counter()
-        r = O.run(c, n_histories=n_hist, n_batches=10, threads=threads)
+        r = O.run(c, n_histories=n_hist, n_batches=n_batches, threads=threads)
         dt = time.perf_counter() - t0
         if not adaptive or dt >= 0.5 * target_s:
             break
@@ -109,7 +210,7 @@ def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
     # one thread on a small sample, for the per-core rate
     n1 = max(10, int(r["n_hist"] / dt / threads * 1.0) // 10 * 10)
     t0 = time.perf_counter()
-    O.run(O.OracleCase(wl), n_histories=n1, n_batches=10, threads=1)
+    O.run(O.OracleCase(wl), n_histories=n1, n_batches=n_batches, threads=1)
     rate1 = n1 / (time.perf_counter() - t0)
     model = ""
     try:
@@ -119,32 +220,27 @@ def cpu_baseline(wl, n_hist: int | None, target_s: float = 15.0):
     except OSError:
         pass
     return dict(value=r["n_hist"] / dt, unit="histories/s", cores=threads, kind="oracle",
-                sample=f"{n_hist:.0e} histories of the same workload, 10 batches, "
+                sample=f"{n_hist:.1e} histories of the same workload in {n_batches} batches, "
                        f"FP64 CPU oracle, {threads} threads, {dt:.1f} s",
                 single_thread_histories_per_s=rate1, host_cpus=os.cpu_count(),
                 cpu_model=model), r
 
 
-def other_oracle_rates(threads: int, ext: dict):
+def other_oracle_rates(threads: int):
     """Oracle histories/s on the 32^3 pencil-beam cube (1e5 histories in 10
-    batches, the whole case) and on 4e6 histories of the synthetic head in 2
-    batches (each batch costs the oracle passes over per-thread tallies of the
-    10.5 M voxels, seconds on 8 threads), with the head's time to 1 % sigma
-    extrapolated from the GPU run's history count."""
+    batches, the whole case) and on 2e7 histories of the cone-beam water
+    cylinder in 10 batches."""
     from oracle import oracle as O
     from synth import workloads as W
     out = {}
     for name, wl, n, nb in [("tiny_pencil_beam", W.tiny(n_histories=100_000), 100_000, 10),
-                            ("head", W.head(n_histories=4_000_000), 4_000_000, 2)]:
+                            ("water_cbct", W.water_cbct(n_histories=20_000_000), 20_000_000,
+                             10)]:
         c = O.OracleCase(wl)
         t0 = time.perf_counter()
         O.run(c, n_histories=n, n_batches=nb, threads=threads)
         dt = time.perf_counter() - t0
         out[name] = dict(histories=n, batches=nb, seconds=dt, histories_per_s=n / dt)
-    h = ext.get("head_time_to_1pct_sigma")
-    if h:
-        out["head"]["time_to_1pct_sigma_s_extrapolated"] = (
-            h["histories"] / out["head"]["histories_per_s"])
     return out
 
 
@@ -185,8 +281,9 @@ def batched_leg(ctx, L, W, Case, tuning, torch, hist_scale, tracking=None):
 
 
 def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
-    """Throughput of the variants beside the plain path (bound-electron
-    Compton, helical CT, fluence-map source), the paper's Table 1 water-box
+    """Throughput of the variants beside the plain path (macro-cell tracking,
+    bound-electron Compton, helical CT, fluence-map source; each autotuned),
+    the paper's Table 1 water-box
     case timed end to end as the paper times it (set-up and upload included),
     and the gamma-index kernel on a full head grid."""
     import numpy as np
@@ -210,8 +307,7 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
             dt = time.perf_counter() - t0
             st = L.ctd_read_stats(ctx, c.cs)
             return dict(histories_per_s=n / dt, steps_per_history=st.n_steps / n,
-                        tuning=dict(waves_per_simd=t.waves_per_simd, refill_min=t.refill_min,
-                                    chunk=t.chunk, tally_mode=t.tally_mode),
+                        tuning={k: getattr(t, k) for k in TUNING_KEYS},
                         deposits_per_history=st.n_deposits / n,
                         crossings_per_history=st.n_crossings / n,
                         sigma_paper=L.ctd_sigma(ctx, c.cs, L.CTD_SIGMA_PAPER, 0.2))
@@ -222,8 +318,7 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
     bow_mh = W.water_box_bowtie()
     bow_mh.geometry["fluence_chains"] = 1 << 18
     macro = dict(tracking=L.CTD_TRACK_MACRO)
-    for name, mk, kw in [("head", lambda: hw, {}),
-                         ("head_macro_tracking", lambda: hw, macro),
+    for name, mk, kw in [("head_macro_tracking", lambda: hw, macro),
                          ("head_bound_electron_compton", lambda: replace(hw, compton="wh"), {}),
                          ("head_helical", lambda: W.head_helical(), {}),
                          ("head_helical_macro_tracking", lambda: W.head_helical(), macro),
@@ -252,10 +347,9 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
             modes[f"tally_mode_{tm}"] = n_hist / (time.perf_counter() - t0)
     out["tiny_pencil_beam_histories_per_s"] = modes
 
-    # the head to 1 % sigma (local, D > 0.5 D_max), batches of 1e8, with the
-    # paper's global majorant and with macro-cell majorants
-    for name, kw, key in [("head_time_to_1pct_sigma", {}, "head"),
-                          ("head_time_to_1pct_sigma_macro_tracking", macro,
+    # the head to 1 % sigma (local, D > 0.5 D_max), batches of 1e8, with
+    # macro-cell majorants (the global majorant's is the main leg's)
+    for name, kw, key in [("head_time_to_1pct_sigma_macro_tracking", macro,
                            "head_macro_tracking")]:
         log(f"extensions: {name}")
         with Case(ctx, hw, **kw) as c:
@@ -405,7 +499,8 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
     makespan = max(x.t_done for x in infos) - min(x.t_submit for x in infos)
     service_rate = n_req / sum(service)
     log(f"serving: served p50 {np.percentile(lat, 50):.2f} s, {hist / makespan:.4g} hist/s")
-    return dict(requests=n_req, arrival_rate_hz=rate_hz, sigma_target=0.01,
+    return dict(requests=n_req, trace=f"first {n_req} of the 200 requests of the Poisson trace",
+                arrival_rate_hz=rate_hz, sigma_target=0.01,
                 batch_histories=batch, max_active=max_active,
                 p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                 histories_per_s=hist / makespan,
@@ -435,6 +530,133 @@ def calibrate_copy():
     print(json.dumps(dict(copy_bytes_read=n, copy_bytes_written=n, launches=3)))
 
 
+def transport_leg(ctx, L, W, Case, torch, stream, name: str, steps: int, warmup: int,
+                  tracking=None, tune=None, tally_mode=None):
+    """One case of workload `name`, timed over `steps` batches of BATCH
+    histories after `warmup` untimed ones, bracketed by synchronizations and
+    HIP events on the library's stream.  tune: None = the pinned launch
+    configuration (the one the committed counters were taken with), "auto" =
+    ctd_autotune.  Returns the leg's figures, including the roofline of its
+    transport kernel."""
+    log(f"building {name} workload")
+    wl = W.by_name(name)
+    tracking = L.CTD_TRACK_GLOBAL if tracking is None else tracking
+    case = Case(ctx, wl, tracking=tracking)
+    if tune == "auto":
+        tuning = L.ctd_autotune(ctx, case.cs, 20_000_000)
+    else:
+        tuning = L.ctd_tuning(*PINNED_TUNING[name])
+        if tally_mode is not None:
+            tuning.tally_mode = tally_mode
+        L.ctd_set_tuning(ctx, case.cs, tuning)
+    log(f"{name}: block={tuning.block} waves/simd={tuning.waves_per_simd} "
+        f"refill_min={tuning.refill_min} chunk={tuning.chunk} tally_mode={tuning.tally_mode} "
+        f"bound_block={tuning.bound_block} defer_min={tuning.defer_min}")
+    L.ctd_run_batches(ctx, case.cs, BATCH, warmup)
+    torch.cuda.synchronize()
+    st0 = L.ctd_read_stats(ctx, case.cs)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    L.ctd_run_batches(ctx, case.cs, BATCH, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    assert gpu_ms > 0.5 * wall * 1e3, "timing events do not bracket the library's work"
+    st1 = L.ctd_read_stats(ctx, case.cs)
+    bal = L.ctd_read_balance(ctx, case.cs)
+    assert bal.q_incident == bal.q_deposited + bal.q_escaped, "energy balance broken"
+    n_timed = steps * BATCH
+    value = n_timed / wall
+    log(f"{name}: {value:.4g} histories/s ({wall:.3f} s wall, {gpu_ms:.1f} ms events)")
+
+    # roofline of the dominant kernel (k_transport): one launch = one batch;
+    # launch time from the HIP events the library records around each
+    # transport launch on its stream
+    d_steps = st1.n_steps - st0.n_steps
+    d_scat = (st1.n_compton - st0.n_compton) + (st1.n_rayleigh - st0.n_rayleigh)
+    d_comp = st1.n_compton - st0.n_compton
+    d_dep = st1.n_deposits - st0.n_deposits
+    ops = (OPS_STEP * d_steps + OPS_SCATTER * d_scat + OPS_COMPTON * d_comp +
+           OPS_HISTORY * n_timed)
+    launch_ms = (st1.transport_ms - st0.transport_ms) / steps
+    launch_s = launch_ms * 1e-3
+    alu = ops / steps / launch_s
+    # algorithmic bytes: a 5 B voxel read (u8 material + f32 density) per
+    # Woodcock step and an 8 B tally update per deposit
+    alg_bytes = 5.0 * d_steps + 8.0 * d_dep
+    hbm = alg_bytes / steps / launch_s
+    atom_rate = d_dep / steps / launch_s
+    atom_peak, _ = L.ctd_microbench(ctx, 1, wl.n_voxels * 8, 1 << 28)
+    counters = load_counters(name, tuning) if tracking == L.CTD_TRACK_GLOBAL else None
+    traffic = (counters["hbm_bytes_per_launch"] / counters["histories_per_launch"] * BATCH
+               if counters else None)
+    valu = None
+    if counters is not None and "valu" in counters:
+        v = counters["valu"]
+        # issue-bound time: a wave64 VALU instruction occupies its SIMD 4 cycles
+        t_issue = v["sq_insts_valu_per_launch"] * 4 / (256 * 4 * 2.4e9)
+        valu = dict(busy_pct=v["valu_busy_pct"], utilization_pct=v["valu_utilization_pct"],
+                    insts_per_history=v["sq_insts_valu_per_launch"] / counters["histories_per_launch"],
+                    issue_bound_ms=t_issue * 1e3, frac=t_issue / launch_s,
+                    source=f"rocprofv3 VALUBusy, VALUUtilization, SQ_INSTS_VALU "
+                           f"(profiles/k_transport_{name}_pmc.json)")
+    fracs = dict(alu=alu / PEAK_LANE_OPS, hbm=hbm / 8e12, atomic=atom_rate / atom_peak)
+    bound = max(fracs, key=fracs.get)
+    unit = dict(alu="T lane-ops/s", hbm="GB/s", atomic="int64 atomics/s")[bound]
+    ach = dict(alu=alu / 1e12, hbm=hbm / 1e9, atomic=atom_rate)[bound]
+    peak = dict(alu=PEAK_LANE_OPS / 1e12, hbm=8000.0, atomic=atom_peak)[bound]
+    roof = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=fracs[bound],
+                traffic=traffic, kernel="k_transport", launch_ms=launch_ms,
+                note="bound = the largest of the ALU, HBM and atomic fractions below",
+                ops_per_history=ops / n_timed, steps_per_history=d_steps / n_timed,
+                deposits_per_history=d_dep / n_timed,
+                alu=dict(achieved=alu / 1e12, peak=PEAK_LANE_OPS / 1e12, unit="T lane-ops/s",
+                         frac=fracs["alu"],
+                         peak_source="256 CUs x 64 lanes x 2.4 GHz, non-packed FP32 / int32"),
+                hbm=dict(achieved=hbm / 1e9, peak=8000.0, unit="GB/s", frac=fracs["hbm"],
+                         bytes_per_history=alg_bytes / n_timed,
+                         counted_bytes_per_history=(traffic / BATCH if traffic else None)),
+                valu=valu,
+                atomic=dict(achieved=atom_rate, peak=atom_peak, unit="int64 atomics/s",
+                            frac=fracs["atomic"],
+                            peak_source="ctd_microbench random 64-bit atomics into a "
+                                        "tally-sized array, measured in this run",
+                            note="tally updates per second; with tally_mode 2 part of them "
+                                 "are LDS atomics" if tuning.tally_mode == 2 else ""))
+    out = dict(workload=WORKLOADS[name] + ("" if tracking == L.CTD_TRACK_GLOBAL
+                                           else "_macro_tracking"),
+               histories_per_s=value, wall_s=wall, ms_per_step=wall * 1e3 / steps,
+               voxels=wl.n_voxels,
+               tuning={k: getattr(tuning, k) for k in TUNING_KEYS},
+               roofline=roof,
+               transport_only_histories_per_s=n_timed / ((st1.transport_ms - st0.transport_ms)
+                                                         * 1e-3),
+               sigma_local=L.ctd_sigma(ctx, case.cs, L.CTD_SIGMA_LOCAL, 0.5),
+               sigma_paper=L.ctd_sigma(ctx, case.cs, L.CTD_SIGMA_PAPER, 0.2))
+    case.close()
+    return out, wl, tuning
+
+
+def time_to_sigma(ctx, L, Case, torch, wl, tuning, tracking=None):
+    """Wall time of ctd_run_to_sigma to 1 % sigma-bar (local, D > 0.5 D_max)
+    with batches of BATCH histories, from a fresh case."""
+    c = Case(ctx, wl, tracking=tracking)
+    L.ctd_set_tuning(ctx, c.cs, tuning)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sig = L.ctd_run_to_sigma(ctx, c.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, BATCH, 200_000_000_000)
+    tts = time.perf_counter() - t0
+    st = L.ctd_read_stats(ctx, c.cs)
+    out = dict(seconds=tts, sigma_local=sig, histories=st.n_histories, batches=st.n_batches,
+               sigma_paper=L.ctd_sigma(ctx, c.cs, L.CTD_SIGMA_PAPER, 0.2))
+    c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,22 +664,29 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="main leg only")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the main leg in the tuner's configuration instead of the pinned one")
     ap.add_argument("--cpu-histories", type=int, default=None)
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--workload", default="water_cbct", choices=sorted(WORKLOADS),
-                    help="workload of the main leg (profiling; the default is the benchmark)")
+    ap.add_argument("--summarize-counters", action="store_true")
+    ap.add_argument("--workload", default="head", choices=sorted(WORKLOADS),
+                    help="main-leg workload (default: the synthetic head)")
     ap.add_argument("--tracking", default="global", choices=["global", "macro"])
     ap.add_argument("--tally-mode", type=int, default=None, choices=[0, 1, 2],
-                    help="force the launch's tally mode (profiling the contention strategy)")
-    ap.add_argument("--legs", default="main,sigma,batched,serving,extensions",
-                    help="comma list of legs to run (--quick = main)")
+                    help="force the main leg's tally mode (profiling)")
+    ap.add_argument("--legs", default="main,water,sigma,batched,serving,extensions",
+                    help="comma-separated legs to run")
     args = ap.parse_args()
-    legs = {"main"} if args.quick else set(args.legs.split(","))
+    legs = set(args.legs.split(","))
+    if args.quick:
+        legs = {"main"}
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.summarize_counters:
+        summarize_counters(args.workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the transport runs on a single MI355X "
@@ -465,7 +694,6 @@ def main():
               "implemented).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1109_3266_amd import ctd as L
@@ -480,119 +708,39 @@ def main():
     torch.cuda.set_stream(stream)
     ctx = L.ctd_create(0)
     L.ctd_set_stream(ctx, stream.cuda_stream)
-    log(f"building {args.workload} workload")
-    wl = W.by_name(args.workload)
     tracking = L.CTD_TRACK_MACRO if args.tracking == "macro" else L.CTD_TRACK_GLOBAL
-    case = Case(ctx, wl, tracking=tracking)
-    tuning = L.ctd_get_tuning(ctx, case.cs)
-    if not args.no_tune:
-        tuning = L.ctd_autotune(ctx, case.cs, 20_000_000)
-    if args.tally_mode is not None:
-        tuning.tally_mode = args.tally_mode
-        L.ctd_set_tuning(ctx, case.cs, tuning)
-    log(f"tuning block={tuning.block} waves/simd={tuning.waves_per_simd} "
-        f"refill_min={tuning.refill_min} chunk={tuning.chunk} tally_mode={tuning.tally_mode}")
 
-    L.ctd_run_batches(ctx, case.cs, BATCH, args.warmup)
-    torch.cuda.synchronize()
-    st0 = L.ctd_read_stats(ctx, case.cs)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    L.ctd_run_batches(ctx, case.cs, BATCH, args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    assert gpu_ms > 0.5 * wall * 1e3, "timing events do not bracket the library's work"
-    st1 = L.ctd_read_stats(ctx, case.cs)
-    bal = L.ctd_read_balance(ctx, case.cs)
-    assert bal.q_incident == bal.q_deposited + bal.q_escaped, "energy balance broken"
-    n_timed = args.steps * BATCH
-    value = n_timed / wall
-    log(f"{value:.4g} histories/s ({wall:.3f} s wall, {gpu_ms:.1f} ms events)")
-
-    # roofline of the dominant kernel (k_transport): one launch = one batch
-    d_steps = st1.n_steps - st0.n_steps
-    d_scat = (st1.n_compton - st0.n_compton) + (st1.n_rayleigh - st0.n_rayleigh)
-    d_comp = st1.n_compton - st0.n_compton
-    ops = (OPS_STEP * d_steps + OPS_SCATTER * d_scat + OPS_COMPTON * d_comp +
-           OPS_HISTORY * n_timed)
-    launch_ms = (st1.transport_ms - st0.transport_ms) / args.steps
-    achieved = ops / args.steps / (launch_ms * 1e-3)
-    traffic = (load_traffic(args.workload, BATCH)
-               if tracking == L.CTD_TRACK_GLOBAL else None)
-    d_dep = st1.n_deposits - st0.n_deposits
-    # algorithmic bytes: 5 B voxel record per Woodcock step + 8 B per tally update
-    alg_bytes = 5.0 * d_steps + 8.0 * d_dep
-    atom_rate = d_dep / args.steps / (launch_ms * 1e-3)
-    atom_peak, _ = L.ctd_microbench(ctx, 1, wl.n_voxels * 8, 1 << 28)
-    counters = load_counters(args.workload) if tracking == L.CTD_TRACK_GLOBAL else None
-    valu = None
-    if counters is not None and "valu" in counters:
-        v = counters["valu"]
-        # issue-bound time: a wave64 VALU instruction occupies a SIMD 4 cycles
-        t_issue = v["sq_insts_valu_per_launch"] * 4 / (256 * 4 * 2.4e9)
-        valu = dict(busy_pct=v["valu_busy_pct"], utilization_pct=v["valu_utilization_pct"],
-                    insts_per_history=v["sq_insts_valu_per_launch"] / counters["histories_per_launch"],
-                    issue_bound_ms=t_issue * 1e3, frac=t_issue / (launch_ms * 1e-3),
-                    source="rocprofv3 VALUBusy, VALUUtilization, SQ_INSTS_VALU (profiles/)")
-    roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_LANE_OPS / 1e12,
-                unit="T lane-ops/s", frac=achieved / PEAK_LANE_OPS, traffic=traffic,
-                kernel="k_transport", launch_ms=launch_ms,
-                ops_per_history=ops / n_timed,
-                steps_per_history=d_steps / n_timed,
-                deposits_per_history=d_dep / n_timed,
-                hbm=dict(achieved=alg_bytes / args.steps / (launch_ms * 1e-3) / 1e9,
-                         peak=8000.0, unit="GB/s",
-                         frac=alg_bytes / args.steps / (launch_ms * 1e-3) / 8e12,
-                         bytes_per_history=alg_bytes / n_timed),
-                valu=valu,
-                atomic=dict(achieved=atom_rate, peak=atom_peak, unit="int64 atomics/s",
-                            frac=atom_rate / atom_peak,
-                            peak_source="ctd_microbench random 64-bit atomics into a "
-                                        "tally-sized array, measured in this run",
-                            note="tally updates per second; with tally_mode 2 part of "
-                                 "them are LDS atomics" if tuning.tally_mode == 2 else ""))
+    main_leg, wl, tuning = transport_leg(ctx, L, W, Case, torch, stream, args.workload,
+                                         args.steps, args.warmup, tracking,
+                                         "auto" if args.autotune else None, args.tally_mode)
+    value = main_leg["histories_per_s"]
     out = dict(metric=METRIC, value=value, unit="histories/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=wall * 1e3 / args.steps, higher_is_better=True,
+               warmup=args.warmup, ms_per_step=main_leg["ms_per_step"], higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload=WORKLOADS[args.workload] +
-                           ("" if tracking == L.CTD_TRACK_GLOBAL else "_macro_tracking"),
-                           histories_per_step=BATCH, histories_total=(args.steps + args.warmup)
-                           * BATCH, voxels=wl.n_voxels, tally="int64 fixed point 2^-24 keV",
-                           tuning=dict(block=tuning.block, waves_per_simd=tuning.waves_per_simd,
-                                       refill_min=tuning.refill_min, chunk=tuning.chunk,
-                                       tally_mode=tuning.tally_mode)),
-               roofline=roof,
-               transport_only_histories_per_s=n_timed / ((st1.transport_ms - st0.transport_ms)
-                                                         * 1e-3),
-               sigma_local=L.ctd_sigma(ctx, case.cs, L.CTD_SIGMA_LOCAL, 0.5),
-               sigma_paper=L.ctd_sigma(ctx, case.cs, L.CTD_SIGMA_PAPER, 0.2),
+               config=dict(workload=main_leg["workload"], histories_per_step=BATCH,
+                           histories_total=(args.steps + args.warmup) * BATCH,
+                           voxels=main_leg["voxels"], tally="int64 fixed point 2^-24 keV",
+                           tracking="Woodcock, global majorant" if tracking ==
+                           L.CTD_TRACK_GLOBAL else "Woodcock, macro-cell majorants",
+                           tuning=main_leg["tuning"]),
+               roofline=main_leg["roofline"],
+               transport_only_histories_per_s=main_leg["transport_only_histories_per_s"],
+               sigma_local=main_leg["sigma_local"], sigma_paper=main_leg["sigma_paper"],
                paper_context="gCTD: ~17 s at 0.4 % mean relative sigma (s/D_max over "
                              "D > 20 % D_max), Zubal HN, 2.5e8 histories, Tesla C2050 FP32")
-    case.close()
 
     if "sigma" in legs:
-        # time to 1 % sigma on the same workload, from a fresh case
         log("time to 1% sigma")
-        c2 = Case(ctx, wl, tracking=tracking)
-        L.ctd_set_tuning(ctx, c2.cs, tuning)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sig = L.ctd_run_to_sigma(ctx, c2.cs, 0.01, 0.5, L.CTD_SIGMA_LOCAL, BATCH,
-                                 200_000_000_000)
-        tts = time.perf_counter() - t0
-        s2 = L.ctd_read_stats(ctx, c2.cs)
-        out["time_to_1pct_sigma"] = dict(seconds=tts, sigma_local=sig,
-                                         histories=s2.n_histories, batches=s2.n_batches,
-                                         sigma_paper=L.ctd_sigma(ctx, c2.cs,
-                                                                 L.CTD_SIGMA_PAPER, 0.2))
-        c2.close()
-        log(f"time to 1% sigma {tts:.2f} s ({s2.n_histories:.3g} histories)")
+        out["time_to_1pct_sigma"] = time_to_sigma(ctx, L, Case, torch, wl, tuning, tracking)
+        log(f"time to 1% sigma {out['time_to_1pct_sigma']['seconds']:.2f} s")
+    if "water" in legs and args.workload != "water_cbct":
+        # the cone-beam water cylinder: 1-byte palette phantom, deposits spread
+        # over 1.6 M voxels, bound by the memory-side tally atomics
+        wleg, wwl, wtun = transport_leg(ctx, L, W, Case, torch, stream, "water_cbct",
+                                        args.steps, args.warmup)
+        if "sigma" in legs:
+            wleg["time_to_1pct_sigma"] = time_to_sigma(ctx, L, Case, torch, wwl, wtun)
+        out["water_cbct"] = wleg
     # the batched and serving legs with the paper's global majorant, then the
     # same cases with the library's automatic choice between global and
     # macro-cell majorants (both sides of each comparison use the same mode)
@@ -609,12 +757,12 @@ def main():
 
     if not args.no_cpu:
         log("cpu baseline")
-        cb, _ = cpu_baseline(wl, args.cpu_histories)
+        cb, _ = cpu_baseline(wl, args.cpu_histories,
+                             n_batches=2 if wl.n_voxels > 4_000_000 else 10)
         tts = out.get("time_to_1pct_sigma")
         if tts:   # the oracle would need the same histories to reach 1 % sigma
             cb["time_to_1pct_sigma_s_extrapolated"] = tts["histories"] / cb["value"]
-        # the oracle on the pencil-beam cube in full and on a sample of the head
-        cb["other_workloads"] = other_oracle_rates(cb["cores"], out.get("extensions", {}))
+        cb["other_workloads"] = other_oracle_rates(cb["cores"])
         out["cpu_baseline"] = cb
     L.ctd_destroy(ctx)
     print(json.dumps(out), flush=True)

@@ -204,6 +204,26 @@ typedef struct {
                             where the workgroup would exceed the LDS limit.
                             Tallies are integer sums: every mode gives the
                             same bits. */
+  int32_t bound_block;   /* Early rejection of fictitious collisions (GLOBAL
+                            tracking of phantoms stored as 8-byte records):
+                            0 off; 1, 2 or 4 = edge in voxels of the blocks
+                            of a 1-byte bound grid built at phantom load.  A
+                            block of one material carries a density level at
+                            or above all of its voxels'; a tentative
+                            collision whose xi reaches the Woodcock sum at
+                            that level is fictitious in every voxel of the
+                            block (float rounding is monotone), so it is
+                            decided without reading the voxel.  Decisions,
+                            and so results, are those of 0, bit for bit. */
+  int32_t defer_min;     /* With a bound grid: a tentative collision the
+                            bound cannot reject waits, and the wave resolves
+                            its waiting collisions together once this many
+                            lanes hold one (or every live lane does), so the
+                            voxel reads and interaction code run with more
+                            lanes active; photons that leave the box add
+                            their counters at the wave's next refill.  0:
+                            every collision at once (1..64).  Each history's
+                            steps are unchanged: same results bit for bit. */
 } ctd_tuning;
 
 /* Deposit/event record of the debug log (test use). type: 0 source, 1

@@ -183,6 +183,60 @@ static int build_palette(ctd_ctx *ctx, ctd_phantom *ph) {
   return CTD_OK;
 }
 
+// Bound grids of a record-layout phantom: for each material present, K
+// density levels spaced evenly over (rho_min, rho_max], rounded up to float,
+// the last exactly rho_max (K = 254 / materials present, at most 32); then
+// every block of 1, 2 and 4 voxels per edge is classified by its material
+// and the first level at or above its largest density (k_block_class).
+static int build_bound_grids(ctd_ctx *ctx, ctd_phantom *ph) {
+  int n_present = 0;
+  for (int m = 0; m < 256; ++m) n_present += ph->present[m] ? 1 : 0;
+  if (n_present == 0 || n_present > 254) return CTD_OK;  // no classes: no early rejection
+  const int K = std::min(32, 254 / n_present);
+  std::vector<uint2> cls(256, make_uint2(0u, 0u));
+  std::vector<int2> range(256, make_int2(0, 0));
+  int c = 0;
+  for (int m = 0; m < 256; ++m) {
+    if (!ph->present[m]) continue;
+    const double lo = ph->rho_min[m], hi = ph->rho_max[m];
+    const float top = (float)hi;  // rho_max came from float bits: exact
+    range[m] = make_int2(c, K);
+    for (int l = 0; l < K; ++l) {
+      float f = l == K - 1 ? top : std::min(round_up_to_float(lo + (hi - lo) * (l + 1) / K), top);
+      uint32_t bits;
+      std::memcpy(&bits, &f, 4);
+      cls[c++] = make_uint2(bits, (uint32_t)m);
+    }
+  }
+  const ctd_grid &g = ph->g;
+  HIPCHK(ctx, hipMalloc(&ph->bclass, sizeof(uint2) * 256));
+  HIPCHK(ctx, hipMalloc(&ph->bclass_range, sizeof(int2) * 256));
+  HIPCHK(ctx, hipMemcpy(ph->bclass, cls.data(), sizeof(uint2) * 256, hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemcpy(ph->bclass_range, range.data(), sizeof(int2) * 256,
+                        hipMemcpyHostToDevice));
+  for (int s = 0; s < 3; ++s) {
+    const int e = (1 << s) - 1;
+    const size_t nb = (size_t)((g.nx + e) >> s) * (size_t)((g.ny + e) >> s) *
+                      (size_t)((g.nz + e) >> s);
+    HIPCHK(ctx, hipMalloc(&ph->bgrid[s], nb));
+    if (launch_block_class(ph->vox, g.nx, g.ny, g.nz, s, ph->bclass, ph->bclass_range,
+                           ph->bgrid[s], ctx->stream) != 0)
+      return hip_err(ctx, hipGetLastError(), "bound grid kernel");
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  ph->nclass = c;
+  return CTD_OK;
+}
+
+static void free_phantom_buffers(ctd_phantom *ph) {
+  dfree(ph->vox);
+  dfree(ph->vox8);
+  dfree(ph->palette);
+  for (auto &b : ph->bgrid) dfree(b);
+  dfree(ph->bclass);
+  dfree(ph->bclass_range);
+}
+
 extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8_t *mat,
                                     const float *rho, int32_t mem, ctd_phantom **out) {
   if (!ctx || !out) return CTD_EINVAL;
@@ -210,15 +264,13 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
     dfree(dmat);
     dfree(drho);
     dfree(dstat);
-    dfree(ph->vox);
-    dfree(ph->vox8);
-    dfree(ph->palette);
+    free_phantom_buffers(ph);
     delete ph;
     return code;
   };
   hipError_t e = hipMalloc(&ph->vox, sizeof(uint2) * V);
   if (e != hipSuccess) return fail(hip_err(ctx, e, "phantom alloc"));
-  e = hipMalloc(&dstat, sizeof(unsigned int) * 514);
+  e = hipMalloc(&dstat, sizeof(unsigned int) * kPackStats);
   if (e != hipSuccess) return fail(hip_err(ctx, e, "phantom stats alloc"));
   const uint8_t *pm = mat;
   const float *pr = rho;
@@ -231,11 +283,11 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
     pm = dmat;
     pr = drho;
   }
-  if ((e = hipMemsetAsync(dstat, 0, sizeof(unsigned int) * 514, ctx->stream)) != hipSuccess)
+  if ((e = hipMemsetAsync(dstat, 0, sizeof(unsigned int) * kPackStats, ctx->stream)) != hipSuccess)
     return fail(hip_err(ctx, e, "phantom stats clear"));
   if (launch_pack(pm, pr, ph->vox, V, dstat, ctx->stream) != 0)
     return fail(hip_err(ctx, hipGetLastError(), "pack kernel"));
-  unsigned int hstat[514];
+  unsigned int hstat[kPackStats];
   if ((e = hipMemcpyAsync(hstat, dstat, sizeof hstat, hipMemcpyDeviceToHost, ctx->stream)) !=
           hipSuccess ||
       (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
@@ -249,6 +301,9 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
     float f;
     std::memcpy(&f, &hstat[m], 4);
     ph->rho_max[m] = (double)f;
+    const unsigned int mn = ~hstat[514 + m];
+    std::memcpy(&f, &mn, 4);
+    ph->rho_min[m] = hstat[256 + m] ? (double)f : 0.0;
     ph->present[m] = hstat[256 + m] != 0;
     ph->count[m] = hstat[256 + m];
   }
@@ -259,6 +314,7 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
   dfree(dstat);
   dstat = nullptr;
   if ((rc = build_palette(ctx, ph)) != CTD_OK) return fail(rc);
+  if (ph->npal == 0 && (rc = build_bound_grids(ctx, ph)) != CTD_OK) return fail(rc);
   *out = ph;
   return CTD_OK;
 }
@@ -268,9 +324,7 @@ extern "C" int32_t ctd_phantom_release(ctd_ctx *ctx, ctd_phantom *ph) {
   if (ph->refs > 0) return set_err(ctx, CTD_EBUSY, "phantom is used by %d case(s)", ph->refs.load());
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  dfree(ph->vox8);
-  dfree(ph->palette);
-  dfree(ph->vox);
+  free_phantom_buffers(ph);
   delete ph;
   return CTD_OK;
 }
@@ -685,6 +739,8 @@ void ctd::fill_desc(ctd_case *cs) {
   d.vox8 = cs->ph->vox8;
   d.palette = cs->ph->palette;
   d.npal = cs->ph->npal;
+  for (int s = 0; s < 3; ++s) d.bgrid[s] = cs->ph->bgrid[s];
+  d.bclass = cs->ph->nclass > 0 ? cs->ph->bclass : nullptr;
   const ctd_matset *ms = cs->ms;
   d.ne = ms->eg.ne;
   d.nzc = ms->nzc;
@@ -826,6 +882,8 @@ ctd_tuning ctd::default_tuning(const ctd_ctx *ctx) {
   t.refill_min = 16;
   t.chunk = 1024;
   t.tally_mode = 0;  // per-XCD copies measured no faster on MI355X; 8x the fold traffic
+  t.bound_block = 2;
+  t.defer_min = 16;
   (void)ctx;
   return t;
 }
@@ -834,7 +892,9 @@ static bool tuning_ok(const ctd_tuning &t) {
   return (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
          t.waves_per_simd >= 1 && t.waves_per_simd <= 8 && t.refill_min >= 1 &&
          t.refill_min <= 64 && t.chunk >= 64 && t.chunk <= 65536 &&
-         t.tally_mode >= 0 && t.tally_mode <= 2;
+         t.tally_mode >= 0 && t.tally_mode <= 2 &&
+         (t.bound_block == 0 || t.bound_block == 1 || t.bound_block == 2 || t.bound_block == 4) &&
+         t.defer_min >= 0 && t.defer_min <= 64;
 }
 
 int ctd::ensure_tally_copies(ctd_ctx *ctx, ctd_case *cs, int copies) {
@@ -918,6 +978,8 @@ static LaunchCfg launch_cfg(const ctd_ctx *ctx, const ctd_tuning &t) {
   cfg.refill_min = t.refill_min;
   cfg.chunk = t.chunk;
   cfg.tally_mode = t.tally_mode;
+  cfg.bound_shift = t.bound_block == 1 ? 0 : t.bound_block == 2 ? 1 : t.bound_block == 4 ? 2 : -1;
+  cfg.defer_min = t.defer_min;
   return cfg;
 }
 
@@ -1580,6 +1642,11 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
     release();
     return rc;
   }
+  // stage 1: launch shape and tally mode with the default bound grid; stage
+  // 2 (below): the bound grid's block size for the best of stage 1
+  const bool bounded = cs->ph->nclass > 0 && cs->mc_cs == 0;
+  const int bb0 = bounded ? default_tuning(ctx).bound_block : 0;
+  const int dm0 = default_tuning(ctx).defer_min;
   std::vector<ctd_tuning> cand;
   for (int tm = ctx->xcd_tally_ok ? 2 : 0; tm >= 0; --tm) {
     if (!transport_lds_fits(256, tm, ctx->device)) continue;
@@ -1592,16 +1659,38 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
           t.refill_min = rm;
           t.chunk = ch;
           t.tally_mode = tm;
+          t.bound_block = bb0;
+          t.defer_min = dm0;
           cand.push_back(t);
         }
   }
+  const size_t stage1 = cand.size();
   hipEvent_t a, b;
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
   double best_ms = INFINITY;
   ctd_tuning best_t = cs->tune;
   std::vector<ctd_case *> one{&tw};
-  for (size_t i = 0; i <= cand.size(); ++i) {
+  for (size_t i = 0;; ++i) {
+    // stage 2: the bound grid's block size, then the collision deferral, each
+    // varied around the best so far
+    if (i == stage1 + 1 && bounded) {
+      for (int bb : {0, 1, 2, 4}) {
+        if (bb == best_t.bound_block) continue;
+        ctd_tuning t = best_t;
+        t.bound_block = bb;
+        cand.push_back(t);
+      }
+    }
+    if (i == stage1 + 4 && bounded && best_t.bound_block > 0) {
+      for (int dm : {0, 8, 16, 32}) {
+        if (dm == best_t.defer_min) continue;
+        ctd_tuning t = best_t;
+        t.defer_min = dm;
+        cand.push_back(t);
+      }
+    }
+    if (i > cand.size()) break;
     const ctd_tuning t = i == 0 ? cand[0] : cand[i - 1];  // first run warms up
     (void)hipEventRecord(a, ctx->stream);
     rc = run_round(ctx, one, std::vector<uint64_t>{trial_histories}, t);

@@ -56,7 +56,15 @@ struct ctd_phantom {
   uint8_t *vox8 = nullptr;  // palette indices when npal > 0
   uint2 *palette = nullptr; // [256] distinct records when npal > 0
   int npal = 0;
+  // bound grids (8-byte record layout): block classes for blocks of 1, 2, 4
+  // voxels per edge, the class table [256] (density level bits, material)
+  // and each material's (first class, level count)
+  uint8_t *bgrid[3] = {nullptr, nullptr, nullptr};
+  uint2 *bclass = nullptr;
+  int2 *bclass_range = nullptr;
+  int nclass = 0;
   double rho_max[256] = {};
+  double rho_min[256] = {};
   bool present[256] = {};
   uint32_t count[256] = {};   // voxels of each material
   int max_mat = 0;

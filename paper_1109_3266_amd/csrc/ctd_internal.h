@@ -45,6 +45,8 @@ constexpr int kAccWords = 3 * ACC_COUNT + 4;
 constexpr float kQScale = 16777216.0f;  // 2^24: tally unit q = 2^-24 keV
 constexpr int kTallyCopies = 8;         // one batch tally per XCD of an MI355X
 constexpr int kMacroBands = 16;         // MACRO tracking: most energy bands
+constexpr int kPackStats = 770;         // words of k_pack's statistics
+constexpr uint32_t kMixedClass = 255;   // bound grid: a block of several materials
 constexpr uint32_t kStepGuard = 1000000u;
 constexpr float kInvMeC2 = (float)(1.0 / 510.99895);
 
@@ -92,6 +94,15 @@ struct CaseDev {
   float mc_fcs, mc_inv_cs;
   int32_t mc_shift, mc_ncell;
   const float *mc_f;
+  // Bound grid (8-byte record layout only): the class of every block of
+  // 2^s x 2^s x 2^s voxels, s = 0, 1, 2 (blocks per axis ceil(n / 2^s), x
+  // fastest; kMixedClass where the block holds more than one material), and
+  // the class table bclass[256] = (float bits of a density level, material):
+  // every voxel of a block of class c has material bclass[c].y and a density
+  // <= the level, so the Woodcock selection evaluated at the level bounds the
+  // voxel's own (float rounding is monotone).  Null where not built.
+  const uint8_t *bgrid[3];
+  const uint2 *bclass;
   // random stream key
   uint32_t key0, key1;
   // tallies
@@ -142,6 +153,8 @@ struct LaunchCfg {
   int refill_min;
   int chunk;
   int tally_mode;
+  int bound_shift;   // bound grid of 2^s-voxel blocks, or -1 (no early rejection)
+  int defer_min;     // with a bound grid: collision pass once this many wait (0: none)
 };
 
 // Kernel launchers (ctd_kernels.hip).  All enqueue on `stream`.
@@ -159,8 +172,9 @@ int launch_fold(unsigned long long *tally, int ncopies, long long *s1, unsigned 
                 int64_t V, unsigned long long *acc, void *stream);
 // Largest XCC id seen by `blocks` workgroups (written to *out, device).
 int launch_xcc_probe(unsigned int *out, int blocks, void *stream);
-// stats[514]: [0,256) max density bits per material, [256,512) voxel count
-// per material, [512] largest material id, [513] voxels with a bad density.
+// stats[kPackStats]: [0,256) max density bits per material, [256,512) voxel
+// count per material, [512] largest material id, [513] voxels with a bad
+// density, [514,770) complemented min density bits per material.
 int launch_pack(const uint8_t *mat, const float *rho, uint2 *vox, int64_t V, unsigned int *stats,
                 void *stream);
 int launch_zero(void *ptr, size_t bytes, void *stream);
@@ -186,6 +200,12 @@ int device_cu_count(int device);
 // material m over the voxels of each cell of cs^3 voxels (out zeroed).
 int launch_cell_max(const uint2 *vox, int nx, int ny, int nz, int cs, int ncx, int ncy, int M,
                     unsigned int *out, void *stream);
+// Bound grid of blocks of 2^shift voxels per edge: out[block] = the class
+// (index into cls) of the smallest density level of the block's material at
+// or above the block's largest density, or kMixedClass.  range[m] = (first
+// class of material m, level count), levels ascending within a material.
+int launch_block_class(const uint2 *vox, int nx, int ny, int nz, int shift, const uint2 *cls,
+                       const int2 *range, uint8_t *out, void *stream);
 int launch_mh_fill(const float *f, int n_f, int C, uint64_t h_begin, uint64_t n, uint32_t key0,
                    uint32_t key1, int32_t *state, int32_t *out, void *stream);
 // Gamma index of ev against ref on an nx*ny*nz grid (ctd_gamma.hip); offs is

@@ -49,6 +49,11 @@ constexpr int kCacheBits = 9;
 constexpr int kCacheSlots = 1 << kCacheBits;
 constexpr int kCacheBytesPerWave = kCacheSlots * (8 + 4);
 
+// a ^ b ^ c in one instruction (gfx950 three-input bitwise op, truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
   uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
@@ -56,8 +61,8 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
-    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    const uint32_t y0 = xor3((uint32_t)(p1 >> 32), x1, k0);
+    const uint32_t y2 = xor3((uint32_t)(p0 >> 32), x3, k1);
     x1 = (uint32_t)p1;
     x3 = (uint32_t)p0;
     x0 = y0;
@@ -106,22 +111,25 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
 
 // The fields the step loop reads, as one wave-uniform record.  It is filled
 // with readfirstlane on every case switch, so the compiler keeps it in scalar
-// registers; everything else about a case (source geometry, counters, log)
-// is read from the wave's LDS copy of the full descriptor.
+// registers; everything else about a case (source geometry, the angular
+// surfaces and cutoff used at real scatters, counters, log) is read from the
+// wave's LDS copy of the full descriptor.
 struct StepCase {
   const GLOBAL uint2 *vox;
   const GLOBAL uint8_t *vox8;
   const GLOBAL float4 *mu_rho;
   const GLOBAL float *mu_max;
-  const GLOBAL float4 *comp_quad;
-  const GLOBAL float4 *rayl_quad;
   GLOBAL unsigned long long *tally;
-  float fnx, fny, fnz, inv_dx, inv_dy, inv_dz, e0, inv_de, e_cut;
-  int32_t nx, ny, ne, nzc, nzr, rayleigh, comp_per_mat, npal;
+  float fnx, fny, fnz, inv_dx, inv_dy, inv_dz, e0, inv_de;
+  int32_t nx, ny, ne, rayleigh, npal;
   // tally mode 2: the wave's LDS sub-tally (slot keys = voxel or -1, values);
   // null in modes 0 and 1
   LOCAL int32_t *ckeys;
   LOCAL unsigned long long *cvals;
+  // bound grid of blocks of 2^bshift voxels per edge (ceil(n / 2^bshift)
+  // blocks per axis); null: every tentative collision reads its voxel
+  const GLOBAL uint8_t *bgrid;
+  int32_t bshift;
   uint32_t key0, key1;
 };
 
@@ -146,17 +154,23 @@ __device__ __forceinline__ int32_t uniform_i(int32_t x) {
 }
 
 // tally_mode 0: the case's tally; 1, 2: this XCD's copy of it; cache: the
-// wave's LDS sub-tally (mode 2) or null.
+// wave's LDS sub-tally (mode 2) or null; bound_shift: the bound grid used
+// (-1: none).
 __device__ __forceinline__ StepCase make_step_case(const CaseDev &c, int tally_mode,
+                                                   int bound_shift,
                                                    LOCAL unsigned char *cache) {
   StepCase s;
+  s.bgrid = nullptr;
+  s.bshift = 0;
+  if (bound_shift >= 0 && c.bclass) {
+    s.bgrid = uniform_ptr(c.bgrid[bound_shift]);
+    s.bshift = bound_shift;
+  }
   s.vox = uniform_ptr(c.vox);
   s.vox8 = uniform_ptr(c.vox8);
   s.npal = uniform_i(c.npal);
   s.mu_rho = uniform_ptr(c.mu_rho);
   s.mu_max = uniform_ptr(c.mu_max);
-  s.comp_quad = uniform_ptr(c.comp_quad);
-  s.rayl_quad = uniform_ptr(c.rayl_quad);
   s.tally = uniform_ptr(c.tally);
   if (tally_mode) s.tally += (size_t)xcc_id() * (size_t)uniform_i((int32_t)c.V);
   s.cvals = (LOCAL unsigned long long *)cache;
@@ -169,14 +183,10 @@ __device__ __forceinline__ StepCase make_step_case(const CaseDev &c, int tally_m
   s.inv_dz = uniform_f(c.inv_dz);
   s.e0 = uniform_f(c.e0);
   s.inv_de = uniform_f(c.inv_de);
-  s.e_cut = uniform_f(c.e_cut);
   s.nx = uniform_i(c.nx);
   s.ny = uniform_i(c.ny);
   s.ne = uniform_i(c.ne);
-  s.nzc = uniform_i(c.nzc);
-  s.nzr = uniform_i(c.nzr);
   s.rayleigh = uniform_i(c.rayleigh);
-  s.comp_per_mat = uniform_i(c.comp_per_mat);
   s.key0 = (uint32_t)uniform_i((int32_t)c.key0);
   s.key1 = (uint32_t)uniform_i((int32_t)c.key1);
   return s;
@@ -261,7 +271,12 @@ struct Photon {
   uint32_t cell;        // x | y << 10 | z << 20; all ones: take it from the position
 };
 
+// Photon.k: the Woodcock step count in the low bits, kScatBit once the photon
+// has scattered, kGoneBit while an escaped photon's counters wait for the
+// wave's next refill step (deferred collisions only).
 constexpr uint32_t kScatBit = 0x80000000u;
+constexpr uint32_t kGoneBit = 0x40000000u;
+constexpr uint32_t kStepMask = 0x3FFFFFFFu;
 
 __device__ __forceinline__ void set_energy(Photon &p, const StepCase &S, float E) {
   p.E = E;
@@ -307,7 +322,7 @@ __device__ __forceinline__ void log_event(const CaseDev &G, Photon &p, int type,
     ctd_event ev;
     ev.h = h;
     ev.seq = p.seq;
-    ev.k = p.k & ~kScatBit;
+    ev.k = p.k & kStepMask;
     ev.type = type;
     ev.reserved = 0;
     ev.vox = vox;
@@ -466,9 +481,64 @@ __device__ __forceinline__ bool escape(Photon &p, const CaseDev &G, Counters &c,
   return false;
 }
 
-// Tentative collision at voxel vox against majorant mumax (Sec. 2.1):
-// photoelectric, Compton, Rayleigh or fictitious from xi = u1 * mumax;
-// returns false when the photon is done.
+// Selection at a tentative collision (Sec. 2.1) in voxel vox of material m
+// and density rho, given the mass attenuation coefficients (a, b, cr) =
+// (photoelectric, Compton, Rayleigh) interpolated at E and xi = u1 * the
+// majorant: photoelectric, Compton, Rayleigh or fictitious by comparing xi
+// with the cumulative sums in that order; returns false when the photon is
+// done.
+template <bool LOG>
+__device__ __forceinline__ bool collide(Photon &p, const StepCase &S, const CaseDev &G,
+                                        Counters &c, const uint4 &r, uint32_t k, int32_t vox,
+                                        uint32_t m, float rho, float a, float b, float cr,
+                                        float xi) {
+  const float mpe = rho * a;
+  const float c1 = mpe + rho * b;
+  if (xi < mpe) {  // photoelectric: absorb, deposit E locally
+    c.add(ACC_N_STEPS, k);
+    c.add(ACC_N_PHOTO, 1);
+    deposit<LOG>(S, G, p, c, vox, p.E, 1, 0.0f);
+    return false;
+  }
+  if (xi < c1) {  // Compton (Sec. 2.2.3): angle from the C surface
+    c.add(ACC_N_COMPTON, 1);
+    p.k |= kScatBit;
+    // surface fields from the wave's LDS copy of the case (read only here)
+    const int nzc = G.nzc;
+    const GLOBAL float4 *Q = (const GLOBAL float4 *)G.comp_quad;
+    if (G.comp_per_mat) Q += (size_t)m * (size_t)(S.ne - 1) * (size_t)(nzc - 1);
+    const float mu = surface(Q, nzc, p.je, p.we, unif(r.z));
+    const float E = p.E;
+    const float Ep = E * __builtin_amdgcn_rcpf(fmaf(E * kInvMeC2, 1.0f - mu, 1.0f));
+    deposit<LOG>(S, G, p, c, vox, E - Ep, 2, Ep);  // exact: Ep > E/2 (Sterbenz)
+    rotate(p, mu, unif(r.w));
+    set_energy(p, S, Ep);
+    if (Ep < G.e_cut) {
+      c.add(ACC_N_STEPS, k);
+      c.add(ACC_N_CUTOFF, 1);
+      deposit<LOG>(S, G, p, c, vox, Ep, 4, 0.0f);
+      return false;
+    }
+    return true;
+  }
+  if (S.rayleigh) {
+    const float c2 = c1 + rho * cr;
+    if (xi < c2) {  // Rayleigh (Sec. 2.2.2): angle from the R surface, E unchanged
+      c.add(ACC_N_RAYLEIGH, 1);
+      p.k |= kScatBit;
+      const int nzr = G.nzr;
+      const GLOBAL float4 *Q =
+          (const GLOBAL float4 *)G.rayl_quad + (size_t)m * (size_t)(S.ne - 1) * (size_t)(nzr - 1);
+      const float mu = surface(Q, nzr, p.je, p.we, unif(r.z));
+      rotate(p, mu, unif(r.w));
+      log_event<LOG>(G, p, 3, vox, 0.0f, p.E);
+    }
+  }
+  return true;  // fictitious or scattered: keep going
+}
+
+// Tentative collision at voxel vox against majorant mumax: read the voxel
+// (1-byte palette index or 8-byte record), then select.
 template <bool LOG>
 __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const CaseDev &G,
                                          const LOCAL uint2 *pal, Counters &c, const uint4 &r,
@@ -483,49 +553,39 @@ __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const Cas
     rbits = rec.x;
     m = rec.y;
   }
-  const float rho = __uint_as_float(rbits);
-  const GLOBAL float4 *t = S.mu_rho + (size_t)m * (size_t)S.ne + (size_t)p.je;
+  const GLOBAL float4 *t = S.mu_rho + (__umul24(m, (uint32_t)S.ne) + (uint32_t)p.je);
   const float4 t0 = t[0], t1 = t[1];
-  const float mpe = rho * lerpf(t0.x, t1.x, p.we);
-  const float c1 = mpe + rho * lerpf(t0.y, t1.y, p.we);
-  const float xi = unif(r.y) * mumax;
-  if (xi < mpe) {  // photoelectric: absorb, deposit E locally
-    c.add(ACC_N_STEPS, k);
-    c.add(ACC_N_PHOTO, 1);
-    deposit<LOG>(S, G, p, c, vox, p.E, 1, 0.0f);
-    return false;
-  }
-  if (xi < c1) {  // Compton (Sec. 2.2.3): angle from the C surface
-    c.add(ACC_N_COMPTON, 1);
-    p.k |= kScatBit;
-    const GLOBAL float4 *Q = S.comp_quad;
-    if (S.comp_per_mat) Q += (size_t)m * (size_t)(S.ne - 1) * (size_t)(S.nzc - 1);
-    const float mu = surface(Q, S.nzc, p.je, p.we, unif(r.z));
-    const float E = p.E;
-    const float Ep = E * __builtin_amdgcn_rcpf(fmaf(E * kInvMeC2, 1.0f - mu, 1.0f));
-    deposit<LOG>(S, G, p, c, vox, E - Ep, 2, Ep);  // exact: Ep > E/2 (Sterbenz)
-    rotate(p, mu, unif(r.w));
-    set_energy(p, S, Ep);
-    if (Ep < S.e_cut) {
-      c.add(ACC_N_STEPS, k);
-      c.add(ACC_N_CUTOFF, 1);
-      deposit<LOG>(S, G, p, c, vox, Ep, 4, 0.0f);
-      return false;
-    }
-    return true;
-  }
-  if (S.rayleigh) {
-    const float c2 = c1 + rho * lerpf(t0.z, t1.z, p.we);
-    if (xi < c2) {  // Rayleigh (Sec. 2.2.2): angle from the R surface, E unchanged
-      c.add(ACC_N_RAYLEIGH, 1);
-      p.k |= kScatBit;
-      const GLOBAL float4 *Q = S.rayl_quad + (size_t)m * (size_t)(S.ne - 1) * (size_t)(S.nzr - 1);
-      const float mu = surface(Q, S.nzr, p.je, p.we, unif(r.z));
-      rotate(p, mu, unif(r.w));
-      log_event<LOG>(G, p, 3, vox, 0.0f, p.E);
-    }
-  }
-  return true;  // fictitious or scattered: keep going
+  const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
+  const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
+  return collide<LOG>(p, S, G, c, r, k, vox, m, __uint_as_float(rbits), a, b, cr,
+                      unif(r.y) * mumax);
+}
+
+// Tentative collision in a single-material block of the bound grid (class cls
+// in the wave's LDS class table: the block's material and a density level at
+// or above every voxel's).  The cumulative sum at the level, formed by the
+// same float operations as the selection, bounds the voxel's own sum (float
+// rounding is monotone), so xi at or above it is a fictitious collision
+// whatever the voxel holds, decided without reading the voxel; otherwise the
+// voxel's density is read and the selection is the one interact() makes.
+template <bool LOG>
+__device__ __forceinline__ bool interact_bounded(Photon &p, const StepCase &S, const CaseDev &G,
+                                                 const LOCAL uint2 *cls_tab, Counters &c,
+                                                 const uint4 &r, uint32_t k, int32_t vox,
+                                                 uint32_t cls) {
+  const uint2 ce = cls_tab[cls];
+  const uint32_t m = ce.y;
+  const float rho_c = __uint_as_float(ce.x);
+  const GLOBAL float4 *t = S.mu_rho + (__umul24(m, (uint32_t)S.ne) + (uint32_t)p.je);
+  const float4 t0 = t[0], t1 = t[1];
+  const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
+  const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
+  const float xi = unif(r.y) * p.mumax;
+  float bound = rho_c * a + rho_c * b;
+  if (S.rayleigh) bound = bound + rho_c * cr;
+  if (xi >= bound) return true;
+  const float rho = __uint_as_float(S.vox[vox].x);
+  return collide<LOG>(p, S, G, c, r, k, vox, m, rho, a, b, cr, xi);
 }
 
 // One Woodcock step (Sec. 2.1) against the global majorant; returns false
@@ -534,7 +594,7 @@ template <bool LOG>
 __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G,
                                      const LOCAL uint2 *pal, Counters &c) {
   p.k += 1;
-  const uint32_t k = p.k & ~kScatBit;
+  const uint32_t k = p.k & kStepMask;
   if (k > kStepGuard) {
     c.add(ACC_STEP_GUARD, 1);
     c.add(ACC_N_STEPS, k);
@@ -548,9 +608,74 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
   const bool inside = (p.px >= 0.0f) & (p.px < S.fnx) & (p.py >= 0.0f) & (p.py < S.fny) &
                       (p.pz >= 0.0f) & (p.pz < S.fnz);
   if (!inside) return escape<LOG>(p, G, c, k);
-  const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)p.pz, (uint32_t)S.ny) + (uint32_t)p.py,
-                                         (uint32_t)S.nx) + (int32_t)p.px;
+  const uint32_t ix = (uint32_t)p.px, iy = (uint32_t)p.py, iz = (uint32_t)p.pz;
+  const int32_t vox = (int32_t)__umul24(__umul24(iz, (uint32_t)S.ny) + iy, (uint32_t)S.nx) +
+                      (int32_t)ix;
+  if (S.bgrid) {
+    const uint32_t e = (1u << S.bshift) - 1u;   // wave-uniform: scalar ops
+    const uint32_t bgx = ((uint32_t)S.nx + e) >> S.bshift, bgy = ((uint32_t)S.ny + e) >> S.bshift;
+    const uint32_t blk = __umul24(__umul24(iz >> S.bshift, bgy) + (iy >> S.bshift), bgx) +
+                         (ix >> S.bshift);
+    const uint32_t cls = S.bgrid[blk];
+    if (cls != kMixedClass) return interact_bounded<LOG>(p, S, G, pal, c, r, k, vox, cls);
+  }
   return interact<LOG>(p, S, G, pal, c, r, k, vox, p.mumax);
+}
+
+// One Woodcock step with deferred collisions (bound grid present): the fast
+// part of step() -- free path, move, exit test and the bound-grid rejection
+// of fictitious collisions -- for every live lane of the wave, leaving the
+// rest to the wave's next collision pass.  Returns kStepOn (fictitious,
+// decided by the bound), kStepPending (a tentative collision at *pvox that
+// needs the voxel: the collision pass reads it and selects exactly as
+// interact() does, with the step's random block recomputed from its counter),
+// kStepGone (left the box: kGoneBit set, its counters added at the next
+// refill step) or kStepDone (stopped by the step guard).
+constexpr int kStepOn = 0, kStepPending = 1, kStepGone = 2, kStepDone = 3;
+
+template <bool LOG>
+__device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const CaseDev &G,
+                                         const LOCAL uint2 *cls_tab, Counters &c,
+                                         int32_t &pvox) {
+  p.k += 1;
+  const uint32_t k = p.k & kStepMask;
+  if (k > kStepGuard) {
+    c.add(ACC_STEP_GUARD, 1);
+    c.add(ACC_N_STEPS, k);
+    return kStepDone;
+  }
+  const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
+  const float s = -__log2f(unif(r.x)) * p.sc;  // -ln(u) / mu_max
+  p.px = fmaf(s, p.ux * S.inv_dx, p.px);
+  p.py = fmaf(s, p.uy * S.inv_dy, p.py);
+  p.pz = fmaf(s, p.uz * S.inv_dz, p.pz);
+  const bool inside = (p.px >= 0.0f) & (p.px < S.fnx) & (p.py >= 0.0f) & (p.py < S.fny) &
+                      (p.pz >= 0.0f) & (p.pz < S.fnz);
+  if (!inside) {
+    p.k |= kGoneBit;
+    return kStepGone;
+  }
+  const uint32_t ix = (uint32_t)p.px, iy = (uint32_t)p.py, iz = (uint32_t)p.pz;
+  const int32_t vox = (int32_t)__umul24(__umul24(iz, (uint32_t)S.ny) + iy, (uint32_t)S.nx) +
+                      (int32_t)ix;
+  const uint32_t e = (1u << S.bshift) - 1u;
+  const uint32_t bgx = ((uint32_t)S.nx + e) >> S.bshift, bgy = ((uint32_t)S.ny + e) >> S.bshift;
+  const uint32_t blk = __umul24(__umul24(iz >> S.bshift, bgy) + (iy >> S.bshift), bgx) +
+                       (ix >> S.bshift);
+  const uint32_t cls = S.bgrid[blk];
+  if (cls != kMixedClass) {
+    const uint2 ce = cls_tab[cls];
+    const float rho_c = __uint_as_float(ce.x);
+    const GLOBAL float4 *t = S.mu_rho + (__umul24(ce.y, (uint32_t)S.ne) + (uint32_t)p.je);
+    const float4 t0 = t[0], t1 = t[1];
+    const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
+    const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
+    float bound = rho_c * a + rho_c * b;
+    if (S.rayleigh) bound = bound + rho_c * cr;
+    if (unif(r.y) * p.mumax >= bound) return kStepOn;
+  }
+  pvox = vox;
+  return kStepPending;
 }
 
 // Woodcock tracking with the macro-cell majorant (MACRO tracking).  A flight
@@ -570,7 +695,7 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
                                            const LOCAL uint2 *pal, Counters &c) {
   if (p.tau < 0.0f) {  // a new flight
     p.k += 1;
-    const uint32_t k0 = p.k & ~kScatBit;
+    const uint32_t k0 = p.k & kStepMask;
     if (k0 > kStepGuard) {
       c.add(ACC_STEP_GUARD, 1);
       c.add(ACC_N_STEPS, k0);
@@ -583,7 +708,7 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
     p.rw = r.w;
     p.cell = 0xFFFFFFFFu;
   }
-  const uint32_t k = p.k & ~kScatBit;
+  const uint32_t k = p.k & kStepMask;
   float tau = p.tau;
   const int ncx = G.mc_nx, ncy = G.mc_ny, ncz = G.mc_nz;
   const float fcs = G.mc_fcs;
@@ -689,16 +814,19 @@ __device__ __forceinline__ int find_bin(const unsigned long long *__restrict__ p
 
 static_assert(sizeof(CaseDev) % 4 == 0 && sizeof(CaseDev) <= 512, "CaseDev copy size");
 
-// Copy a case descriptor (and its voxel palette, if any) into the wave's LDS
-// slots (lanes copy words).
+// Copy a case descriptor (and its voxel palette, or else its bound-grid class
+// table, if any) into the wave's LDS slots (lanes copy words).
 __device__ __forceinline__ void stage_case(CaseDev *dst, uint2 *pal, const CaseDev *src,
                                            int lane) {
   const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
   uint32_t *d = reinterpret_cast<uint32_t *>(dst);
   for (int i = lane; i < (int)(sizeof(CaseDev) / 4); i += 64) d[i] = s[i];
   const uint2 *sp = src->palette;
+  const uint2 *sc = src->bclass;
   if (__builtin_amdgcn_readfirstlane(src->npal) > 0)
     for (int i = lane; i < 256; i += 64) pal[i] = sp[i];
+  else if (sc)
+    for (int i = lane; i < 256; i += 64) pal[i] = sc[i];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -715,7 +843,8 @@ template <bool LOG, bool MACRO>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k_transport(const RoundCase *__restrict__ rcs, int nrc,
                                                    uint64_t total_chunks,
                                                    unsigned long long *chunk_ctr, int refill_min,
-                                                   int chunk, int tally_mode) {
+                                                   int chunk, int tally_mode, int bound_shift,
+                                                   int defer_min) {
   __shared__ unsigned long long wave_acc[8][ACC_COUNT];
   __shared__ CaseDev wave_case[8];
   __shared__ uint2 wave_pal[8][256];
@@ -744,7 +873,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
       tally_mode == 2 ? (LOCAL unsigned char *)cache_lds + w * kCacheBytesPerWave : nullptr;
   if (cache) clear_cache(cache, lane);
   Photon p;
+  p.k = 0;
   bool alive = false;
+  int32_t pvox = -1;   // deferred collisions: voxel of the lane's pending collision
   const uint32_t first_chunk =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (uint32_t)w);
 
@@ -752,6 +883,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
     const unsigned long long dead = __ballot(!alive);
     const int ndead = __popcll(dead);
     if (ndead == 64 || ndead >= refill_min) {
+      // counters of photons that left the box since the last refill step
+      if (!alive && (p.k & kGoneBit)) {
+        p.k &= ~kGoneBit;
+        escape<LOG>(p, G, cnt, p.k & kStepMask);
+      }
       // switch to the pending case once the wave has drained
       if (pend >= 0 && ndead == 64 && pool_next >= pool_end) {
         if (cur >= 0) {
@@ -762,7 +898,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
         cur = pend;
         pend = -1;
         stage_case(&G, pal, rcs[cur].cd, lane);
-        S = make_step_case(G, tally_mode, cache);
+        S = make_step_case(G, tally_mode, bound_shift, cache);
         pool_next = pend_lo;
         pool_end = pend_hi;
         wbin = find_bin(rcs[cur].prefix, G.nbins, pool_next);
@@ -793,7 +929,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
             refills = 0;
             cur = rc;
             stage_case(&G, pal, rcs[cur].cd, lane);
-            S = make_step_case(G, tally_mode, cache);
+            S = make_step_case(G, tally_mode, bound_shift, cache);
             wbin = find_bin(rcs[cur].prefix, G.nbins, lo);
           }
           pool_next = lo;
@@ -827,11 +963,26 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
       if (queue_done && pend < 0 && pool_next >= pool_end) break;
       continue;
     }
-    if (alive) {
-      if constexpr (MACRO)
-        alive = step_macro<LOG>(p, S, G, pal_lds, cnt);
-      else
-        alive = step<LOG>(p, S, G, pal_lds, cnt);
+    if constexpr (MACRO) {
+      if (alive) alive = step_macro<LOG>(p, S, G, pal_lds, cnt);
+    } else if (S.bgrid && defer_min > 0) {
+      // collision pass: the pending tentative collisions of the wave, once
+      // defer_min of them have gathered (or every live lane waits on one)
+      const unsigned long long pm = __ballot(alive && pvox >= 0);
+      if (pm && (__popcll(pm) >= defer_min || pm == __ballot(alive))) {
+        if (alive && pvox >= 0) {
+          const uint32_t k = p.k & kStepMask;
+          const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
+          alive = interact<LOG>(p, S, G, pal_lds, cnt, r, k, pvox, p.mumax);
+          pvox = -1;
+        }
+      }
+      if (alive && pvox < 0) {
+        const int st = step_fast<LOG>(p, S, G, pal_lds, cnt, pvox);
+        alive = st <= kStepPending;
+      }
+    } else if (alive) {
+      alive = step<LOG>(p, S, G, pal_lds, cnt);
     }
   }
   if (cur >= 0) {
@@ -854,6 +1005,47 @@ __global__ void __launch_bounds__(256) k_cell_max(const uint2 *__restrict__ vox,
     const int y = (int)(t % ny), z = (int)(t / ny);
     const int64_t cell = ((int64_t)(z / cs) * ncy + y / cs) * ncx + x / cs;
     atomicMax(out + cell * M + rec.y, rec.x);
+  }
+}
+
+// Bound grid: one lane per block of 2^shift voxels per edge.  A block whose
+// voxels share one material m gets the first of m's density levels (ascending
+// in cls[range[m].x ...]) that is at or above the block's largest density;
+// the last level is m's largest density over the phantom, so one exists.
+// Densities are >= 0 and sign-clear, so their bits order like their values.
+__global__ void __launch_bounds__(256) k_block_class(const uint2 *__restrict__ vox, int nx, int ny,
+                                                     int nz, int shift, int bx, int by,
+                                                     int64_t nblocks,
+                                                     const uint2 *__restrict__ cls,
+                                                     const int2 *__restrict__ range,
+                                                     uint8_t *__restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int B = 1 << shift;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += stride) {
+    const int x0 = (int)(b % bx) * B;
+    const int64_t t = b / bx;
+    const int y0 = (int)(t % by) * B, z0 = (int)(t / by) * B;
+    const int x1 = min(x0 + B, nx), y1 = min(y0 + B, ny), z1 = min(z0 + B, nz);
+    uint32_t m = vox[((int64_t)z0 * ny + y0) * nx + x0].y, rmax = 0u;
+    bool mixed = false;
+    for (int z = z0; z < z1; ++z)
+      for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x) {
+          const uint2 r = vox[((int64_t)z * ny + y) * nx + x];
+          mixed |= r.y != m;
+          rmax = max(rmax, r.x);
+        }
+    uint32_t c = kMixedClass;
+    if (!mixed) {
+      const int2 rg = range[m];
+      c = (uint32_t)(rg.x + rg.y - 1);
+      for (int l = 0; l < rg.y; ++l)
+        if (cls[rg.x + l].x >= rmax) {
+          c = (uint32_t)(rg.x + l);
+          break;
+        }
+    }
+    out[b] = (uint8_t)c;
   }
 }
 
@@ -968,32 +1160,39 @@ __global__ void k_xcc_probe(unsigned int *out) {
   if (threadIdx.x == 0) atomicMax(out, xcc_id());
 }
 
-// Pack (mat, rho) into 8-byte voxel records; per-material max density (as
-// float bits, valid for rho >= 0) and presence flag, max material id and a
-// count of bad densities.  stats: [0,256) rho max bits, [256,512) presence,
-// [512] max material id, [513] bad count.
+// Pack (mat, rho) into 8-byte voxel records; per-material max and min
+// density (as float bits, which order like the values for rho >= 0; the min
+// stored complemented so that all-zero memory is its neutral start), voxel
+// counts, max material id and a count of bad densities.  stats (kPackStats
+// words): [0,256) rho max bits, [256,512) voxel count, [512] max material id,
+// [513] bad count, [514,770) complemented rho min bits.
 __global__ void __launch_bounds__(256) k_pack(const uint8_t *__restrict__ mat,
                                               const float *__restrict__ rho,
                                               uint2 *__restrict__ vox, int64_t V,
                                               unsigned int *stats) {
-  __shared__ unsigned int lmax[256], lcnt[256];
+  __shared__ unsigned int lmax[256], lcnt[256], lmin[256];
   __shared__ unsigned int lmat, lbad;
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) { lmax[i] = 0u; lcnt[i] = 0u; }
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) { lmax[i] = 0u; lcnt[i] = 0u; lmin[i] = 0u; }
   if (threadIdx.x == 0) { lmat = 0u; lbad = 0u; }
   __syncthreads();
   unsigned int mymat = 0u, mybad = 0u;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
     const unsigned int m = mat[i];
-    // -0.0 is stored as +0.0: the per-material maxima below (and the cell
-    // maxima of MACRO tracking) order densities by their float bits, which
-    // only match their values for sign-clear floats
+    // -0.0 is stored as +0.0: the per-material extremes below (and the cell
+    // maxima of MACRO tracking and the bound classes) order densities by
+    // their float bits, which only match their values for sign-clear floats
     const float r = rho[i] == 0.0f ? 0.0f : rho[i];
     const bool ok = (r >= 0.0f) && (r <= 3.4e38f);
     vox[i] = make_uint2(__float_as_uint(r), m);
     mymat = max(mymat, m);
     atomicAdd(&lcnt[m], 1u);
-    if (ok) atomicMax(&lmax[m], __float_as_uint(r)); else mybad += 1u;
+    if (ok) {
+      atomicMax(&lmax[m], __float_as_uint(r));
+      atomicMax(&lmin[m], ~__float_as_uint(r));
+    } else {
+      mybad += 1u;
+    }
   }
   atomicMax(&lmat, mymat);
   if (mybad) atomicAdd(&lbad, mybad);
@@ -1001,6 +1200,7 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t *__restrict__ mat,
   for (int i = threadIdx.x; i < 256; i += blockDim.x) {
     if (lmax[i]) atomicMax(&stats[i], lmax[i]);
     if (lcnt[i]) atomicAdd(&stats[256 + i], lcnt[i]);
+    if (lmin[i]) atomicMax(&stats[514 + i], lmin[i]);
   }
   if (threadIdx.x == 0) {
     atomicMax(&stats[512], lmat);
@@ -1192,7 +1392,8 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                        : (macro ? k_transport<false, true> : k_transport<false, false>);
   const size_t lds = cfg.tally_mode == 2 ? (size_t)(cfg.block / 64) * kCacheBytesPerWave : 0;
   hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.block), lds, s, rc_dev, nrc, total_chunks,
-                     chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode);
+                     chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode, cfg.bound_shift,
+                     cfg.defer_min);
   return check_launch();
 }
 
@@ -1244,6 +1445,17 @@ int launch_cell_max(const uint2 *vox, int nx, int ny, int nz, int cs, int ncx, i
   if (V <= 0) return 0;
   hipLaunchKernelGGL(k_cell_max, dim3(grid_for(V, 256, 8192)), dim3(256), 0, (hipStream_t)stream,
                      vox, nx, ny, V, cs, ncx, ncy, M, out);
+  return check_launch();
+}
+
+int launch_block_class(const uint2 *vox, int nx, int ny, int nz, int shift, const uint2 *cls,
+                       const int2 *range, uint8_t *out, void *stream) {
+  const int e = (1 << shift) - 1;
+  const int bx = (nx + e) >> shift, by = (ny + e) >> shift, bz = (nz + e) >> shift;
+  const int64_t nb = (int64_t)bx * by * bz;
+  if (nb <= 0) return 0;
+  hipLaunchKernelGGL(k_block_class, dim3(grid_for(nb, 256, 8192)), dim3(256), 0,
+                     (hipStream_t)stream, vox, nx, ny, nz, shift, bx, by, nb, cls, range, out);
   return check_launch();
 }
 

@@ -175,7 +175,9 @@ static void admit(ctd_server *sv) {
     const int copies = sv->cfg.tuning.block && sv->cfg.tuning.tally_mode != 0 ? kTallyCopies : 1;
     const uint64_t case_bytes = case_footprint(e.g, r->geo, r->p, r->ms->eg.ne, copies,
                                                sv->cfg.batch_histories);
-    const uint64_t ph_bytes = e.dev ? 0 : (uint64_t)V * 9 + 4096;
+    // records, plus a palette index or the bound grids (1, 2, 4-voxel blocks)
+    const uint64_t ph_bytes =
+        e.dev ? 0 : (uint64_t)V * 9 + (uint64_t)V / 8 + (uint64_t)V / 64 + 8192;
     const uint64_t need = case_bytes + ph_bytes;
     if (need > sv->cfg.hbm_budget_bytes) {  // can never fit
       sv->queue.pop_front();

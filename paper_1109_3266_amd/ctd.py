@@ -98,7 +98,8 @@ class ctd_stats(C.Structure):
 
 class ctd_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("waves_per_simd", C.c_int32),
-                ("refill_min", C.c_int32), ("chunk", C.c_int32), ("tally_mode", C.c_int32)]
+                ("refill_min", C.c_int32), ("chunk", C.c_int32), ("tally_mode", C.c_int32),
+                ("bound_block", C.c_int32), ("defer_min", C.c_int32)]
 
 
 class ctd_gamma_params(C.Structure):

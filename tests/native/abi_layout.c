@@ -19,7 +19,7 @@ int main(void) {
   S(ctd_stats) F(ctd_stats, n_steps) F(ctd_stats, transport_ms) F(ctd_stats, n_batches)
   F(ctd_stats, n_histories) F(ctd_stats, n_crossings) F(ctd_stats, tracking) F(ctd_stats, max_s1)
   F(ctd_stats, max_s2_hi)
-  S(ctd_tuning) F(ctd_tuning, tally_mode)
+  S(ctd_tuning) F(ctd_tuning, tally_mode) F(ctd_tuning, bound_block) F(ctd_tuning, defer_min)
   S(ctd_event) F(ctd_event, vox) F(ctd_event, e) F(ctd_event, E)
   S(ctd_gamma_params) F(ctd_gamma_params, gamma_cap) F(ctd_gamma_params, substeps)
   S(ctd_server_config) F(ctd_server_config, dose_frac) F(ctd_server_config, tuning)

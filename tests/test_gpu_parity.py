@@ -584,3 +584,88 @@ def test_autotune_leaves_results_unchanged(ctx, variant):
             c.run(30_000)
             out.append(c.tally())
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][2], out[1][2])
+
+
+def _smooth_phantom(shape, n_mat, seed, noise=0.03, n_hist=100_000):
+    """Blocky regions of n_mat materials (one material per 3x3x3 cell, so
+    bound-grid blocks are mostly single-material and some straddle two),
+    densities with multiplicative noise; cone beam."""
+    wl = random_phantom(shape, n_mat, seed=seed, n_hist=n_hist)
+    rng = np.random.default_rng(seed + 1)
+    nz, ny, nx = shape
+    cells = rng.integers(0, n_mat, ((nz + 2) // 3, (ny + 2) // 3, (nx + 2) // 3))
+    mat = cells.repeat(3, 0).repeat(3, 1).repeat(3, 2)[:nz, :ny, :nx].astype(np.uint8)
+    from synth import physics as ph
+    dens = np.array([ph.MATERIALS[m][0] for m in wl.materials])
+    wl.mat = mat
+    wl.rho = (dens[mat] * (1.0 + noise * rng.standard_normal(shape))).clip(0).astype(np.float32)
+    return wl
+
+
+@pytest.mark.parametrize("name", ["head", "smooth6", "smooth3_ragged"])
+def test_bound_grid_block_sizes_bit_identical(ctx, name):
+    """Early rejection of fictitious collisions by the bound grid decides the
+    same collisions as reading every voxel, and deferring the remaining
+    collisions to a wave-wide pass changes no history: tallies, second
+    moments, step counts and the balance are identical with blocks of 1, 2
+    and 4 voxels, with collision passes at 1, 8, 16 and 64 waiting lanes and
+    without either (grid edges that do not divide the phantom included), and
+    the default run pairs with the oracle."""
+    if name == "head":
+        wl = W.head(scale=4, n_histories=300_000)
+    elif name == "smooth6":
+        wl = _smooth_phantom((20, 24, 28), 6, seed=41)
+    else:
+        wl = _smooth_phantom((13, 7, 11), 3, seed=42)     # odd sizes: partial blocks
+    say(f"bound grid block sizes on {name}")
+    outs = {}
+    for bb, dm in [(0, 0), (1, 0), (2, 0), (4, 0), (1, 16), (2, 1), (2, 8), (2, 64), (4, 16)]:
+        outs[bb, dm] = gpu_run(ctx, wl, tuning=L.ctd_tuning(256, 5, 16, 1024, 0, bb, dm))
+    ref = outs[0, 0]
+    for key, o in outs.items():
+        assert np.array_equal(o["s1"], ref["s1"]), key
+        assert np.array_equal(o["s2_hi"], ref["s2_hi"]) and np.array_equal(o["s2_lo"], ref["s2_lo"])
+        assert o["st"].n_steps == ref["st"].n_steps and o["st"].n_real == ref["st"].n_real
+        assert o["bal"].q_escaped == ref["bal"].q_escaped
+        assert o["bal"].n_unscattered == ref["bal"].n_unscattered
+    check_balance(outs[2, 8], wl.n_histories)
+    paired_compare(outs[2, 8], O.run(O.OracleCase(wl), threads=8))
+
+
+def test_bound_grid_fallbacks(ctx):
+    """The grid is skipped where it does not apply, with unchanged results: a
+    palette phantom (piecewise-constant densities), a phantom with more
+    materials than classes, and macro-cell tracking; a batched round mixing
+    record and palette phantoms equals the solo runs."""
+    say("bound grid fallbacks")
+    t2 = L.ctd_tuning(256, 5, 16, 1024, 0, 2)
+    t0 = L.ctd_tuning(256, 5, 16, 1024, 0, 0)
+    wc = W.water_cbct(scale=4, n_histories=100_000)          # palette layout
+    a, b = gpu_run(ctx, wc, tuning=t2), gpu_run(ctx, wc, tuning=t0)
+    assert np.array_equal(a["s1"], b["s1"]) and a["st"].n_steps == b["st"].n_steps
+    # 255 materials present: no class table, every collision reads its voxel
+    many = random_phantom((16, 16, 16), 2, seed=43, n_hist=50_000)
+    many.mat = (np.arange(many.mat.size) % 255).reshape(many.mat.shape).astype(np.uint8)
+    many.materials = [many.materials[i % 2] for i in range(255)]
+    many.rayleigh = False
+    a, b = gpu_run(ctx, many, tuning=t2), gpu_run(ctx, many, tuning=t0)
+    assert np.array_equal(a["s1"], b["s1"]) and a["st"].n_steps == b["st"].n_steps
+    # macro-cell tracking ignores the grid
+    hw = W.head(scale=8, n_histories=100_000)
+    a = gpu_run(ctx, hw, tuning=t2, tracking=L.CTD_TRACK_MACRO)
+    b = gpu_run(ctx, hw, tuning=t0, tracking=L.CTD_TRACK_MACRO)
+    assert np.array_equal(a["s1"], b["s1"])
+    # one round over a record phantom and a palette phantom
+    cases = [W.head(scale=8, n_histories=80_000), W.water_cbct(scale=8, n_histories=60_000)]
+    solo = [gpu_run(ctx, wl, tuning=t0) for wl in cases]
+    objs = [Case(ctx, wl) for wl in cases]
+    try:
+        for o in objs:
+            L.ctd_set_tuning(ctx, o.cs, t2)
+        L.ctd_run_many(ctx, [o.cs for o in objs], [wl.n_histories for wl in cases])
+        for o, s in zip(objs, solo):
+            s1, hi, lo, nb = o.tally()
+            assert np.array_equal(s1, s["s1"]) and np.array_equal(hi, s["s2_hi"])
+    finally:
+        for o in objs:
+            o.close()
