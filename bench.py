@@ -123,11 +123,14 @@ def _pmc_rows(d: str):
 def summarize_counters(workload: str):
     """Write profiles/k_transport_<workload>_pmc.json from the counter runs."""
     import statistics
-    kern = "k_transport<false, false>"
+    kern = "k_transport<false, false,"     # the unlogged global-majorant instances
 
     def per_launch(d, name):
         v = [x for k, n, x, _ in _pmc_rows(d) if kern in k and n == name]
         return statistics.mean(v), len(v)
+
+    names = sorted({k.split("(")[0].replace("void ctd::", "")
+                    for k, n, x, _ in _pmc_rows(f"gpurun_out/pmc_{workload}_fetch") if kern in k})
 
     def copy_scale(d, name):
         v = sorted((x for k, n, x, _ in _pmc_rows(d) if "copy" in k.lower() and n == name),
@@ -141,7 +144,7 @@ def summarize_counters(workload: str):
     valu = {name: per_launch(f"gpurun_out/pmc_{workload}_valu", name)[0]
             for name in ("VALUBusy", "VALUUtilization", "SQ_INSTS_VALU", "SQ_INSTS_SALU")}
     t = PINNED_TUNING[workload]
-    out = dict(kernel="k_transport<false, false>", workload=workload,
+    out = dict(kernel=", ".join(names), workload=workload,
                kernel_sha=kernel_source_hash(),
                kernel_sha_covers="ctd_kernels.hip up to the MACRO set-up kernel (transport "
                                  "helpers, steps, k_transport)",
@@ -597,11 +600,8 @@ def transport_leg(ctx, L, W, Case, torch, stream, name: str, steps: int, warmup:
     valu = None
     if counters is not None and "valu" in counters:
         v = counters["valu"]
-        # issue-bound time: a wave64 VALU instruction occupies its SIMD 4 cycles
-        t_issue = v["sq_insts_valu_per_launch"] * 4 / (256 * 4 * 2.4e9)
         valu = dict(busy_pct=v["valu_busy_pct"], utilization_pct=v["valu_utilization_pct"],
                     insts_per_history=v["sq_insts_valu_per_launch"] / counters["histories_per_launch"],
-                    issue_bound_ms=t_issue * 1e3, frac=t_issue / launch_s,
                     source=f"rocprofv3 VALUBusy, VALUUtilization, SQ_INSTS_VALU "
                            f"(profiles/k_transport_{name}_pmc.json)")
     fracs = dict(alu=alu / PEAK_LANE_OPS, hbm=hbm / 8e12, atomic=atom_rate / atom_peak)

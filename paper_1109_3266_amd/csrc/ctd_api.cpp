@@ -78,6 +78,14 @@ extern "C" int32_t ctd_create(ctd_ctx **out, int32_t device) {
   ctx->stream = ctx->own;
   ctx->n_cu = device_cu_count(device);
   if (ctx->n_cu <= 0) ctx->n_cu = 256;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) ==
+          hipSuccess && v > 0)
+    ctx->lds_per_cu = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+          hipSuccess && v > 0)
+    ctx->lds_per_block = v;
+  (void)hipGetLastError();
   ctx->slots.resize(64);
   if (hipMalloc(&ctx->sigma_scratch, sizeof(double) * (3 * kSigmaBlocks + 4)) != hipSuccess ||
       hipHostMalloc(&ctx->sigma_host, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
@@ -980,6 +988,11 @@ static LaunchCfg launch_cfg(const ctd_ctx *ctx, const ctd_tuning &t) {
   cfg.tally_mode = t.tally_mode;
   cfg.bound_shift = t.bound_block == 1 ? 0 : t.bound_block == 2 ? 1 : t.bound_block == 4 ? 2 : -1;
   cfg.defer_min = t.defer_min;
+  cfg.tab_n = 0;
+  cfg.tab_ne = 0;
+  // LDS per workgroup that keeps 4 x waves_per_simd waves resident per CU
+  const int wgs_per_cu = std::max(1, 4 * t.waves_per_simd / (t.block / 64));
+  cfg.lds_budget = (size_t)std::min(ctx->lds_per_block, ctx->lds_per_cu / wgs_per_cu);
   return cfg;
 }
 
@@ -1029,7 +1042,11 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
   }
   std::memset(h + ctr_off, 0, 256);
   HIPCHK(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
-  const LaunchCfg cfg = launch_cfg(ctx, t);
+  LaunchCfg cfg = launch_cfg(ctx, t);
+  if (nrc == 1) {   // a single case's tables may be staged in LDS
+    cfg.tab_n = items[0].tab_n;
+    cfg.tab_ne = items[0].tab_ne;
+  }
   if (chunks > 0 &&
       launch_transport((const RoundCase *)d, nrc, chunks, (unsigned long long *)(d + ctr_off),
                        cfg, with_log, macro, ctx->stream) != 0)
@@ -1107,6 +1124,8 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     it.h_begin = cases[i]->h_next;
     it.n = n[i];
     it.macro = cases[i]->mc_cs > 0;
+    it.tab_n = cases[i]->ms->M * cases[i]->ms->eg.ne;
+    it.tab_ne = cases[i]->ms->eg.ne;
     if (cases[i]->d_mh_state) {
       rc0 = ensure_mh_buffer(ctx, cases[i], n[i]);
       if (rc0 != CTD_OK) return rc0;
@@ -1322,7 +1341,9 @@ extern "C" int32_t ctd_run_batches_static(ctd_ctx *ctx, ctd_case *cs, uint64_t b
   if (alloc_bins(batch_histories, nb, cs->sp->w.data(), cnt) != CTD_OK)
     return set_err(ctx, CTD_EINVAL, "bin allocation failed");
   for (int j = 0; j < nb; ++j) a.prefix[j + 1] = a.prefix[j] + cnt[j];
-  const LaunchCfg cfg = launch_cfg(ctx, t);
+  LaunchCfg cfg = launch_cfg(ctx, t);
+  cfg.tab_n = cs->ms->M * cs->ms->eg.ne;
+  cfg.tab_ne = cs->ms->eg.ne;
   const uint64_t chunks = (batch_histories + (uint64_t)t.chunk - 1) / (uint64_t)t.chunk;
   unsigned char *table = (unsigned char *)ctx->static_table;
   const bool with_log = cs->log_cap > 0;

@@ -21,6 +21,7 @@ struct RoundItem {
   std::vector<unsigned long long> prefix;
   const int32_t *beamlets = nullptr;   // Alg. A1 beamlets of the round, or null
   bool macro = false;                  // MACRO tracking case
+  int tab_n = 0, tab_ne = 0;           // the case's mu/rho rows and energy nodes
 };
 
 }  // namespace ctd
@@ -43,6 +44,7 @@ struct ctd_ctx {
   double *sigma_host = nullptr;
   bool xcd_tally_ok = false;  // every XCC id < kTallyCopies
   unsigned int max_xcc = 0;
+  int lds_per_cu = 160 * 1024, lds_per_block = 64 * 1024;  // device LDS limits
   // device address of this device's static round table (ctd_run_batches_static),
   // looked up at creation with the device current; null if the lookup failed
   void *static_table = nullptr;

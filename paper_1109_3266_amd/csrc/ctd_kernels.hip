@@ -49,6 +49,16 @@ constexpr int kCacheBits = 9;
 constexpr int kCacheSlots = 1 << kCacheBits;
 constexpr int kCacheBytesPerWave = kCacheSlots * (8 + 4);
 
+// Dynamic LDS of a transport workgroup, in this order: one slot of
+// kWaveLdsBytes per wave (its event counters, its copy of the case
+// descriptor, its 256-entry palette or bound-class table); in tally mode 2,
+// each wave's sub-tally; in a single-case launch whose tables fit, the
+// case's majorant nodes (padded to 16 B) and mu/rho rows, shared by the
+// workgroup.
+constexpr int kWaveAccBytes = (ACC_COUNT * 8 + 15) & ~15;
+constexpr int kWaveCaseBytes = ((int)sizeof(CaseDev) + 15) & ~15;
+constexpr int kWaveLdsBytes = kWaveAccBytes + kWaveCaseBytes + 256 * 8;
+
 // a ^ b ^ c in one instruction (gfx950 three-input bitwise op, truth table 0x96)
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -119,6 +129,10 @@ struct StepCase {
   const GLOBAL uint8_t *vox8;
   const GLOBAL float4 *mu_rho;
   const GLOBAL float *mu_max;
+  // the workgroup's LDS copies of mu_rho and mu_max, or null (read mu_rho,
+  // mu_max through the caches)
+  const LOCAL float4 *tab;
+  const LOCAL float *tabmax;
   GLOBAL unsigned long long *tally;
   float fnx, fny, fnz, inv_dx, inv_dy, inv_dz, e0, inv_de;
   int32_t nx, ny, ne, rayleigh, npal;
@@ -170,6 +184,8 @@ __device__ __forceinline__ StepCase make_step_case(const CaseDev &c, int tally_m
   s.vox8 = uniform_ptr(c.vox8);
   s.npal = uniform_i(c.npal);
   s.mu_rho = uniform_ptr(c.mu_rho);
+  s.tab = nullptr;
+  s.tabmax = nullptr;
   s.mu_max = uniform_ptr(c.mu_max);
   s.tally = uniform_ptr(c.tally);
   if (tally_mode) s.tally += (size_t)xcc_id() * (size_t)uniform_i((int32_t)c.V);
@@ -278,13 +294,30 @@ constexpr uint32_t kScatBit = 0x80000000u;
 constexpr uint32_t kGoneBit = 0x40000000u;
 constexpr uint32_t kStepMask = 0x3FFFFFFFu;
 
+// mu/rho rows ti and ti + 1 (energy nodes je, je + 1 of one material): from
+// the workgroup's LDS copy (TAB) or through the caches.
+template <bool TAB>
+__device__ __forceinline__ void table_rows(const StepCase &S, uint32_t ti, float4 &t0, float4 &t1) {
+  if constexpr (TAB) {
+    t0 = S.tab[ti];
+    t1 = S.tab[ti + 1];
+  } else {
+    t0 = S.mu_rho[ti];
+    t1 = S.mu_rho[ti + 1];
+  }
+}
+
+template <bool TAB>
 __device__ __forceinline__ void set_energy(Photon &p, const StepCase &S, float E) {
   p.E = E;
   const float f = (E - S.e0) * S.inv_de;
   const int j = min(max((int)f, 0), S.ne - 2);
   p.je = j;
   p.we = f - (float)j;
-  p.mumax = lerpf(S.mu_max[j], S.mu_max[j + 1], p.we);
+  if constexpr (TAB)
+    p.mumax = lerpf(S.tabmax[j], S.tabmax[j + 1], p.we);
+  else
+    p.mumax = lerpf(S.mu_max[j], S.mu_max[j + 1], p.we);
   p.sc = 0.69314718055994531f * __builtin_amdgcn_rcpf(p.mumax);
 }
 
@@ -368,7 +401,7 @@ __device__ __forceinline__ void deposit(const StepCase &S, const CaseDev &G, Pho
 
 // Source photon of history h from spectrum bin j (Sec. 2.2.5-2.2.6); returns
 // false when the ray misses the voxel box (the photon escapes at once).
-template <bool LOG>
+template <bool LOG, bool TAB>
 __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t h, int j,
                        const int32_t *__restrict__ mh_beam, uint64_t local, Counters &c) {
   p.hlo = (uint32_t)h;
@@ -466,7 +499,7 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
   p.py = fminf(fmaxf(fmaf(tin, D[1], Sv[1]), 0.0f), __int_as_float(__float_as_int(N[1]) - 1));
   p.pz = fminf(fmaxf(fmaf(tin, D[2], Sv[2]), 0.0f), __int_as_float(__float_as_int(N[2]) - 1));
   p.ux = dx; p.uy = dy; p.uz = dz;
-  set_energy(p, S, E);
+  set_energy<TAB>(p, S, E);
   return true;
 }
 
@@ -487,7 +520,7 @@ __device__ __forceinline__ bool escape(Photon &p, const CaseDev &G, Counters &c,
 // majorant: photoelectric, Compton, Rayleigh or fictitious by comparing xi
 // with the cumulative sums in that order; returns false when the photon is
 // done.
-template <bool LOG>
+template <bool LOG, bool TAB>
 __device__ __forceinline__ bool collide(Photon &p, const StepCase &S, const CaseDev &G,
                                         Counters &c, const uint4 &r, uint32_t k, int32_t vox,
                                         uint32_t m, float rho, float a, float b, float cr,
@@ -512,7 +545,7 @@ __device__ __forceinline__ bool collide(Photon &p, const StepCase &S, const Case
     const float Ep = E * __builtin_amdgcn_rcpf(fmaf(E * kInvMeC2, 1.0f - mu, 1.0f));
     deposit<LOG>(S, G, p, c, vox, E - Ep, 2, Ep);  // exact: Ep > E/2 (Sterbenz)
     rotate(p, mu, unif(r.w));
-    set_energy(p, S, Ep);
+    set_energy<TAB>(p, S, Ep);
     if (Ep < G.e_cut) {
       c.add(ACC_N_STEPS, k);
       c.add(ACC_N_CUTOFF, 1);
@@ -539,7 +572,7 @@ __device__ __forceinline__ bool collide(Photon &p, const StepCase &S, const Case
 
 // Tentative collision at voxel vox against majorant mumax: read the voxel
 // (1-byte palette index or 8-byte record), then select.
-template <bool LOG>
+template <bool LOG, bool TAB>
 __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const CaseDev &G,
                                          const LOCAL uint2 *pal, Counters &c, const uint4 &r,
                                          uint32_t k, int32_t vox, float mumax) {
@@ -553,11 +586,12 @@ __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const Cas
     rbits = rec.x;
     m = rec.y;
   }
-  const GLOBAL float4 *t = S.mu_rho + (__umul24(m, (uint32_t)S.ne) + (uint32_t)p.je);
-  const float4 t0 = t[0], t1 = t[1];
+  const uint32_t ti = __umul24(m, (uint32_t)S.ne) + (uint32_t)p.je;
+  float4 t0, t1;
+  table_rows<TAB>(S, ti, t0, t1);
   const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
   const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
-  return collide<LOG>(p, S, G, c, r, k, vox, m, __uint_as_float(rbits), a, b, cr,
+  return collide<LOG, TAB>(p, S, G, c, r, k, vox, m, __uint_as_float(rbits), a, b, cr,
                       unif(r.y) * mumax);
 }
 
@@ -568,7 +602,7 @@ __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const Cas
 // rounding is monotone), so xi at or above it is a fictitious collision
 // whatever the voxel holds, decided without reading the voxel; otherwise the
 // voxel's density is read and the selection is the one interact() makes.
-template <bool LOG>
+template <bool LOG, bool TAB>
 __device__ __forceinline__ bool interact_bounded(Photon &p, const StepCase &S, const CaseDev &G,
                                                  const LOCAL uint2 *cls_tab, Counters &c,
                                                  const uint4 &r, uint32_t k, int32_t vox,
@@ -576,8 +610,9 @@ __device__ __forceinline__ bool interact_bounded(Photon &p, const StepCase &S, c
   const uint2 ce = cls_tab[cls];
   const uint32_t m = ce.y;
   const float rho_c = __uint_as_float(ce.x);
-  const GLOBAL float4 *t = S.mu_rho + (__umul24(m, (uint32_t)S.ne) + (uint32_t)p.je);
-  const float4 t0 = t[0], t1 = t[1];
+  const uint32_t ti = __umul24(m, (uint32_t)S.ne) + (uint32_t)p.je;
+  float4 t0, t1;
+  table_rows<TAB>(S, ti, t0, t1);
   const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
   const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
   const float xi = unif(r.y) * p.mumax;
@@ -585,12 +620,12 @@ __device__ __forceinline__ bool interact_bounded(Photon &p, const StepCase &S, c
   if (S.rayleigh) bound = bound + rho_c * cr;
   if (xi >= bound) return true;
   const float rho = __uint_as_float(S.vox[vox].x);
-  return collide<LOG>(p, S, G, c, r, k, vox, m, rho, a, b, cr, xi);
+  return collide<LOG, TAB>(p, S, G, c, r, k, vox, m, rho, a, b, cr, xi);
 }
 
 // One Woodcock step (Sec. 2.1) against the global majorant; returns false
 // when the photon is done.
-template <bool LOG>
+template <bool LOG, bool TAB>
 __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G,
                                      const LOCAL uint2 *pal, Counters &c) {
   p.k += 1;
@@ -617,9 +652,9 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
     const uint32_t blk = __umul24(__umul24(iz >> S.bshift, bgy) + (iy >> S.bshift), bgx) +
                          (ix >> S.bshift);
     const uint32_t cls = S.bgrid[blk];
-    if (cls != kMixedClass) return interact_bounded<LOG>(p, S, G, pal, c, r, k, vox, cls);
+    if (cls != kMixedClass) return interact_bounded<LOG, TAB>(p, S, G, pal, c, r, k, vox, cls);
   }
-  return interact<LOG>(p, S, G, pal, c, r, k, vox, p.mumax);
+  return interact<LOG, TAB>(p, S, G, pal, c, r, k, vox, p.mumax);
 }
 
 // One Woodcock step with deferred collisions (bound grid present): the fast
@@ -633,7 +668,7 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
 // refill step) or kStepDone (stopped by the step guard).
 constexpr int kStepOn = 0, kStepPending = 1, kStepGone = 2, kStepDone = 3;
 
-template <bool LOG>
+template <bool LOG, bool TAB>
 __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const CaseDev &G,
                                          const LOCAL uint2 *cls_tab, Counters &c,
                                          int32_t &pvox) {
@@ -666,8 +701,9 @@ __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const Cas
   if (cls != kMixedClass) {
     const uint2 ce = cls_tab[cls];
     const float rho_c = __uint_as_float(ce.x);
-    const GLOBAL float4 *t = S.mu_rho + (__umul24(ce.y, (uint32_t)S.ne) + (uint32_t)p.je);
-    const float4 t0 = t[0], t1 = t[1];
+    const uint32_t ti = __umul24(ce.y, (uint32_t)S.ne) + (uint32_t)p.je;
+    float4 t0, t1;
+    table_rows<TAB>(S, ti, t0, t1);
     const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
     const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
     float bound = rho_c * a + rho_c * b;
@@ -690,7 +726,7 @@ __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const Cas
 // least one crossing or ends the flight.
 constexpr int kMacroCrossings = 4;
 
-template <bool LOG>
+template <bool LOG, bool TAB>
 __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const CaseDev &G,
                                            const LOCAL uint2 *pal, Counters &c) {
   if (p.tau < 0.0f) {  // a new flight
@@ -787,7 +823,7 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
   const int iz = min(max((int)p.pz, cz * cs), min(cz * cs + cs, (int)S.fnz) - 1);
   const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)iz, (uint32_t)S.ny) + (uint32_t)iy,
                                          (uint32_t)S.nx) + ix;
-  return interact<LOG>(p, S, G, pal, c, make_uint4(0u, p.ry, p.rz, p.rw), k, vox, mu_c);
+  return interact<LOG, TAB>(p, S, G, pal, c, make_uint4(0u, p.ry, p.rz, p.rw), k, vox, mu_c);
 }
 
 // ------------------------------------------------------- transport kernel
@@ -839,22 +875,36 @@ __device__ __forceinline__ void stage_case(CaseDev *dst, uint2 *pal, const CaseD
 // macro-cell step spills a few words outside its cell walk and gains more
 // from the fifth wave hiding its dependent cell/majorant loads than the
 // spills cost.
-template <bool LOG, bool MACRO>
+template <bool LOG, bool MACRO, bool TAB>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k_transport(const RoundCase *__restrict__ rcs, int nrc,
                                                    uint64_t total_chunks,
                                                    unsigned long long *chunk_ctr, int refill_min,
                                                    int chunk, int tally_mode, int bound_shift,
-                                                   int defer_min) {
-  __shared__ unsigned long long wave_acc[8][ACC_COUNT];
-  __shared__ CaseDev wave_case[8];
-  __shared__ uint2 wave_pal[8][256];
-  extern __shared__ unsigned long long cache_lds[];   // tally mode 2: kCacheBytesPerWave per wave
+                                                   int defer_min, int tab_n, int tab_ne) {
+  extern __shared__ unsigned long long dyn_lds[];   // layout: see kWaveLdsBytes
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  CaseDev &G = wave_case[w];
-  uint2 *pal = wave_pal[w];
+  unsigned char *slot = (unsigned char *)dyn_lds + w * kWaveLdsBytes;
+  CaseDev &G = *(CaseDev *)(slot + kWaveAccBytes);
+  uint2 *pal = (uint2 *)(slot + kWaveAccBytes + kWaveCaseBytes);
   const LOCAL uint2 *pal_lds = (const LOCAL uint2 *)pal;
+  unsigned char *after_slots = (unsigned char *)dyn_lds + nw * kWaveLdsBytes;
+  // single-case launch: the workgroup stages the case's majorant nodes and
+  // mu/rho rows once; every wave's step reads them from LDS
+  LOCAL float *tabmax = nullptr;
+  LOCAL float4 *tab = nullptr;
+  if (TAB) {
+    tabmax = (LOCAL float *)(after_slots + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0));
+    tab = (LOCAL float4 *)(tabmax + ((tab_ne + 3) & ~3));
+    const CaseDev *cd = rcs[0].cd;
+    const float4 *src = cd->mu_rho;
+    const float *srcm = cd->mu_max;
+    for (int i = threadIdx.x; i < tab_n; i += blockDim.x) tab[i] = src[i];
+    for (int i = threadIdx.x; i < tab_ne; i += blockDim.x) tabmax[i] = srcm[i];
+    __syncthreads();
+  }
 
   // wave-uniform state
   StepCase S;
@@ -867,10 +917,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
   uint32_t refills = 0;
 
   Counters cnt;
-  cnt.s = wave_acc[w];
+  cnt.s = (unsigned long long *)slot;
   if (lane < ACC_COUNT) cnt.s[lane] = 0ull;
   LOCAL unsigned char *cache =
-      tally_mode == 2 ? (LOCAL unsigned char *)cache_lds + w * kCacheBytesPerWave : nullptr;
+      tally_mode == 2 ? (LOCAL unsigned char *)after_slots + w * kCacheBytesPerWave : nullptr;
   if (cache) clear_cache(cache, lane);
   Photon p;
   p.k = 0;
@@ -899,6 +949,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
         pend = -1;
         stage_case(&G, pal, rcs[cur].cd, lane);
         S = make_step_case(G, tally_mode, bound_shift, cache);
+        S.tab = tab;
+        S.tabmax = tabmax;
         pool_next = pend_lo;
         pool_end = pend_hi;
         wbin = find_bin(rcs[cur].prefix, G.nbins, pool_next);
@@ -930,6 +982,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
             cur = rc;
             stage_case(&G, pal, rcs[cur].cd, lane);
             S = make_step_case(G, tally_mode, bound_shift, cache);
+        S.tab = tab;
+        S.tabmax = tabmax;
             wbin = find_bin(rcs[cur].prefix, G.nbins, lo);
           }
           pool_next = lo;
@@ -950,7 +1004,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
           const uint64_t local = pool_next + rank;
           int j = wbin;
           while (j + 1 < G.nbins && local >= R.prefix[j + 1]) ++j;
-          alive = source<LOG>(p, S, G, R.h_begin + local, j, R.beamlets, local, cnt);
+          alive = source<LOG, TAB>(p, S, G, R.h_begin + local, j, R.beamlets, local, cnt);
         }
         pool_next += m;
         refills += 1;
@@ -964,7 +1018,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
       continue;
     }
     if constexpr (MACRO) {
-      if (alive) alive = step_macro<LOG>(p, S, G, pal_lds, cnt);
+      if (alive) alive = step_macro<LOG, TAB>(p, S, G, pal_lds, cnt);
     } else if (S.bgrid && defer_min > 0) {
       // collision pass: the pending tentative collisions of the wave, once
       // defer_min of them have gathered (or every live lane waits on one)
@@ -973,16 +1027,16 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
         if (alive && pvox >= 0) {
           const uint32_t k = p.k & kStepMask;
           const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
-          alive = interact<LOG>(p, S, G, pal_lds, cnt, r, k, pvox, p.mumax);
+          alive = interact<LOG, TAB>(p, S, G, pal_lds, cnt, r, k, pvox, p.mumax);
           pvox = -1;
         }
       }
       if (alive && pvox < 0) {
-        const int st = step_fast<LOG>(p, S, G, pal_lds, cnt, pvox);
+        const int st = step_fast<LOG, TAB>(p, S, G, pal_lds, cnt, pvox);
         alive = st <= kStepPending;
       }
     } else if (alive) {
-      alive = step<LOG>(p, S, G, pal_lds, cnt);
+      alive = step<LOG, TAB>(p, S, G, pal_lds, cnt);
     }
   }
   if (cur >= 0) {
@@ -1388,27 +1442,43 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
                      bool macro, void *stream) {
   hipStream_t s = (hipStream_t)stream;
-  auto kern = with_log ? (macro ? k_transport<true, true> : k_transport<true, false>)
-                       : (macro ? k_transport<false, true> : k_transport<false, false>);
-  const size_t lds = cfg.tally_mode == 2 ? (size_t)(cfg.block / 64) * kCacheBytesPerWave : 0;
+  // stage the tables only where the workgroup's LDS then still allows the
+  // resident workgroups the grid is sized for
+  int tab_n = nrc == 1 ? cfg.tab_n : 0;
+  size_t lds = transport_lds_bytes(cfg.block, cfg.tally_mode, 0, 0);
+  if (tab_n > 0) {
+    const size_t with = transport_lds_bytes(cfg.block, cfg.tally_mode, tab_n, cfg.tab_ne);
+    if (with <= cfg.lds_budget) lds = with; else tab_n = 0;
+  }
+  using Kern = void (*)(const RoundCase *, int, uint64_t, unsigned long long *, int, int, int,
+                        int, int, int, int);
+  static const Kern kerns[2][2][2] = {
+      {{k_transport<false, false, false>, k_transport<false, false, true>},
+       {k_transport<false, true, false>, k_transport<false, true, true>}},
+      {{k_transport<true, false, false>, k_transport<true, false, true>},
+       {k_transport<true, true, false>, k_transport<true, true, true>}}};
+  const Kern kern = kerns[with_log ? 1 : 0][macro ? 1 : 0][tab_n > 0 ? 1 : 0];
   hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.block), lds, s, rc_dev, nrc, total_chunks,
                      chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode, cfg.bound_shift,
-                     cfg.defer_min);
+                     cfg.defer_min, tab_n, tab_n > 0 ? cfg.tab_ne : 0);
   return check_launch();
 }
 
+size_t transport_lds_bytes(int block, int tally_mode, int tab_n, int tab_ne) {
+  const size_t nw = (size_t)(block / 64);
+  size_t b = nw * kWaveLdsBytes + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0);
+  if (tab_n > 0) b += (size_t)((tab_ne + 3) & ~3) * 4 + (size_t)tab_n * 16;
+  return b;
+}
+
 bool transport_lds_fits(int block, int tally_mode, int device) {
-  if (tally_mode != 2) return true;  // static LDS only, sized for 512-thread workgroups
-  hipFuncAttributes a;
   int lim = 0;
-  if (hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_transport<false, false>)) !=
-          hipSuccess ||
-      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
-          hipSuccess) {
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+      hipSuccess) {
     (void)hipGetLastError();  // not a launch error: leave nothing for check_launch
     return false;
   }
-  return a.sharedSizeBytes + (size_t)(block / 64) * kCacheBytesPerWave <= (size_t)lim;
+  return transport_lds_bytes(block, tally_mode, 0, 0) <= (size_t)lim;
 }
 
 static int grid_for(int64_t n, int block, int cap) {
