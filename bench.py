@@ -413,9 +413,22 @@ def extensions_leg(ctx, L, W, Case, torch, tuning, n_hist: int = 200_000_000):
     return out
 
 
+def _wait_all(L, sv, tickets, n: int):
+    """Block until all n submitted requests have finished, printing progress."""
+    last = time.time()
+    while True:
+        done = sum(1 for t in tickets if t is not None and L.ctd_server_poll(sv, t).state >= 2)
+        if done == n:
+            return
+        if time.time() - last > 20:
+            log(f"serving: {done}/{n} requests finished")
+            last = time.time()
+        time.sleep(0.2)
+
+
 def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
                 batch: int = 10_000_000, max_h: int = 300_000_000_000, tracking=None,
-                max_active: int = 64, detail: bool = False):
+                max_active: int = 64, detail: bool = False, warmup_req: int = 0):
     """Poisson stream of run-to-1%-sigma requests from the batched case
     distribution.  Baseline: the same requests run one at a time in arrival
     order (FIFO), latencies from the measured service times and the trace; a
@@ -423,7 +436,9 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
     host arrays, case creation, the run, the exact sums back to the host,
     freeing), the material set, spectrum and geometry being built beforehand
     in both.  Served: the continuous-batching server fed in real time.
-    tracking as in batched_leg, for the solo runs and the served requests."""
+    tracking as in batched_leg, for the solo runs and the served requests.
+    Latency percentiles leave out the first warmup_req requests (they still
+    run and load the queue)."""
     import threading
 
     import numpy as np
@@ -453,6 +468,8 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
         service.append((t1 - t0) + (time.perf_counter() - t2))
         if i < 3:
             ref[i] = s1
+        if (i + 1) % 10 == 0:
+            log(f"serving: {i + 1}/{n_req} FIFO service times measured")
     end, lat_plain = 0.0, []
     for a, sv_t in zip(arrivals, service):
         end = max(end, a) + sv_t
@@ -485,6 +502,7 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
         th = threading.Thread(target=feed)
         th.start()
         th.join()
+        _wait_all(L, sv, tickets, n_req)
         infos = [L.ctd_server_wait(sv, t)[1] for t in tickets]
         same = all(np.array_equal(ref[i], L.ctd_server_read_tally(sv, tickets[i],
                                                                   wls[i].n_voxels)[0])
@@ -496,19 +514,23 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
             inp.close()
     lat = [x.t_done - x.t_submit for x in infos]
     hist = sum(x.histories for x in infos)
+    w = min(warmup_req, n_req - 1)
+    lat_w, lat_plain_w = lat[w:], lat_plain[w:]
     per_request = dict(arrival_s=[float(a) for a in arrivals], service_s=service,
                        fifo_latency_s=lat_plain, served_latency_s=lat,
                        served_admit_s=[x.t_admit - x.t_submit for x in infos]) if detail else None
     makespan = max(x.t_done for x in infos) - min(x.t_submit for x in infos)
     service_rate = n_req / sum(service)
-    log(f"serving: served p50 {np.percentile(lat, 50):.2f} s, {hist / makespan:.4g} hist/s")
-    return dict(requests=n_req, trace=f"first {n_req} of the 200 requests of the Poisson trace",
-                arrival_rate_hz=rate_hz, sigma_target=0.01,
+    log(f"serving: served p50 {np.percentile(lat_w, 50):.2f} s, {hist / makespan:.4g} hist/s")
+    return dict(requests=n_req,
+                trace=(f"{n_req} of the 200 requests of the Poisson trace" if n_req < 200 else
+                       "the 200-request Poisson trace"),
+                warmup_requests=w, arrival_rate_hz=rate_hz, sigma_target=0.01,
                 batch_histories=batch, max_active=max_active,
-                p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                p50_s=float(np.percentile(lat_w, 50)), p99_s=float(np.percentile(lat_w, 99)),
                 histories_per_s=hist / makespan,
-                plain_fifo_p50_s=float(np.percentile(lat_plain, 50)),
-                plain_fifo_p99_s=float(np.percentile(lat_plain, 99)),
+                plain_fifo_p50_s=float(np.percentile(lat_plain_w, 50)),
+                plain_fifo_p99_s=float(np.percentile(lat_plain_w, 99)),
                 plain_histories_per_s=hist_plain / makespan_plain,
                 mean_service_s=float(np.mean(service)),
                 single_gpu_service_rate_hz=service_rate,
@@ -519,6 +541,49 @@ def serving_leg(ctx, L, W, torch, n_req: int, rate_hz: float = 2.0,
                 identical_to_plain=bool(same), rounds=st.rounds,
                 phantom_loads=st.phantom_loads,
                 **({"per_request": per_request} if detail else {}))
+
+
+def trace_idle(trace_dir: str):
+    """GPU idle share of the served phase in a rocprofv3 kernel trace (csv)
+    of a run with the serving leg: the server's host threads launch every
+    dispatch from the first served round on, so the window runs from the first
+    dispatch of a thread other than the one that launched the process's first
+    dispatch to the last dispatch; busy time is the union of the dispatch
+    intervals inside it."""
+    import csv
+    import glob
+    import statistics
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)[0]
+    rows = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Thread_Id"],
+                   r["Kernel_Name"]) for r in csv.DictReader(open(f)))
+    main_thread = rows[0][2]
+    served = [r for r in rows if r[2] != main_thread]
+    w0, w1 = served[0][0], max(e for _, e, _, _ in served)
+    busy, gaps, cur = 0, [], None
+    for s, e, _, _ in rows:
+        if e <= w0 or s >= w1:
+            continue
+        s, e = max(s, w0), min(e, w1)
+        if cur is None or s > cur[1]:
+            if cur is not None:
+                busy += cur[1] - cur[0]
+                gaps.append(s - cur[1])
+            cur = [s, e]
+        else:
+            cur[1] = max(cur[1], e)
+    busy += cur[1] - cur[0]
+    span = w1 - w0
+    big = [g for g in gaps if g > 1_000_000]
+    kinds = {}
+    for _, _, _, n in served:
+        k = n.split("(")[0].replace("void ", "")
+        kinds[k] = kinds.get(k, 0) + 1
+    print(json.dumps(dict(
+        trace=f, window_s=span / 1e9, busy_s=busy / 1e9, idle_frac=(span - busy) / span,
+        gaps=len(gaps), gap_sum_s=sum(gaps) / 1e9,
+        gap_median_us=statistics.median(gaps) / 1e3 if gaps else 0.0,
+        gaps_over_1ms=len(big), gaps_over_1ms_s=sum(big) / 1e9,
+        dispatches=len(served), dispatches_by_kernel=kinds), indent=1))
 
 
 def calibrate_copy():
@@ -669,8 +734,14 @@ def main():
     ap.add_argument("--cpu-histories", type=int, default=None)
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--serving-requests", type=int, default=12)
+    ap.add_argument("--serving-warmup", type=int, default=0,
+                    help="leading requests left out of the latency percentiles")
+    ap.add_argument("--serving-modes", default="global,auto",
+                    help="tracking modes of the serving leg: global, auto or both")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-counters", action="store_true")
+    ap.add_argument("--trace-idle", metavar="DIR",
+                    help="GPU idle share of the served phase in a kernel trace, then exit")
     ap.add_argument("--workload", default="head", choices=sorted(WORKLOADS),
                     help="main-leg workload (default: the synthetic head)")
     ap.add_argument("--tracking", default="global", choices=["global", "macro"])
@@ -687,6 +758,9 @@ def main():
         return
     if args.summarize_counters:
         summarize_counters(args.workload)
+        return
+    if args.trace_idle:
+        trace_idle(args.trace_idle)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the transport runs on a single MI355X "
@@ -749,9 +823,14 @@ def main():
         out["batched_auto_tracking"] = batched_leg(ctx, L, W, Case, tuning, torch,
                                                    args.batched_scale, L.CTD_TRACK_AUTO)
     if "serving" in legs and args.serving_requests > 0:
-        out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests)
-        out["serving_auto_tracking"] = serving_leg(ctx, L, W, torch, args.serving_requests,
-                                                   tracking=L.CTD_TRACK_AUTO)
+        modes = set(args.serving_modes.split(","))
+        if "global" in modes:
+            out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests,
+                                         warmup_req=args.serving_warmup)
+        if "auto" in modes:
+            out["serving_auto_tracking"] = serving_leg(ctx, L, W, torch, args.serving_requests,
+                                                       tracking=L.CTD_TRACK_AUTO,
+                                                       warmup_req=args.serving_warmup)
     if "extensions" in legs:
         out["extensions"] = extensions_leg(ctx, L, W, Case, torch, tuning)
 

@@ -446,16 +446,21 @@ int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out, uint64_t 
                            uint64_t *n);
 
 /* ---------------- serving (continuous batching) ----------------
- * A server owns a private context on `device` and a host thread.  Phantoms
- * are registered once (host arrays, copied) and loaded to the device on first
- * use; they stay resident and are evicted least-recently-used when an
- * admission needs the room.  Requests (a phantom key, material set, spectrum,
- * geometry, parameters and a sigma-bar target) queue in arrival order and are
- * admitted while their device footprint fits hbm_budget_bytes.  Each round
- * runs one batch of batch_histories for every admitted request in a single
- * launch of the batched engine; requests arriving meanwhile join the next
- * round.  Every request follows the batch schedule of ctd_run_to_sigma with
- * the same batch size, so its result is identical alone or among others.
+ * A server owns two private contexts on `device` and two host threads: one
+ * enqueues the rounds, the other admits requests and copies results out
+ * while the rounds run.  Phantoms are registered once (host arrays, copied)
+ * and loaded to the device on first use; they stay resident and are evicted
+ * least-recently-used when an admission needs the room.  Requests (a phantom
+ * key, material set, spectrum, geometry, parameters and a sigma-bar target)
+ * queue in arrival order and are admitted while their device footprint fits
+ * hbm_budget_bytes.  Each round runs one batch of batch_histories for every
+ * admitted request in a single launch of the batched engine; the host waits
+ * for the device once per iteration of up to 24 rounds or 2e8 histories,
+ * and requests admitted meanwhile join the next iteration.  Every request
+ * follows the batch schedule of ctd_run_to_sigma with the same batch size, so
+ * its result is identical alone or among others.  Beyond the budget the
+ * server keeps staging buffers sized by the largest registered phantom: 5
+ * bytes per voxel of device memory and 29 of pinned host memory.
  * Material sets, spectra and geometries may come from any context on the same
  * device; a request holds them from submission until it finishes (releasing
  * one earlier returns CTD_EBUSY).  The calls may come from any host thread,
@@ -512,7 +517,8 @@ int32_t ctd_server_read_tally(ctd_server *sv, uint64_t ticket, uint64_t n_voxels
 int32_t ctd_server_release(ctd_server *sv, uint64_t ticket);
 int32_t ctd_server_cancel(ctd_server *sv, uint64_t ticket);
 int32_t ctd_server_read_stats(ctd_server *sv, ctd_server_stats *out);
-/* Finish the running round, cancel the rest, free everything. */
+/* Finish the running iteration, copy out the requests that reached their
+ * target in it, cancel the rest, free everything. */
 int32_t ctd_server_stop(ctd_server *sv);
 
 #ifdef __cplusplus

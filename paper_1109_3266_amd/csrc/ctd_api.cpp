@@ -88,6 +88,7 @@ extern "C" int32_t ctd_create(ctd_ctx **out, int32_t device) {
   (void)hipGetLastError();
   ctx->slots.resize(64);
   if (hipMalloc(&ctx->sigma_scratch, sizeof(double) * (3 * kSigmaBlocks + 4)) != hipSuccess ||
+      hipMalloc(&ctx->pack_stats, sizeof(unsigned int) * kPackStats) != hipSuccess ||
       hipHostMalloc(&ctx->sigma_host, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
     ctd_destroy(ctx);
     return CTD_ENOMEM;
@@ -125,6 +126,7 @@ extern "C" int32_t ctd_destroy(ctd_ctx *ctx) {
     dfree(s.dev);
   }
   dfree(ctx->sigma_scratch);
+  dfree(ctx->pack_stats);
   if (ctx->sigma_host) (void)hipHostFree(ctx->sigma_host);
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
@@ -266,20 +268,19 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
   ph->V = V;
   uint8_t *dmat = nullptr;
   float *drho = nullptr;
-  unsigned int *dstat = nullptr;
+  // the context's statistics buffer: a device-memory input is packed with no
+  // allocation freed on the way (a free waits for the whole device)
+  unsigned int *dstat = ctx->pack_stats;
   int rc = CTD_OK;
   auto fail = [&](int code) {
     dfree(dmat);
     dfree(drho);
-    dfree(dstat);
     free_phantom_buffers(ph);
     delete ph;
     return code;
   };
   hipError_t e = hipMalloc(&ph->vox, sizeof(uint2) * V);
   if (e != hipSuccess) return fail(hip_err(ctx, e, "phantom alloc"));
-  e = hipMalloc(&dstat, sizeof(unsigned int) * kPackStats);
-  if (e != hipSuccess) return fail(hip_err(ctx, e, "phantom stats alloc"));
   const uint8_t *pm = mat;
   const float *pr = rho;
   if (mem == CTD_MEM_HOST) {
@@ -319,8 +320,6 @@ extern "C" int32_t ctd_phantom_load(ctd_ctx *ctx, const ctd_grid *g, const uint8
   dfree(drho);
   dmat = nullptr;
   drho = nullptr;
-  dfree(dstat);
-  dstat = nullptr;
   if ((rc = build_palette(ctx, ph)) != CTD_OK) return fail(rc);
   if (ph->npal == 0 && (rc = build_bound_grids(ctx, ph)) != CTD_OK) return fail(rc);
   *out = ph;
@@ -1262,17 +1261,25 @@ int ctd::check_batch_sizes(ctd_ctx *ctx, const ctd_case *cs, uint64_t next_size)
   return CTD_OK;
 }
 
-int ctd::sigma_now(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *out) {
+int ctd::sigma_async(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *host_out) {
   if (cs->batches < 2) return set_err(ctx, CTD_EINVAL, "sigma needs >= 2 folded batches");
   int rc = check_batch_sizes(ctx, cs, 0);
   if (rc != CTD_OK) return rc;
   double rho_min = cs->p.sigma_rho_min;
+  // the scratch is reused by the next reduction on the stream, which starts
+  // after this one's results have been copied out
   double *out_dev = ctx->sigma_scratch + 3 * kSigmaBlocks;
   if (launch_sigma(cs->d_s1, cs->d_s2, cs->ph->vox, cs->ph->V, cs->batches, rho_min, frac, kind,
                    ctx->sigma_scratch, kSigmaBlocks, out_dev, ctx->stream) != 0)
     return hip_err(ctx, hipGetLastError(), "sigma launch");
-  HIPCHK(ctx, hipMemcpyAsync(ctx->sigma_host, out_dev, 3 * sizeof(double),
-                             hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(host_out, out_dev, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  return CTD_OK;
+}
+
+int ctd::sigma_now(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *out) {
+  int rc = sigma_async(ctx, cs, kind, frac, ctx->sigma_host);
+  if (rc != CTD_OK) return rc;
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   *out = ctx->sigma_host[0];
   return CTD_OK;

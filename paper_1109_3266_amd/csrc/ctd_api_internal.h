@@ -42,6 +42,7 @@ struct ctd_ctx {
   size_t next_slot = 0;
   double *sigma_scratch = nullptr;
   double *sigma_host = nullptr;
+  unsigned int *pack_stats = nullptr;  // [kPackStats] phantom statistics of k_pack
   bool xcd_tally_ok = false;  // every XCC id < kTallyCopies
   unsigned int max_xcc = 0;
   int lds_per_cu = 160 * 1024, lds_per_block = 64 * 1024;  // device LDS limits
@@ -163,6 +164,10 @@ int run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vector<ui
               const ctd_tuning &t);
 std::vector<uint64_t> split_batches(uint64_t n, int nb);
 int sigma_now(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *out);
+// Enqueue the sigma-bar reduction of a case on ctx->stream and the copy of
+// its three results (sigma-bar, D_max, voxels counted) to host_out, which
+// should be pinned; nothing waits.
+int sigma_async(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *host_out);
 // CTD_OK when the case's folded batches, together with `next` more of
 // next_size histories (none when next_size = 0), differ in size by at most
 // one history; else CTD_EINVAL with a message.

@@ -1,17 +1,34 @@
 // Dose-serving loop: continuous batching of run-to-sigma requests over the
 // batched transport engine on one GPU.
 //
-// A host thread owns a private context.  Requests queue in arrival order and
-// are admitted while their device footprint (tallies, plus the phantom when
-// it is not already resident) fits the budget; loaded phantoms stay resident
-// and are evicted least-recently-used when an admission needs the room.
-// Every round gives each admitted request one batch of the configured size in
-// a single launch of the multi-case kernel, so requests that arrive while a
-// round runs join the next one.  A request follows exactly the batch schedule
-// of ctd_run_to_sigma (pilot of n_batches, then the shared sigma plan), and
-// tallies depend only on a case's own batches, so each result is identical
-// whether the request runs alone or among others.  On completion the exact
-// sums are copied to host memory and the request's device memory is freed.
+// Two host threads, each with a private context on the device:
+//
+//  * the runner owns the transport stream.  Each iteration enqueues several
+//    rounds back to back (up to kIterationHistories histories, kIterationRounds
+//    rounds); a round gives every admitted request with planned batches left
+//    one batch of the configured size in a single launch of the multi-case
+//    kernel.  A request whose plan completes in a round gets its sigma-bar
+//    reduction enqueued right behind that round, with the three results
+//    copied to a pinned host slot, so the host waits once per iteration.
+//    Then it stops the request or plans more batches, exactly as
+//    ctd_run_to_sigma does alone.
+//  * the host worker does the rest on a second stream while the rounds run:
+//    admissions (phantom upload through pinned and device staging, packing,
+//    case set-up) and the copy of finished requests' exact sums to host
+//    memory.
+//
+// Freeing device memory waits for the whole device, so the runner frees the
+// cases of finished requests once per iteration, after enqueueing the next
+// one; nothing else is freed while rounds run except evicted phantoms and
+// the staging buffers when a larger phantom first needs them.
+//
+// Requests queue in arrival order and are admitted while their device
+// footprint (tallies, plus the phantom when it is not already resident) fits
+// the budget; loaded phantoms stay resident and are evicted least-recently-
+// used when an admission needs the room.  A request follows exactly the batch
+// schedule of ctd_run_to_sigma (pilot of n_batches, then the shared sigma
+// plan), and tallies depend only on a case's own batches, so each result is
+// identical whether the request runs alone or among others.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +50,14 @@
 using namespace ctd;
 
 namespace {
+
+// Work the runner enqueues between two host waits: about 20-40 ms of
+// transport on MI355X, long next to the wait and the re-planning between
+// iterations and short next to a request's seconds of service.  The round
+// cap keeps an iteration within a context's 64 launch-table slots (two per
+// round when global and MACRO cases share it).
+constexpr uint64_t kIterationHistories = 200000000ull;
+constexpr int kIterationRounds = 24;
 
 struct PhantomEntry {
   ctd_grid g{};
@@ -58,10 +83,11 @@ struct Request {
   double sigma = NAN;
   double t_submit = 0, t_admit = 0, t_done = 0;
   ctd_case *cs = nullptr;
-  uint64_t planned = 0;      // batches the current plan runs to
+  uint64_t planned = 0;      // batches the current plan runs to (runner)
   uint64_t footprint = 0;    // device bytes of the case
-  // progress, updated by the server thread under the lock (poll reads these,
-  // never the case, which the thread updates unlocked during a round)
+  int end_state = 0, end_status = CTD_OK;  // taken once the case is freed
+  // progress, updated by the runner under the lock (poll reads these, never
+  // the case, which the runner updates unlocked during an iteration)
   uint64_t histories = 0;
   uint32_t batches = 0;
   // results kept on the host after completion
@@ -69,25 +95,63 @@ struct Request {
   std::vector<uint64_t> s2_hi, s2_lo;
 };
 
+// A pinned host or device buffer that only grows: freeing waits for the
+// whole device, so it is replaced only when a larger size is first needed.
+struct GrowBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  bool host = false;
+  hipError_t reserve(size_t bytes) {
+    if (cap >= bytes) return hipSuccess;
+    release();
+    hipError_t e = host ? hipHostMalloc(&p, bytes, hipHostMallocDefault) : hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = bytes;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)(host ? hipHostFree(p) : hipFree(p));
+    p = nullptr;
+    cap = 0;
+  }
+};
+
 }  // namespace
 
 struct ctd_server {
-  ctd_ctx *ctx = nullptr;
+  ctd_ctx *ctx = nullptr;   // the runner's: rounds, folds, sigma-bar checks
+  ctd_ctx *aux = nullptr;   // the host worker's: admissions, result copies
   ctd_server_config cfg{};
-  std::thread th;
+  std::thread runner, worker;
   mutable std::mutex mu;   // guards everything below, err included
-  std::condition_variable cv_work, cv_done;
-  std::deque<Request *> queue;
-  std::vector<Request *> active;
+  std::condition_variable cv_run, cv_host, cv_done;
+  std::deque<Request *> queue;     // submitted, not admitted
+  std::vector<Request *> ready;    // admitted, joining the next iteration
+  std::vector<Request *> active;   // in the rounds
+  std::deque<Request *> readback;  // plan done at sigma-bar: sums to copy out
+  std::vector<Request *> retire;   // cases to free before the final state
   std::map<uint64_t, std::unique_ptr<Request>> all;
   std::map<uint64_t, PhantomEntry> phantoms;
   uint64_t used_bytes = 0, next_ticket = 1, use_clock = 0;
-  bool stop = false;
+  uint64_t free_epoch = 0;   // counts device frees: admissions waiting for room retry
+  int64_t max_voxels = 0;    // largest registered phantom (sizes the staging)
+  bool stop = false, runner_quiet = false, worker_done = false;
   std::string err;
   std::chrono::steady_clock::time_point t0;
   ctd_server_stats stats{};
+  // runner only
+  GrowBuf sig_host{nullptr, 0, true};
+  // host worker only
+  GrowBuf up_host{nullptr, 0, true}, up_dev{nullptr, 0, false}, rb_host{nullptr, 0, true};
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void wake() {
+    cv_run.notify_all();
+    cv_host.notify_all();
   }
 };
 
@@ -102,213 +166,368 @@ static int sv_err(ctd_server *sv, int code, const char *fmt, ...) {
   return code;
 }
 
-// ---------------------------------------------------------- server thread
+// ------------------------------------------------------------ both threads
 
-// Evict unused resident phantoms (least recently used first) until `need`
-// more bytes fit; `keep`, the phantom of the request being admitted, is never
-// evicted (its size is not part of `need` when it is resident).  Called with
-// the lock held.
-static bool make_room(ctd_server *sv, uint64_t need, const PhantomEntry *keep) {
-  while (sv->used_bytes + need > sv->cfg.hbm_budget_bytes) {
-    PhantomEntry *victim = nullptr;
-    for (auto &kv : sv->phantoms) {
-      PhantomEntry &e = kv.second;
-      if (&e != keep && e.dev && e.users == 0 && (!victim || e.last_use < victim->last_use))
-        victim = &e;
-    }
-    if (!victim) return false;
-    ctd_phantom_release(sv->ctx, victim->dev);
-    victim->dev = nullptr;
-    sv->used_bytes -= victim->dev_bytes;
-    sv->stats.evictions++;
-  }
-  return true;
-}
-
-static void finish(ctd_server *sv, Request *r, int state, int status) {
+// Final state of a request that holds no case.  Lock held.
+static void complete(ctd_server *sv, Request *r, int state, int status) {
   r->state = state;
   r->status = status;
   r->t_done = sv->now();
-  if (r->cs) {
-    if (state == 2) {
-      const int64_t V = r->cs->ph->V;
-      r->s1.resize((size_t)V);
-      r->s2_hi.resize((size_t)V);
-      r->s2_lo.resize((size_t)V);
-      uint32_t nb = 0;
-      int rc = ctd_read_tally(sv->ctx, r->cs, r->s1.data(), r->s2_hi.data(), r->s2_lo.data(),
-                              &nb);
-      if (rc != CTD_OK) {
-        r->state = 4;
-        r->status = rc;
-      }
-    }
-    r->histories = r->cs->h_next;
-    r->batches = r->cs->batches;
-    ctd_case_destroy(sv->ctx, r->cs);
-    r->cs = nullptr;
-    sv->used_bytes -= r->footprint;
-    auto it = sv->phantoms.find(r->phantom_key);
-    if (it != sv->phantoms.end()) it->second.users--;
-  }
   if (r->held) {
     r->ms->refs--;
     r->sp->refs--;
     r->geo->refs--;
     r->held = false;
   }
-  if (r->state == 2) sv->stats.completed++;
+  if (state == 2) sv->stats.completed++;
+  sv->cv_done.notify_all();
 }
 
-// Admit queued requests in arrival order while they fit.  Lock held.
-static void admit(ctd_server *sv) {
-  while (!sv->queue.empty() && (int)sv->active.size() < sv->cfg.max_active) {
-    Request *r = sv->queue.front();
-    if (r->cancel) {
-      sv->queue.pop_front();
-      finish(sv, r, 3, CTD_ECANCELLED);
-      continue;
-    }
-    auto it = sv->phantoms.find(r->phantom_key);
-    PhantomEntry &e = it->second;
-    const int64_t V = (int64_t)e.g.nx * e.g.ny * e.g.nz;
-    const int copies = sv->cfg.tuning.block && sv->cfg.tuning.tally_mode != 0 ? kTallyCopies : 1;
-    const uint64_t case_bytes = case_footprint(e.g, r->geo, r->p, r->ms->eg.ne, copies,
-                                               sv->cfg.batch_histories);
-    // records, plus a palette index or the bound grids (1, 2, 4-voxel blocks)
-    const uint64_t ph_bytes =
-        e.dev ? 0 : (uint64_t)V * 9 + (uint64_t)V / 8 + (uint64_t)V / 64 + 8192;
-    const uint64_t need = case_bytes + ph_bytes;
-    if (need > sv->cfg.hbm_budget_bytes) {  // can never fit
-      sv->queue.pop_front();
-      finish(sv, r, 4, CTD_ENOMEM);
-      continue;
-    }
-    if (!make_room(sv, need, &e)) break;  // wait for running requests to finish
-    int rc = CTD_OK;
-    if (!e.dev) {
-      rc = ctd_phantom_load(sv->ctx, &e.g, e.mat.data(), e.rho.data(), CTD_MEM_HOST, &e.dev);
-      if (rc == CTD_OK) {
-        e.dev_bytes = ph_bytes;
-        sv->used_bytes += ph_bytes;
-        sv->stats.phantom_loads++;
-      }
-    } else {
-      sv->stats.phantom_hits++;
-    }
-    sv->queue.pop_front();
-    if (rc == CTD_OK) rc = ctd_case_create(sv->ctx, e.dev, r->ms, r->sp, r->geo, &r->p, &r->cs);
-    if (rc == CTD_OK && sv->cfg.tuning.block)
-      rc = ctd_set_tuning(sv->ctx, r->cs, &sv->cfg.tuning);
-    if (rc != CTD_OK) {
-      if (r->cs) {
-        ctd_case_destroy(sv->ctx, r->cs);
-        r->cs = nullptr;
-      }
-      sv->err = ctd_last_error(sv->ctx);
-      finish(sv, r, 4, rc);
-      continue;
-    }
-    e.users++;
-    e.last_use = ++sv->use_clock;
-    r->footprint = case_bytes;
-    sv->used_bytes += case_bytes;
-    r->planned = std::min<uint64_t>((uint64_t)r->p.n_batches,
-                                    std::max<uint64_t>(sv->cfg.max_histories /
-                                                       sv->cfg.batch_histories, 2));
-    r->state = 1;
-    r->t_admit = sv->now();
-    sv->active.push_back(r);
+// Hand a request with a case to the runner, which frees the case and then
+// gives the request its final state.  Lock held.
+static void retire_later(ctd_server *sv, Request *r, int state, int status) {
+  r->end_state = state;
+  r->end_status = status;
+  sv->retire.push_back(r);
+  sv->cv_run.notify_all();
+}
+
+// ------------------------------------------------------------------ runner
+
+// Free the cases of retiring requests (no lock: each free waits for the
+// device).
+static void free_cases(ctd_server *sv, const std::vector<Request *> &dead) {
+  for (Request *r : dead) {
+    if (!r->cs) continue;
+    ctd_case_destroy(sv->ctx, r->cs);
+    r->cs = nullptr;
   }
 }
 
-static void server_loop(ctd_server *sv) {
+// Their final states, once the memory is back.  Lock held.
+static void complete_retired(ctd_server *sv, const std::vector<Request *> &dead) {
+  for (Request *r : dead) {
+    sv->used_bytes -= r->footprint;
+    r->footprint = 0;
+    auto it = sv->phantoms.find(r->phantom_key);
+    if (it != sv->phantoms.end()) it->second.users--;
+    complete(sv, r, r->end_state, r->end_status);
+  }
+  if (!dead.empty()) {
+    sv->free_epoch++;
+    sv->cv_host.notify_all();   // an admission may fit now
+  }
+}
+
+static void runner_loop(ctd_server *sv) {
   (void)hipSetDevice(sv->ctx->device);
   const uint64_t bh = sv->cfg.batch_histories;
   const uint64_t max_b = std::max<uint64_t>(sv->cfg.max_histories / bh, 2);
+  std::vector<Request *> dead, act, checked;
+  std::vector<int> check_rc;
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
-    // cancelled running requests leave between rounds
+    // admitted requests join; cancelled ones, and all of them on stop, leave
+    for (Request *r : sv->ready) sv->active.push_back(r);
+    sv->ready.clear();
     for (size_t i = 0; i < sv->active.size();) {
       Request *r = sv->active[i];
-      if (r->cancel) {
-        finish(sv, r, 3, CTD_ECANCELLED);
+      if (r->cancel || sv->stop) {
+        retire_later(sv, r, 3, CTD_ECANCELLED);
         sv->active.erase(sv->active.begin() + (long)i);
       } else {
         ++i;
       }
     }
-    admit(sv);
+    if (sv->stop && !sv->runner_quiet) {
+      sv->runner_quiet = true;   // no more requests will reach the read-back list
+      sv->cv_host.notify_all();
+    }
+    dead.clear();
+    dead.swap(sv->retire);
     if (sv->active.empty()) {
-      sv->cv_done.notify_all();
-      if (sv->stop) break;
-      sv->cv_work.wait(lk);
+      if (!dead.empty()) {
+        lk.unlock();
+        free_cases(sv, dead);
+        lk.lock();
+        complete_retired(sv, dead);
+        continue;
+      }
+      if (sv->stop && sv->worker_done) break;
+      sv->cv_run.wait(lk);
       continue;
     }
-    if (sv->stop) {
-      for (Request *r : sv->active) finish(sv, r, 3, CTD_ECANCELLED);
+    act = sv->active;
+    if (sv->sig_host.reserve(sizeof(double) * 4 * act.size()) != hipSuccess) {
+      sv_err(sv, CTD_ENOMEM, "pinned sigma-bar slots");
+      for (Request *r : act) retire_later(sv, r, 4, CTD_ENOMEM);
+      sv->active.clear();
+      sv->retire.insert(sv->retire.end(), dead.begin(), dead.end());
+      continue;
+    }
+    double *slot = (double *)sv->sig_host.p;
+    lk.unlock();
+
+    // one iteration: rounds back to back, sigma-bar behind each completed plan
+    int rc = CTD_OK;
+    uint64_t hist = 0;
+    int rounds = 0;
+    checked.clear();
+    check_rc.clear();
+    std::vector<ctd_case *> cases;
+    std::vector<Request *> reqs;
+    while (rc == CTD_OK && rounds < kIterationRounds && hist < kIterationHistories) {
+      cases.clear();
+      reqs.clear();
+      for (Request *r : act) {
+        if (r->cs->batches < r->planned) {
+          cases.push_back(r->cs);
+          reqs.push_back(r);
+        }
+      }
+      if (cases.empty()) break;
+      const ctd_tuning t = sv->cfg.tuning.block ? sv->cfg.tuning : cases[0]->tune;
+      rc = run_round(sv->ctx, cases, std::vector<uint64_t>(cases.size(), bh), t);
+      if (rc != CTD_OK) break;
+      ++rounds;
+      hist += (uint64_t)cases.size() * bh;
+      for (Request *r : reqs) {
+        if (r->cs->batches < r->planned) continue;
+        check_rc.push_back(sigma_async(sv->ctx, r->cs, sv->cfg.sigma_kind, sv->cfg.dose_frac,
+                                       slot + 4 * checked.size()));
+        checked.push_back(r);
+      }
+    }
+    // retiring cases are freed while the iteration runs
+    free_cases(sv, dead);
+    if (hipStreamSynchronize(sv->ctx->stream) != hipSuccess && rc == CTD_OK) rc = CTD_EDEVICE;
+
+    lk.lock();
+    complete_retired(sv, dead);
+    for (Request *r : act) {
+      r->histories = r->cs->h_next;
+      r->batches = r->cs->batches;
+    }
+    sv->stats.rounds += (uint64_t)rounds;
+    sv->stats.histories += hist;
+    if (rc != CTD_OK) {
+      sv->err = ctd_last_error(sv->ctx);
+      for (Request *r : act) retire_later(sv, r, 4, rc);
       sv->active.clear();
       continue;
     }
-    // one round: every admitted request with planned batches left runs one
-    std::vector<ctd_case *> cases;
-    std::vector<Request *> reqs;
-    for (Request *r : sv->active) {
-      if (r->cs->batches < r->planned) {
-        cases.push_back(r->cs);
-        reqs.push_back(r);
+    for (size_t i = 0; i < checked.size(); ++i) {
+      Request *r = checked[i];
+      const double sig = check_rc[i] == CTD_OK ? slot[4 * i] : NAN;
+      r->sigma = sig;
+      const uint64_t more = std::isnan(sig) ? 0 : sigma_plan(r->cs->batches, sig, r->target, max_b);
+      if (more > 0) {
+        r->planned = r->cs->batches + more;
+        continue;
+      }
+      sv->active.erase(std::find(sv->active.begin(), sv->active.end(), r));
+      if (std::isnan(sig)) {
+        if (check_rc[i] != CTD_OK) sv->err = ctd_last_error(sv->ctx);
+        retire_later(sv, r, 4, check_rc[i] != CTD_OK ? check_rc[i] : CTD_EDEVICE);
+      } else {
+        sv->readback.push_back(r);
+        sv->cv_host.notify_all();
       }
     }
-    lk.unlock();
-    int rc = CTD_OK;
-    if (!cases.empty()) {
-      const ctd_tuning t = sv->cfg.tuning.block ? sv->cfg.tuning : cases[0]->tune;
-      rc = run_round(sv->ctx, cases, std::vector<uint64_t>(cases.size(), bh), t);
-      if (rc == CTD_OK && hipStreamSynchronize(sv->ctx->stream) != hipSuccess)
-        rc = CTD_EDEVICE;
+    sv->cv_done.notify_all();   // progress
+  }
+}
+
+// ------------------------------------------------------------- host worker
+
+// Copy a finished request's exact sums to its host arrays through the pinned
+// staging buffer, on the worker's stream.  No lock.
+static int read_back(ctd_server *sv, Request *r, int64_t max_voxels) {
+  ctd_ctx *aux = sv->aux;
+  const ctd_case *cs = r->cs;
+  const size_t V = (size_t)cs->ph->V;
+  hipError_t e = sv->rb_host.reserve(24 * std::max<size_t>(V, (size_t)max_voxels));
+  if (e != hipSuccess) return hip_err(aux, e, "pinned read-back buffer");
+  char *h = (char *)sv->rb_host.p;
+  if ((e = hipMemcpyAsync(h, cs->d_s1, 8 * V, hipMemcpyDeviceToHost, aux->stream)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(h + 8 * V, cs->d_s2, 16 * V, hipMemcpyDeviceToHost, aux->stream)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(aux->stream)) != hipSuccess)
+    return hip_err(aux, e, "result read-back");
+  const int64_t *s1 = (const int64_t *)h;
+  const uint64_t *s2 = (const uint64_t *)(h + 8 * V);
+  r->s1.assign(s1, s1 + V);
+  r->s2_hi.resize(V);
+  r->s2_lo.resize(V);
+  for (size_t v = 0; v < V; ++v) {
+    r->s2_lo[v] = s2[2 * v];
+    r->s2_hi[v] = s2[2 * v + 1];
+  }
+  return CTD_OK;
+}
+
+// Upload a registered phantom through the pinned and device staging buffers
+// (mat at 0, rho at the next 256-byte boundary) and pack it.  No lock.
+static int load_phantom(ctd_server *sv, const PhantomEntry &e, int64_t max_voxels,
+                        ctd_phantom **out) {
+  ctd_ctx *aux = sv->aux;
+  const size_t V = e.mat.size();
+  const size_t Vm = std::max<size_t>(V, (size_t)max_voxels);
+  const size_t off = (V + 255) & ~(size_t)255;
+  const size_t bytes = off + 4 * V;
+  hipError_t err = sv->up_host.reserve(((Vm + 255) & ~(size_t)255) + 4 * Vm);
+  if (err == hipSuccess) err = sv->up_dev.reserve(((Vm + 255) & ~(size_t)255) + 4 * Vm);
+  if (err != hipSuccess) return hip_err(aux, err, "phantom staging");
+  char *h = (char *)sv->up_host.p;
+  char *d = (char *)sv->up_dev.p;
+  std::memcpy(h, e.mat.data(), V);
+  std::memcpy(h + off, e.rho.data(), 4 * V);
+  if ((err = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, aux->stream)) != hipSuccess)
+    return hip_err(aux, err, "phantom upload");
+  // packing runs behind the copy on the same stream and is waited for
+  return ctd_phantom_load(aux, &e.g, (const uint8_t *)d, (const float *)(d + off),
+                          CTD_MEM_DEVICE, out);
+}
+
+// Admit the request at the head of the queue if it fits (evicting unused
+// resident phantoms, least recently used first, never its own).  Entered and
+// left with the lock held; the device work runs unlocked.  Returns false
+// when the request must wait for memory.
+static bool admit_one(ctd_server *sv, std::unique_lock<std::mutex> &lk) {
+  Request *r = sv->queue.front();
+  PhantomEntry &e = sv->phantoms.find(r->phantom_key)->second;
+  const int64_t V = (int64_t)e.g.nx * e.g.ny * e.g.nz;
+  const int copies = sv->cfg.tuning.block && sv->cfg.tuning.tally_mode != 0 ? kTallyCopies : 1;
+  const uint64_t case_bytes = case_footprint(e.g, r->geo, r->p, r->ms->eg.ne, copies,
+                                             sv->cfg.batch_histories);
+  // records, plus a palette index or the bound grids (1, 2, 4-voxel blocks)
+  const uint64_t ph_bytes =
+      e.dev ? 0 : (uint64_t)V * 9 + (uint64_t)V / 8 + (uint64_t)V / 64 + 8192;
+  const uint64_t need = case_bytes + ph_bytes;
+  if (need > sv->cfg.hbm_budget_bytes) {  // can never fit
+    sv->queue.pop_front();
+    complete(sv, r, 4, CTD_ENOMEM);
+    return true;
+  }
+  std::vector<ctd_phantom *> evict;
+  uint64_t evict_bytes = 0;
+  for (;;) {
+    if (sv->used_bytes - evict_bytes + need <= sv->cfg.hbm_budget_bytes) break;
+    PhantomEntry *victim = nullptr;
+    for (auto &kv : sv->phantoms) {
+      PhantomEntry &x = kv.second;
+      if (&x != &e && x.dev && x.users == 0 &&
+          std::find(evict.begin(), evict.end(), x.dev) == evict.end() &&
+          (!victim || x.last_use < victim->last_use))
+        victim = &x;
     }
-    // requests whose plan is complete: sigma-bar, then stop or plan more
-    std::vector<std::pair<Request *, double>> checked;
-    if (rc == CTD_OK) {
-      for (Request *r : sv->active) {
-        if (r->cs->batches < r->planned) continue;
-        double sig = INFINITY;
-        int rs = sigma_now(sv->ctx, r->cs, sv->cfg.sigma_kind, sv->cfg.dose_frac, &sig);
-        checked.push_back({r, rs == CTD_OK ? sig : NAN});
-      }
+    if (!victim) return false;   // wait for running requests to finish
+    evict.push_back(victim->dev);
+    evict_bytes += victim->dev_bytes;
+  }
+  for (auto &kv : sv->phantoms) {
+    PhantomEntry &x = kv.second;
+    if (x.dev && std::find(evict.begin(), evict.end(), x.dev) != evict.end()) {
+      x.dev = nullptr;
+      x.dev_bytes = 0;
+      sv->stats.evictions++;
     }
-    lk.lock();
-    for (Request *r : reqs) {
-      r->histories = r->cs->h_next;
-      r->batches = r->cs->batches;
+  }
+  sv->used_bytes = sv->used_bytes - evict_bytes + need;   // reserved while unlocked
+  sv->queue.pop_front();
+  ctd_phantom *ph = e.dev;
+  const bool load = ph == nullptr;
+  const int64_t max_voxels = sv->max_voxels;
+  lk.unlock();
+
+  for (ctd_phantom *x : evict) ctd_phantom_release(sv->aux, x);
+  int rc = CTD_OK;
+  if (load) rc = load_phantom(sv, e, max_voxels, &ph);
+  ctd_case *cs = nullptr;
+  if (rc == CTD_OK) rc = ctd_case_create(sv->aux, ph, r->ms, r->sp, r->geo, &r->p, &cs);
+  if (rc == CTD_OK && sv->cfg.tuning.block) rc = ctd_set_tuning(sv->aux, cs, &sv->cfg.tuning);
+  if (rc == CTD_OK && cs->d_mh_state) rc = ensure_mh_buffer(sv->aux, cs, sv->cfg.batch_histories);
+  if (rc != CTD_OK && cs) {
+    ctd_case_destroy(sv->aux, cs);
+    cs = nullptr;
+  }
+  std::string msg = rc != CTD_OK ? ctd_last_error(sv->aux) : std::string();
+
+  lk.lock();
+  if (load) {
+    if (ph) {   // loaded (the case may still have failed)
+      e.dev = ph;
+      e.dev_bytes = ph_bytes;
+      sv->stats.phantom_loads++;
+    } else {
+      sv->used_bytes -= ph_bytes;
     }
-    sv->stats.rounds++;
-    sv->stats.histories += (uint64_t)cases.size() * bh;
-    if (rc != CTD_OK) {
-      sv->err = ctd_last_error(sv->ctx);
-      for (Request *r : reqs) {
-        sv->active.erase(std::find(sv->active.begin(), sv->active.end(), r));
-        finish(sv, r, 4, rc);
-      }
-      sv->cv_done.notify_all();
+  } else {
+    sv->stats.phantom_hits++;
+  }
+  sv->free_epoch++;   // the evictions
+  if (rc != CTD_OK) {
+    sv->used_bytes -= case_bytes;
+    sv->err = msg;
+    complete(sv, r, 4, rc);
+    return true;
+  }
+  e.users++;
+  e.last_use = ++sv->use_clock;
+  r->cs = cs;
+  r->footprint = case_bytes;
+  r->planned = std::min<uint64_t>((uint64_t)r->p.n_batches,
+                                  std::max<uint64_t>(sv->cfg.max_histories /
+                                                     sv->cfg.batch_histories, 2));
+  r->state = 1;
+  r->t_admit = sv->now();
+  sv->ready.push_back(r);
+  sv->cv_run.notify_all();
+  return true;
+}
+
+static void worker_loop(ctd_server *sv) {
+  (void)hipSetDevice(sv->aux->device);
+  uint64_t blocked_at = ~0ull;   // free_epoch when the head request last did not fit
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    if (!sv->readback.empty()) {
+      Request *r = sv->readback.front();
+      sv->readback.pop_front();
+      const int64_t max_voxels = sv->max_voxels;
+      lk.unlock();
+      const int rc = read_back(sv, r, max_voxels);
+      std::string msg = rc != CTD_OK ? ctd_last_error(sv->aux) : std::string();
+      lk.lock();
+      if (rc != CTD_OK) sv->err = msg;
+      retire_later(sv, r, rc == CTD_OK ? 2 : 4, rc);
       continue;
     }
-    for (auto &c : checked) {
-      Request *r = c.first;
-      r->sigma = c.second;
-      r->histories = r->cs->h_next;
-      r->batches = r->cs->batches;
-      const uint64_t more = std::isnan(c.second) ? 0 : sigma_plan(r->cs->batches, c.second,
-                                                                   r->target, max_b);
-      if (more == 0) {
-        sv->active.erase(std::find(sv->active.begin(), sv->active.end(), r));
-        finish(sv, r, std::isnan(c.second) ? 4 : 2, std::isnan(c.second) ? CTD_EDEVICE : CTD_OK);
+    for (size_t i = 0; i < sv->queue.size();) {   // cancelled while queued
+      Request *r = sv->queue[i];
+      if (r->cancel) {
+        sv->queue.erase(sv->queue.begin() + (long)i);
+        complete(sv, r, 3, CTD_ECANCELLED);
       } else {
-        r->planned = r->cs->batches + more;
+        ++i;
       }
     }
-    sv->cv_done.notify_all();
+    if (sv->stop) {
+      if (sv->runner_quiet) break;
+      sv->cv_host.wait(lk);
+      continue;
+    }
+    const bool slot_free =
+        (int)(sv->ready.size() + sv->active.size()) < sv->cfg.max_active;
+    if (sv->queue.empty() || !slot_free || blocked_at == sv->free_epoch) {
+      sv->cv_host.wait(lk);
+      continue;
+    }
+    if (!admit_one(sv, lk)) blocked_at = sv->free_epoch;
   }
+  sv->worker_done = true;
+  sv->cv_run.notify_all();
 }
 
 // ------------------------------------------------------------------- C ABI
@@ -324,15 +543,28 @@ extern "C" int32_t ctd_server_start(int32_t device, const ctd_server_config *cfg
   ctd_server *sv = new (std::nothrow) ctd_server();
   if (!sv) return CTD_ENOMEM;
   int rc = ctd_create(&sv->ctx, device);
+  if (rc == CTD_OK) rc = ctd_create(&sv->aux, device);
   if (rc != CTD_OK) {
+    if (sv->ctx) ctd_destroy(sv->ctx);
     delete sv;
     return rc;
   }
   sv->cfg = *cfg;
   sv->t0 = std::chrono::steady_clock::now();
   try {
-    sv->th = std::thread(server_loop, sv);
+    sv->worker = std::thread(worker_loop, sv);
+    sv->runner = std::thread(runner_loop, sv);
   } catch (...) {
+    if (sv->worker.joinable()) {
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->runner_quiet = true;   // no runner: nothing will reach the read-back list
+        sv->wake();
+      }
+      sv->worker.join();
+    }
+    ctd_destroy(sv->aux);
     ctd_destroy(sv->ctx);
     delete sv;
     return CTD_ENOMEM;
@@ -368,6 +600,7 @@ extern "C" int32_t ctd_server_add_phantom(ctd_server *sv, uint64_t key, const ct
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->phantoms.count(key)) return sv_err(sv, CTD_EBUSY, "phantom key already registered");
   sv->phantoms.emplace(key, std::move(e));
+  sv->max_voxels = std::max(sv->max_voxels, V);
   return CTD_OK;
 }
 
@@ -397,7 +630,7 @@ extern "C" int32_t ctd_server_submit(ctd_server *sv, uint64_t phantom_key, ctd_m
   sv->queue.push_back(r.get());
   sv->all.emplace(r->ticket, std::move(r));
   sv->stats.submitted++;
-  sv->cv_work.notify_all();
+  sv->cv_host.notify_all();
   return CTD_OK;
 }
 
@@ -445,7 +678,7 @@ extern "C" int32_t ctd_server_cancel(ctd_server *sv, uint64_t ticket) {
   auto it = sv->all.find(ticket);
   if (it == sv->all.end()) return CTD_ENOTFOUND;
   it->second->cancel = true;
-  sv->cv_work.notify_all();
+  sv->wake();
   return CTD_OK;
 }
 
@@ -485,7 +718,9 @@ extern "C" int32_t ctd_server_read_stats(ctd_server *sv, ctd_server_stats *out) 
   std::lock_guard<std::mutex> lk(sv->mu);
   *out = sv->stats;
   out->queued = (uint32_t)sv->queue.size();
-  out->active = (uint32_t)sv->active.size();
+  // admitted and not yet finished: joining, in the rounds, being read back or freed
+  out->active = (uint32_t)(sv->ready.size() + sv->active.size() + sv->readback.size() +
+                           sv->retire.size());
   out->resident_bytes = sv->used_bytes;
   return CTD_OK;
 }
@@ -496,17 +731,25 @@ extern "C" int32_t ctd_server_stop(ctd_server *sv) {
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->stop = true;
     for (Request *r : sv->queue) r->cancel = true;
-    sv->cv_work.notify_all();
+    sv->wake();
   }
-  if (sv->th.joinable()) sv->th.join();
+  // the runner finishes its iteration and cancels the admitted requests; the
+  // worker copies out what had already reached its sigma-bar target
+  if (sv->worker.joinable()) sv->worker.join();
+  if (sv->runner.joinable()) sv->runner.join();
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    for (Request *r : sv->queue) finish(sv, r, 3, CTD_ECANCELLED);
+    for (Request *r : sv->queue) complete(sv, r, 3, CTD_ECANCELLED);
     sv->queue.clear();
     for (auto &kv : sv->phantoms)
-      if (kv.second.dev) ctd_phantom_release(sv->ctx, kv.second.dev);
+      if (kv.second.dev) ctd_phantom_release(sv->aux, kv.second.dev);
     sv->cv_done.notify_all();
   }
+  sv->sig_host.release();
+  sv->up_host.release();
+  sv->up_dev.release();
+  sv->rb_host.release();
+  ctd_destroy(sv->aux);
   ctd_destroy(sv->ctx);
   delete sv;
   return CTD_OK;

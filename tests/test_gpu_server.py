@@ -109,8 +109,11 @@ def test_server_admission_budget_and_resident_phantoms(ctx):
     say("server admission")
     wls = _requests(3, seed=5)
     V = max(wl.n_voxels for wl in wls)
-    # room for about one request (tallies 32 B/voxel + phantom 9 B/voxel)
-    sv = L.ctd_server_start(0, _cfg(budget=V * 41 + (4 << 20)))
+    # room for one request on the largest phantom (tallies 32 B/voxel +
+    # phantom 9 B/voxel) and little more: the third request on phantom 0
+    # must evict an unused phantom to fit.  Evictions happen only when they
+    # make enough room for the admission.
+    sv = L.ctd_server_start(0, _cfg(budget=V * 41 + (256 << 10)))
     inputs = [Inputs(ctx, wl) for wl in wls]
     try:
         for i, wl in enumerate(wls):
