@@ -235,6 +235,7 @@ static int build_bound_grids(ctd_ctx *ctx, ctd_phantom *ph) {
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   ph->nclass = c;
+  ph->bclass_host.assign(cls.begin(), cls.begin() + c);
   return CTD_OK;
 }
 
@@ -601,6 +602,53 @@ int ctd::upload_desc(ctd_ctx *ctx, ctd_case *cs) {
   return CTD_OK;
 }
 
+// Bound-test sums (CaseDev::bnd): for material m and energy cell j the sum
+// over the processes of the largest value the column's linear interpolation
+// takes in the cell, rounded up to float with a relative margin of 2^-20.
+// Inside the grid the weight w = f - j lies in [0, 1) exactly, and the float
+// interpolation fma(w, x1 - x0, x0) stays within (1 + u)^2 of the larger node
+// (u = 2^-24); the selection's sums of the rho-scaled terms add at most
+// (1 + u)^3.  So a class level rho_c times this sum, rounded, is at or above
+// the selection's sum at rho_c, hence at every density of the block (float
+// rounding is monotone).  In the top cell (E up to the last node) the
+// rounding of f = (E - e0) / dE can put w a little past 1 (by at most about
+// 3u (ne - 1)); there the column is extended to w = 1 + 4u ne.
+static std::vector<float> bound_sums(const ctd_matset *ms, bool rayleigh) {
+  const int ne = ms->eg.ne;
+  std::vector<float> out((size_t)ms->M * (size_t)(ne - 1));
+  const double w_top = 1.0 + 4.0 * 0x1p-24 * ne;
+  for (int m = 0; m < ms->M; ++m) {
+    const float *r = ms->mu_rho.data() + (size_t)m * ne * 3;
+    for (int j = 0; j + 1 < ne; ++j) {
+      const float *x0 = r + (size_t)j * 3, *x1 = x0 + 3;
+      const double w = j + 2 == ne ? w_top : 1.0;
+      auto peak = [&](int k) {   // largest value of the column over the cell
+        return std::max((double)x0[k], (double)x0[k] + w * ((double)x1[k] - (double)x0[k]));
+      };
+      double sum = peak(0) + peak(1);
+      if (rayleigh) sum += peak(2);
+      out[(size_t)m * (ne - 1) + j] = round_up_to_float(sum * (1.0 + 0x1p-20));
+    }
+  }
+  return out;
+}
+
+// The bound test of a case is exact while every class level times its
+// material's bound-test sum stays a normal float: only absurdly small
+// densities and cross sections would leave that range.
+static bool bound_test_in_range(const ctd_phantom *ph, const std::vector<float> &bnd, int ne) {
+  for (const uint2 &c : ph->bclass_host) {
+    float rho;
+    std::memcpy(&rho, &c.x, 4);
+    if (rho == 0.0f) continue;
+    for (int j = 0; j + 1 < ne; ++j) {
+      const double v = (double)rho * bnd[(size_t)c.y * (ne - 1) + j];
+      if (v != 0.0 && v < 0x1p-100) return false;
+    }
+  }
+  return true;
+}
+
 extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms,
                                    ctd_spectrum *sp, ctd_geometry *geo, const ctd_params *p,
                                    ctd_case **out) {
@@ -681,6 +729,14 @@ extern "C" int32_t ctd_case_create(ctd_ctx *ctx, ctd_phantom *ph, ctd_matset *ms
       (e = hipMalloc(&cs->d_mu_max, 4 * eg.ne)) != hipSuccess ||
       (e = hipMalloc(&cs->d_bin_lo, 4 * blo.size())) != hipSuccess)
     return cleanup(hip_err(ctx, e, "case alloc"));
+  {
+    const std::vector<float> bnd = bound_sums(ms, p->rayleigh != 0);
+    cs->use_bound_grid = ph->nclass > 0 && bound_test_in_range(ph, bnd, eg.ne);
+    if ((e = hipMalloc(&cs->d_bnd, 4 * bnd.size())) != hipSuccess ||
+        (e = hipMemcpy(cs->d_bnd, bnd.data(), 4 * bnd.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+      return cleanup(hip_err(ctx, e, "bound-test sums"));
+  }
   if (!geo->proj_sc.empty() &&
       (e = hipMalloc(&cs->d_proj, sizeof(float4) * geo->proj_sc.size())) != hipSuccess)
     return cleanup(hip_err(ctx, e, "case alloc"));
@@ -747,7 +803,8 @@ void ctd::fill_desc(ctd_case *cs) {
   d.palette = cs->ph->palette;
   d.npal = cs->ph->npal;
   for (int s = 0; s < 3; ++s) d.bgrid[s] = cs->ph->bgrid[s];
-  d.bclass = cs->ph->nclass > 0 ? cs->ph->bclass : nullptr;
+  d.bclass = cs->use_bound_grid ? cs->ph->bclass : nullptr;
+  d.bnd = cs->d_bnd;
   const ctd_matset *ms = cs->ms;
   d.ne = ms->eg.ne;
   d.nzc = ms->nzc;
@@ -833,6 +890,7 @@ void ctd::free_case_buffers(ctd_case *cs) {
   dfree(cs->d_mh_state);
   dfree(cs->d_mh_beam);
   dfree(cs->d_mc_f);
+  dfree(cs->d_bnd);
   dfree(cs->d_log);
   dfree(cs->d_log_n);
   for (auto &t : cs->timing) {
@@ -939,7 +997,7 @@ uint64_t ctd::case_footprint(const ctd_grid &g, const ctd_geometry *geo, const c
                              int ne, int tally_copies, uint64_t round_histories) {
   const uint64_t V = (uint64_t)g.nx * g.ny * g.nz;
   uint64_t b = V * (24 + 8 * (uint64_t)tally_copies) + 8 * kAccWords + sizeof(CaseDev) +
-               sizeof(float4) * geo->proj_sc.size() + 65536;
+               sizeof(float4) * geo->proj_sc.size() + 65536 + 4 * 256 * (uint64_t)ne;
   if (p.tracking != CTD_TRACK_GLOBAL) {  // MACRO, or AUTO that may choose it
     int n[3];
     const uint64_t cells = (uint64_t)macro_cells(g, macro_edge(g, p.macro_cell), n);
@@ -1008,8 +1066,10 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
     poff[i] = bytes;
     bytes += 8 * (items[i].prefix.size());
   }
+  // one chunk counter per case
   const size_t ctr_off = (bytes + 255) & ~(size_t)255;
-  bytes = ctr_off + 256;
+  const size_t ctr_bytes = (8 * (size_t)nrc + 255) & ~(size_t)255;
+  bytes = ctr_off + ctr_bytes;
   ctd_ctx::Slot &s = ctx->slots[ctx->next_slot];
   ctx->next_slot = (ctx->next_slot + 1) % ctx->slots.size();
   if (s.ev) HIPCHK(ctx, hipEventSynchronize(s.ev));
@@ -1028,6 +1088,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
   char *h = (char *)s.host;
   char *d = (char *)s.dev;
   RoundCase *rc = (RoundCase *)h;
+  LaunchCfg cfg = launch_cfg(ctx, t);
   uint64_t chunks = 0;
   for (int i = 0; i < nrc; ++i) {
     rc[i].cd = items[i].cd;
@@ -1039,12 +1100,14 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
     chunks += (items[i].n + (uint64_t)t.chunk - 1) / (uint64_t)t.chunk;
     std::memcpy(h + poff[i], items[i].prefix.data(), 8 * items[i].prefix.size());
   }
-  std::memset(h + ctr_off, 0, 256);
+  home_round_cases(rc, nrc, chunks, cfg.grid, cfg.block / 64);
+  std::memset(h + ctr_off, 0, ctr_bytes);
   HIPCHK(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
-  LaunchCfg cfg = launch_cfg(ctx, t);
-  if (nrc == 1) {   // a single case's tables may be staged in LDS
-    cfg.tab_n = items[0].tab_n;
-    cfg.tab_ne = items[0].tab_ne;
+  // LDS room for the largest case's tables: each workgroup stages the
+  // tables of the case it works on
+  for (const RoundItem &it : items) {
+    cfg.tab_n = std::max(cfg.tab_n, it.tab_n);
+    cfg.tab_ne = std::max(cfg.tab_ne, it.tab_ne);
   }
   if (chunks > 0 &&
       launch_transport((const RoundCase *)d, nrc, chunks, (unsigned long long *)(d + ctr_off),
@@ -1351,6 +1414,7 @@ extern "C" int32_t ctd_run_batches_static(ctd_ctx *ctx, ctd_case *cs, uint64_t b
   LaunchCfg cfg = launch_cfg(ctx, t);
   cfg.tab_n = cs->ms->M * cs->ms->eg.ne;
   cfg.tab_ne = cs->ms->eg.ne;
+  a.home_waves = (uint32_t)cfg.grid * (uint32_t)(cfg.block / 64);
   const uint64_t chunks = (batch_histories + (uint64_t)t.chunk - 1) / (uint64_t)t.chunk;
   unsigned char *table = (unsigned char *)ctx->static_table;
   const bool with_log = cs->log_cap > 0;

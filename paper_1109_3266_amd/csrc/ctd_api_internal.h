@@ -66,6 +66,7 @@ struct ctd_phantom {
   uint2 *bclass = nullptr;
   int2 *bclass_range = nullptr;
   int nclass = 0;
+  std::vector<uint2> bclass_host;   // host copy of the class table
   double rho_max[256] = {};
   double rho_min[256] = {};
   bool present[256] = {};
@@ -123,6 +124,8 @@ struct ctd_case {
   int32_t *d_mh_beam = nullptr;    // Alg. A1: beamlets of the current round
   uint64_t mh_cap = 0;
   float *d_mc_f = nullptr;         // MACRO tracking: majorant factors [n_band][cells]
+  float *d_bnd = nullptr;          // bound-test sums per material and energy cell
+  bool use_bound_grid = false;     // the phantom's bound grid serves this case
   int mc_cs = 0, mc_n[3] = {0, 0, 0}, mc_classes = 0, mc_shift = 0, mc_bands = 0;
   unsigned long long *d_tally = nullptr;
   int tally_copies = 1;     // 1, or kTallyCopies once tally_mode 1 is selected

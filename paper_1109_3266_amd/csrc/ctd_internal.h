@@ -4,6 +4,8 @@
 // each participating case, one batch of histories, consumed in chunks.
 #pragma once
 
+#include <algorithm>
+
 #include <stddef.h>
 #include <stdint.h>
 
@@ -103,6 +105,11 @@ struct CaseDev {
   // voxel's own (float rounding is monotone).  Null where not built.
   const uint8_t *bgrid[3];
   const uint2 *bclass;
+  // per material and energy cell j ([E_j, E_j+1]): a float at or above the
+  // interaction sum (photoelectric + Compton, + Rayleigh when on) that the
+  // selection forms anywhere in the cell, so rho_c * bnd bounds the selection
+  // at class level rho_c without the table rows  [nmat][ne - 1]
+  const float *bnd;
   // random stream key
   uint32_t key0, key1;
   // tallies
@@ -124,7 +131,31 @@ struct RoundCase {
   const unsigned long long *prefix;
   uint64_t h_begin, n, chunk_begin;
   const int32_t *beamlets;     // [n] Alg. A1 beamlet per history, or null
+  // the case's home workgroups [wg_lo, next case's wg_lo) of the launch's
+  // grid (home_round_cases); home_waves = their waves, which take the case's
+  // first chunks by rank
+  uint32_t wg_lo, home_waves;
 };
+
+// Fill wg_lo and home_waves of a round's cases for a grid of `grid`
+// workgroups of `waves` waves (chunk_begin already set).  Workgroup g's home
+// is the case holding chunk g * waves of the round, so the grid starts on
+// the first chunks in case order, as one wave per chunk would, and moves on
+// through the cases in order: the cases in flight at any time stay few, and
+// their phantoms and tallies stay in cache.
+inline void home_round_cases(RoundCase *rc, int nrc, uint64_t total_chunks, int grid,
+                             int waves) {
+  (void)total_chunks;
+  auto first_wg = [&](uint64_t chunk) {  // first g with g * waves >= chunk, at most grid
+    const uint64_t g = (chunk + (uint64_t)waves - 1) / (uint64_t)waves;
+    return (uint32_t)std::min<uint64_t>(g, (uint64_t)grid);
+  };
+  for (int i = 0; i < nrc; ++i) {
+    rc[i].wg_lo = first_wg(rc[i].chunk_begin);
+    const uint32_t hi = i + 1 < nrc ? first_wg(rc[i + 1].chunk_begin) : (uint32_t)grid;
+    rc[i].home_waves = (hi - rc[i].wg_lo) * (uint32_t)waves;
+  }
+}
 
 // Entry point that allocates nothing (ctd_run_batches_static): the launch
 // table of one single-case round -- the RoundCase, the spectrum's bin prefix
@@ -143,7 +174,8 @@ struct StaticRoundArgs {
   const CaseDev *cd;
   uint64_t h_begin, n;
   const int32_t *beamlets;
-  int32_t nbins, pad;
+  int32_t nbins;
+  uint32_t home_waves;   // every wave of the grid: the one case is everyone's home
   unsigned long long prefix[kStaticMaxBins + 1];
 };
 

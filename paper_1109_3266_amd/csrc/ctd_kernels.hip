@@ -49,15 +49,18 @@ constexpr int kCacheBits = 9;
 constexpr int kCacheSlots = 1 << kCacheBits;
 constexpr int kCacheBytesPerWave = kCacheSlots * (8 + 4);
 
-// Dynamic LDS of a transport workgroup, in this order: one slot of
-// kWaveLdsBytes per wave (its event counters, its copy of the case
-// descriptor, its 256-entry palette or bound-class table); in tally mode 2,
-// each wave's sub-tally; in a single-case launch whose tables fit, the
-// case's majorant nodes (padded to 16 B) and mu/rho rows, shared by the
-// workgroup.
+// Dynamic LDS of a transport workgroup, in this order: a 16-byte header
+// (the workgroup's next case); the descriptor of the case the workgroup works
+// on and its 256-entry palette or bound-class table (every wave of a
+// workgroup works on the same case); per wave, its event counters; in tally
+// mode 2, each wave's sub-tally; where the tables fit, the case's majorant
+// nodes (padded to 16 B) and mu/rho rows.
 constexpr int kWaveAccBytes = (ACC_COUNT * 8 + 15) & ~15;
 constexpr int kWaveCaseBytes = ((int)sizeof(CaseDev) + 15) & ~15;
-constexpr int kWaveLdsBytes = kWaveAccBytes + kWaveCaseBytes + 256 * 8;
+constexpr int kWgHeaderBytes = 16;
+constexpr int kWgCaseOff = kWgHeaderBytes;
+constexpr int kWgPalOff = kWgCaseOff + kWaveCaseBytes;
+constexpr int kWgSlotsOff = kWgPalOff + 256 * 8;
 
 // a ^ b ^ c in one instruction (gfx950 three-input bitwise op, truth table 0x96)
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
@@ -133,6 +136,9 @@ struct StepCase {
   // mu_max through the caches)
   const LOCAL float4 *tab;
   const LOCAL float *tabmax;
+  const LOCAL float *tabbnd;
+  // bound-test sums per material and energy cell (CaseDev::bnd)
+  const GLOBAL float *bnd;
   GLOBAL unsigned long long *tally;
   float fnx, fny, fnz, inv_dx, inv_dy, inv_dz, e0, inv_de;
   int32_t nx, ny, ne, rayleigh, npal;
@@ -186,6 +192,8 @@ __device__ __forceinline__ StepCase make_step_case(const CaseDev &c, int tally_m
   s.mu_rho = uniform_ptr(c.mu_rho);
   s.tab = nullptr;
   s.tabmax = nullptr;
+  s.tabbnd = nullptr;
+  s.bnd = uniform_ptr(c.bnd);
   s.mu_max = uniform_ptr(c.mu_max);
   s.tally = uniform_ptr(c.tally);
   if (tally_mode) s.tally += (size_t)xcc_id() * (size_t)uniform_i((int32_t)c.V);
@@ -305,6 +313,14 @@ __device__ __forceinline__ void table_rows(const StepCase &S, uint32_t ti, float
     t0 = S.mu_rho[ti];
     t1 = S.mu_rho[ti + 1];
   }
+}
+
+// Bound-test sum of material m in energy cell j (CaseDev::bnd).
+template <bool TAB>
+__device__ __forceinline__ float bound_sum(const StepCase &S, uint32_t m, int j) {
+  const uint32_t i = __umul24(m, (uint32_t)(S.ne - 1)) + (uint32_t)j;
+  if constexpr (TAB) return S.tabbnd[i];
+  else return S.bnd[i];
 }
 
 template <bool TAB>
@@ -610,15 +626,13 @@ __device__ __forceinline__ bool interact_bounded(Photon &p, const StepCase &S, c
   const uint2 ce = cls_tab[cls];
   const uint32_t m = ce.y;
   const float rho_c = __uint_as_float(ce.x);
+  const float xi = unif(r.y) * p.mumax;
+  if (xi >= rho_c * bound_sum<TAB>(S, m, p.je)) return true;
   const uint32_t ti = __umul24(m, (uint32_t)S.ne) + (uint32_t)p.je;
   float4 t0, t1;
   table_rows<TAB>(S, ti, t0, t1);
   const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
   const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
-  const float xi = unif(r.y) * p.mumax;
-  float bound = rho_c * a + rho_c * b;
-  if (S.rayleigh) bound = bound + rho_c * cr;
-  if (xi >= bound) return true;
   const float rho = __uint_as_float(S.vox[vox].x);
   return collide<LOG, TAB>(p, S, G, c, r, k, vox, m, rho, a, b, cr, xi);
 }
@@ -701,14 +715,7 @@ __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const Cas
   if (cls != kMixedClass) {
     const uint2 ce = cls_tab[cls];
     const float rho_c = __uint_as_float(ce.x);
-    const uint32_t ti = __umul24(ce.y, (uint32_t)S.ne) + (uint32_t)p.je;
-    float4 t0, t1;
-    table_rows<TAB>(S, ti, t0, t1);
-    const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
-    const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
-    float bound = rho_c * a + rho_c * b;
-    if (S.rayleigh) bound = bound + rho_c * cr;
-    if (unif(r.y) * p.mumax >= bound) return kStepOn;
+    if (unif(r.y) * p.mumax >= rho_c * bound_sum<TAB>(S, ce.y, p.je)) return kStepOn;
   }
   pvox = vox;
   return kStepPending;
@@ -828,16 +835,6 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
 
 // ------------------------------------------------------- transport kernel
 
-__device__ __forceinline__ int find_round_case(const RoundCase *__restrict__ rcs, int nrc,
-                                               uint64_t t) {
-  int lo = 0, hi = nrc - 1;
-  while (lo < hi) {  // last index with chunk_begin <= t
-    const int mid = (lo + hi + 1) >> 1;
-    if (rcs[mid].chunk_begin <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ int find_bin(const unsigned long long *__restrict__ prefix, int nbins,
                                         uint64_t local) {
   int lo = 0, hi = nbins - 1;
@@ -848,24 +845,39 @@ __device__ __forceinline__ int find_bin(const unsigned long long *__restrict__ p
   return lo;
 }
 
+// Chunks of round case c, reloaded from the launch table where needed
+// rather than kept live across the step loop.
+__device__ __forceinline__ uint64_t case_chunk_count(const RoundCase *__restrict__ rcs, int nrc,
+                                                     uint64_t total_chunks, int c) {
+  return (c + 1 < nrc ? rcs[c + 1].chunk_begin : total_chunks) - rcs[c].chunk_begin;
+}
+
+// The home case of workgroup g: the last case whose home workgroups start
+// at or before g.
+__device__ __forceinline__ int home_case(const RoundCase *__restrict__ rcs, int nrc, uint32_t g) {
+  int lo = 0, hi = nrc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rcs[mid].wg_lo <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 static_assert(sizeof(CaseDev) % 4 == 0 && sizeof(CaseDev) <= 512, "CaseDev copy size");
 
 // Copy a case descriptor (and its voxel palette, or else its bound-grid class
-// table, if any) into the wave's LDS slots (lanes copy words).
-__device__ __forceinline__ void stage_case(CaseDev *dst, uint2 *pal, const CaseDev *src,
-                                           int lane) {
+// table, if any) into the workgroup's LDS (threads copy words; the caller's
+// barrier publishes them).
+__device__ __forceinline__ void stage_case(CaseDev *dst, uint2 *pal, const CaseDev *src) {
   const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
   uint32_t *d = reinterpret_cast<uint32_t *>(dst);
-  for (int i = lane; i < (int)(sizeof(CaseDev) / 4); i += 64) d[i] = s[i];
+  for (int i = threadIdx.x; i < (int)(sizeof(CaseDev) / 4); i += blockDim.x) d[i] = s[i];
   const uint2 *sp = src->palette;
   const uint2 *sc = src->bclass;
   if (__builtin_amdgcn_readfirstlane(src->npal) > 0)
-    for (int i = lane; i < 256; i += 64) pal[i] = sp[i];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) pal[i] = sp[i];
   else if (sc)
-    for (int i = lane; i < 256; i += 64) pal[i] = sc[i];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) pal[i] = sc[i];
 }
 
 // MACRO selects the macro-cell step for every case of the launch (a round
@@ -881,40 +893,29 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
                                                    unsigned long long *chunk_ctr, int refill_min,
                                                    int chunk, int tally_mode, int bound_shift,
                                                    int defer_min, int tab_n, int tab_ne) {
-  extern __shared__ unsigned long long dyn_lds[];   // layout: see kWaveLdsBytes
+  extern __shared__ unsigned long long dyn_lds[];   // layout: see kWgSlotsOff
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  unsigned char *slot = (unsigned char *)dyn_lds + w * kWaveLdsBytes;
-  CaseDev &G = *(CaseDev *)(slot + kWaveAccBytes);
-  uint2 *pal = (uint2 *)(slot + kWaveAccBytes + kWaveCaseBytes);
+  unsigned char *base = (unsigned char *)dyn_lds;
+  int *wg_next = (int *)base;   // the workgroup's next case (header word)
+  CaseDev &G = *(CaseDev *)(base + kWgCaseOff);
+  uint2 *pal = (uint2 *)(base + kWgPalOff);
   const LOCAL uint2 *pal_lds = (const LOCAL uint2 *)pal;
-  unsigned char *after_slots = (unsigned char *)dyn_lds + nw * kWaveLdsBytes;
-  // single-case launch: the workgroup stages the case's majorant nodes and
-  // mu/rho rows once; every wave's step reads them from LDS
+  unsigned char *slot = base + kWgSlotsOff + w * kWaveAccBytes;
+  unsigned char *after_slots = base + kWgSlotsOff + nw * kWaveAccBytes;
+  // staged tables: the majorant nodes and mu/rho rows of the workgroup's
+  // current case and its bound-test sums, shared by its waves (room for the
+// round's largest case)
   LOCAL float *tabmax = nullptr;
   LOCAL float4 *tab = nullptr;
+  LOCAL float *tabbnd = nullptr;
   if (TAB) {
     tabmax = (LOCAL float *)(after_slots + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0));
     tab = (LOCAL float4 *)(tabmax + ((tab_ne + 3) & ~3));
-    const CaseDev *cd = rcs[0].cd;
-    const float4 *src = cd->mu_rho;
-    const float *srcm = cd->mu_max;
-    for (int i = threadIdx.x; i < tab_n; i += blockDim.x) tab[i] = src[i];
-    for (int i = threadIdx.x; i < tab_ne; i += blockDim.x) tabmax[i] = srcm[i];
-    __syncthreads();
+    tabbnd = (LOCAL float *)(tab + tab_n);
   }
-
-  // wave-uniform state
-  StepCase S;
-  int cur = -1;                         // round-case index of the wave's case
-  uint64_t pool_next = 0, pool_end = 0; // local history indices of `cur`
-  int wbin = 0;                         // bin of pool_next
-  int pend = -1;                        // claimed chunk of another case
-  uint64_t pend_lo = 0, pend_hi = 0;
-  bool queue_done = false;
-  uint32_t refills = 0;
 
   Counters cnt;
   cnt.s = (unsigned long long *)slot;
@@ -922,126 +923,153 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
   LOCAL unsigned char *cache =
       tally_mode == 2 ? (LOCAL unsigned char *)after_slots + w * kCacheBytesPerWave : nullptr;
   if (cache) clear_cache(cache, lane);
+
+  // Workgroup g starts on its home case (RoundCase::wg_lo: the case holding
+  // chunk g * waves of the round).  The home waves of a case take its first
+  // chunks by rank, with no atomic (the launch does not start with every
+  // wave queueing on one address); every later claim of case c is
+  // home_waves(c) + atomicAdd(counter c).  When a case has no chunk left,
+  // the workgroup's waves drain, and the workgroup moves on together to the
+  // next case (cyclically) that still has chunks, restaging its tables; it
+  // exits when none has.  Results do not depend on this order: each history
+  // is a function of its id, and the tallies are exact integer sums.
+  int c = home_case(rcs, nrc, blockIdx.x);
+  bool home = true;
+  StepCase S;
+  uint64_t pool_next = 0, pool_end = 0;  // local history indices of case c
+  int wbin = 0;                          // bin of pool_next
+  bool first = true, claims_done = false;
+  uint32_t refills = 0;
   Photon p;
   p.k = 0;
   bool alive = false;
   int32_t pvox = -1;   // deferred collisions: voxel of the lane's pending collision
-  const uint32_t first_chunk =
-      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (uint32_t)w);
-
   for (;;) {
-    const unsigned long long dead = __ballot(!alive);
-    const int ndead = __popcll(dead);
-    if (ndead == 64 || ndead >= refill_min) {
-      // counters of photons that left the box since the last refill step
-      if (!alive && (p.k & kGoneBit)) {
-        p.k &= ~kGoneBit;
-        escape<LOG>(p, G, cnt, p.k & kStepMask);
-      }
-      // switch to the pending case once the wave has drained
-      if (pend >= 0 && ndead == 64 && pool_next >= pool_end) {
-        if (cur >= 0) {
-          flush(cnt, G.acc, lane, refills);
-          flush_cache(S, lane);
+    if (TAB) {
+      const CaseDev *cd = rcs[c].cd;
+      const int n_rows = cd->nmat * cd->ne, n_e = cd->ne;
+      const float4 *src = cd->mu_rho;
+      const float *srcm = cd->mu_max;
+      for (int i = threadIdx.x; i < n_rows; i += blockDim.x) tab[i] = src[i];
+      for (int i = threadIdx.x; i < n_e; i += blockDim.x) tabmax[i] = srcm[i];
+      const float *srcb = cd->bnd;
+      const int n_b = cd->nmat * (n_e - 1);
+      for (int i = threadIdx.x; i < n_b; i += blockDim.x) tabbnd[i] = srcb[i];
+    }
+    stage_case(&G, pal, rcs[c].cd);
+    __syncthreads();   // case and tables staged before any wave steps
+    pool_next = pool_end = 0;
+    wbin = 0;
+    first = true;
+    claims_done = false;
+    refills = 0;
+
+    for (;;) {
+      const unsigned long long dead = __ballot(!alive);
+      const int ndead = __popcll(dead);
+      if (ndead == 64 || ndead >= refill_min) {
+        // counters of photons that left the box since the last refill step
+        if (!alive && (p.k & kGoneBit)) {
+          p.k &= ~kGoneBit;
+          escape<LOG>(p, G, cnt, p.k & kStepMask);
         }
-        refills = 0;
-        cur = pend;
-        pend = -1;
-        stage_case(&G, pal, rcs[cur].cd, lane);
-        S = make_step_case(G, tally_mode, bound_shift, cache);
-        S.tab = tab;
-        S.tabmax = tabmax;
-        pool_next = pend_lo;
-        pool_end = pend_hi;
-        wbin = find_bin(rcs[cur].prefix, G.nbins, pool_next);
-      }
-      // claim chunks until the pool has work or the queue is empty
-      while (pool_next >= pool_end && pend < 0 && !queue_done) {
-        // a wave's first chunk is its index in the grid (no counter atomic,
-        // so the launch does not start with every wave queueing on one
-        // address); the counter hands out the chunks after those
-        unsigned long long t = first_chunk;
-        if (cur >= 0) {
-          if (lane == 0) t = atomicAdd(chunk_ctr, 1ull);
-          t = lane0_u64(t) + (uint64_t)gridDim.x * (blockDim.x >> 6);
-        }
-        if (t >= total_chunks) {
-          queue_done = true;
-          break;
-        }
-        const int rc = find_round_case(rcs, nrc, t);
-        const uint64_t lo = (t - rcs[rc].chunk_begin) * (uint64_t)chunk;
-        const uint64_t hi = min(lo + (uint64_t)chunk, rcs[rc].n);
-        if (rc == cur || cur < 0 || ndead == 64) {
-          if (rc != cur) {
-            if (cur >= 0) {
-              flush(cnt, G.acc, lane, refills);
-              flush_cache(S, lane);
-            }
-            refills = 0;
-            cur = rc;
-            stage_case(&G, pal, rcs[cur].cd, lane);
-            S = make_step_case(G, tally_mode, bound_shift, cache);
-        S.tab = tab;
-        S.tabmax = tabmax;
-            wbin = find_bin(rcs[cur].prefix, G.nbins, lo);
+        // claim a chunk of case c when the pool is empty
+        while (pool_next >= pool_end && !claims_done) {
+          uint64_t t;
+          if (home && first) {
+            t = (uint64_t)__builtin_amdgcn_readfirstlane(
+                (blockIdx.x - rcs[c].wg_lo) * (uint32_t)nw + (uint32_t)w);
+          } else {
+            unsigned long long a = 0;
+            if (lane == 0) a = atomicAdd(chunk_ctr + c, 1ull);
+            t = rcs[c].home_waves + lane0_u64(a);
           }
+          if (t >= case_chunk_count(rcs, nrc, total_chunks, c)) {
+            claims_done = true;
+            break;
+          }
+          const uint64_t lo = t * (uint64_t)chunk;
+          const uint64_t hi = min(lo + (uint64_t)chunk, rcs[c].n);
+          // the wave's step constants at its first chunk; a wave's claims
+          // of one case increase, so later bin searches start from the last
+          if (first) {
+            S = make_step_case(G, tally_mode, bound_shift, cache);
+            S.tab = tab;
+            S.tabmax = tabmax;
+            S.tabbnd = tabbnd;
+            wbin = find_bin(rcs[c].prefix, G.nbins, lo);
+          }
+          first = false;
           pool_next = lo;
           pool_end = hi;
-        } else {
-          pend = rc;
-          pend_lo = lo;
-          pend_hi = hi;
+        }
+        // hand out pool ids to idle lanes, lowest lanes first
+        if (pool_next < pool_end && ndead > 0) {
+          const uint64_t avail = pool_end - pool_next;
+          const uint32_t m = (uint32_t)min((uint64_t)ndead, avail);
+          const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
+          const RoundCase &R = rcs[c];
+          if (!alive && rank < m) {
+            const uint64_t local = pool_next + rank;
+            int j = wbin;
+            while (j + 1 < G.nbins && local >= R.prefix[j + 1]) ++j;
+            alive = source<LOG, TAB>(p, S, G, R.h_begin + local, j, R.beamlets, local, cnt);
+          }
+          pool_next += m;
+          refills += 1;
+          if (pool_next < pool_end) {
+            while (wbin + 1 < G.nbins && pool_next >= R.prefix[wbin + 1]) ++wbin;
+          }
         }
       }
-      // hand out pool ids to idle lanes, lowest lanes first
-      if (pool_next < pool_end && ndead > 0) {
-        const RoundCase &R = rcs[cur];
-        const uint64_t avail = pool_end - pool_next;
-        const uint32_t m = (uint32_t)min((uint64_t)ndead, avail);
-        const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
-        if (!alive && rank < m) {
-          const uint64_t local = pool_next + rank;
-          int j = wbin;
-          while (j + 1 < G.nbins && local >= R.prefix[j + 1]) ++j;
-          alive = source<LOG, TAB>(p, S, G, R.h_begin + local, j, R.beamlets, local, cnt);
+      if (__ballot(alive) == 0ull) {
+        if (claims_done && pool_next >= pool_end) break;   // case c done for this wave
+        continue;
+      }
+      if constexpr (MACRO) {
+        if (alive) alive = step_macro<LOG, TAB>(p, S, G, pal_lds, cnt);
+      } else if (S.bgrid && defer_min > 0) {
+        // collision pass: the pending tentative collisions of the wave, once
+        // defer_min of them have gathered (or every live lane waits on one)
+        const unsigned long long pm = __ballot(alive && pvox >= 0);
+        if (pm && (__popcll(pm) >= defer_min || pm == __ballot(alive))) {
+          if (alive && pvox >= 0) {
+            const uint32_t k = p.k & kStepMask;
+            const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
+            alive = interact<LOG, TAB>(p, S, G, pal_lds, cnt, r, k, pvox, p.mumax);
+            pvox = -1;
+          }
         }
-        pool_next += m;
-        refills += 1;
-        if (pool_next < pool_end) {
-          while (wbin + 1 < G.nbins && pool_next >= R.prefix[wbin + 1]) ++wbin;
+        if (alive && pvox < 0) {
+          const int st = step_fast<LOG, TAB>(p, S, G, pal_lds, cnt, pvox);
+          alive = st <= kStepPending;
         }
+      } else if (alive) {
+        alive = step<LOG, TAB>(p, S, G, pal_lds, cnt);
       }
     }
-    if (__ballot(alive) == 0ull) {
-      if (queue_done && pend < 0 && pool_next >= pool_end) break;
-      continue;
+    if (!first) {   // the wave ran histories of case c
+      flush(cnt, G.acc, lane, refills);
+      flush_cache(S, lane);
     }
-    if constexpr (MACRO) {
-      if (alive) alive = step_macro<LOG, TAB>(p, S, G, pal_lds, cnt);
-    } else if (S.bgrid && defer_min > 0) {
-      // collision pass: the pending tentative collisions of the wave, once
-      // defer_min of them have gathered (or every live lane waits on one)
-      const unsigned long long pm = __ballot(alive && pvox >= 0);
-      if (pm && (__popcll(pm) >= defer_min || pm == __ballot(alive))) {
-        if (alive && pvox >= 0) {
-          const uint32_t k = p.k & kStepMask;
-          const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
-          alive = interact<LOG, TAB>(p, S, G, pal_lds, cnt, r, k, pvox, p.mumax);
-          pvox = -1;
-        }
+    // every wave of the workgroup has drained case c: pick the next case
+    // with chunks left, scanning cyclically from c + 1 (c itself last)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int nxt = -1;
+      for (int i = 1; i <= nrc && nxt < 0; ++i) {
+        const int d = c + i < nrc ? c + i : c + i - nrc;
+        const uint64_t taken =
+            rcs[d].home_waves +
+            __hip_atomic_load(chunk_ctr + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (taken < case_chunk_count(rcs, nrc, total_chunks, d)) nxt = d;
       }
-      if (alive && pvox < 0) {
-        const int st = step_fast<LOG, TAB>(p, S, G, pal_lds, cnt, pvox);
-        alive = st <= kStepPending;
-      }
-    } else if (alive) {
-      alive = step<LOG, TAB>(p, S, G, pal_lds, cnt);
+      *wg_next = nxt;
     }
-  }
-  if (cur >= 0) {
-    flush(cnt, G.acc, lane, refills);
-    flush_cache(S, lane);
+    __syncthreads();
+    c = __builtin_amdgcn_readfirstlane(*wg_next);   // uniform: scalar from here on
+    home = false;
+    if (c < 0) break;
   }
 }
 
@@ -1419,6 +1447,8 @@ __global__ void __launch_bounds__(256) k_static_round_setup(unsigned char *table
     rc->n = a.n;
     rc->chunk_begin = 0;
     rc->beamlets = a.beamlets;
+    rc->wg_lo = 0;
+    rc->home_waves = a.home_waves;
   }
 }
 
@@ -1442,9 +1472,10 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
                      bool macro, void *stream) {
   hipStream_t s = (hipStream_t)stream;
-  // stage the tables only where the workgroup's LDS then still allows the
-  // resident workgroups the grid is sized for
-  int tab_n = nrc == 1 ? cfg.tab_n : 0;
+  // stage the tables (room for the round's largest case) only where the
+  // workgroup's LDS then still allows the resident workgroups the grid is
+  // sized for
+  int tab_n = cfg.tab_n;
   size_t lds = transport_lds_bytes(cfg.block, cfg.tally_mode, 0, 0);
   if (tab_n > 0) {
     const size_t with = transport_lds_bytes(cfg.block, cfg.tally_mode, tab_n, cfg.tab_ne);
@@ -1466,8 +1497,9 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
 
 size_t transport_lds_bytes(int block, int tally_mode, int tab_n, int tab_ne) {
   const size_t nw = (size_t)(block / 64);
-  size_t b = nw * kWaveLdsBytes + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0);
-  if (tab_n > 0) b += (size_t)((tab_ne + 3) & ~3) * 4 + (size_t)tab_n * 16;
+  size_t b = kWgSlotsOff + nw * kWaveAccBytes + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0);
+  // majorant nodes, mu/rho rows and (room for) the bound-test sums
+  if (tab_n > 0) b += (size_t)((tab_ne + 3) & ~3) * 4 + (size_t)tab_n * 20;
   return b;
 }
 
