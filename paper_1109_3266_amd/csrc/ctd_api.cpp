@@ -1100,7 +1100,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
     chunks += (items[i].n + (uint64_t)t.chunk - 1) / (uint64_t)t.chunk;
     std::memcpy(h + poff[i], items[i].prefix.data(), 8 * items[i].prefix.size());
   }
-  home_round_cases(rc, nrc, chunks, cfg.grid, cfg.block / 64);
+  home_round_cases(rc, nrc, cfg.grid, cfg.block / 64);
   std::memset(h + ctr_off, 0, ctr_bytes);
   HIPCHK(ctx, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream));
   // LDS room for the largest case's tables: each workgroup stages the

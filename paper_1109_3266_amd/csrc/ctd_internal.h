@@ -5,11 +5,13 @@
 #pragma once
 
 #include <algorithm>
+#include <vector>
 
 #include <stddef.h>
 #include <stdint.h>
 
 #include "ctd.h"
+#include "ctd_schedule.h"
 
 namespace ctd {
 
@@ -137,23 +139,16 @@ struct RoundCase {
   uint32_t wg_lo, home_waves;
 };
 
-// Fill wg_lo and home_waves of a round's cases for a grid of `grid`
-// workgroups of `waves` waves (chunk_begin already set).  Workgroup g's home
-// is the case holding chunk g * waves of the round, so the grid starts on
-// the first chunks in case order, as one wave per chunk would, and moves on
-// through the cases in order: the cases in flight at any time stay few, and
-// their phantoms and tallies stay in cache.
-inline void home_round_cases(RoundCase *rc, int nrc, uint64_t total_chunks, int grid,
-                             int waves) {
-  (void)total_chunks;
-  auto first_wg = [&](uint64_t chunk) {  // first g with g * waves >= chunk, at most grid
-    const uint64_t g = (chunk + (uint64_t)waves - 1) / (uint64_t)waves;
-    return (uint32_t)std::min<uint64_t>(g, (uint64_t)grid);
-  };
+// Fill wg_lo and home_waves of a round's cases (chunk_begin already set) for
+// a grid of `grid` workgroups of `waves` waves (ctd_schedule.h).
+inline void home_round_cases(RoundCase *rc, int nrc, int grid, int waves) {
+  std::vector<uint64_t> begin((size_t)nrc);
+  std::vector<uint32_t> lo((size_t)nrc), hw((size_t)nrc);
+  for (int i = 0; i < nrc; ++i) begin[i] = rc[i].chunk_begin;
+  home_workgroups(begin.data(), nrc, grid, waves, lo.data(), hw.data());
   for (int i = 0; i < nrc; ++i) {
-    rc[i].wg_lo = first_wg(rc[i].chunk_begin);
-    const uint32_t hi = i + 1 < nrc ? first_wg(rc[i + 1].chunk_begin) : (uint32_t)grid;
-    rc[i].home_waves = (hi - rc[i].wg_lo) * (uint32_t)waves;
+    rc[i].wg_lo = lo[i];
+    rc[i].home_waves = hw[i];
   }
 }
 

@@ -145,3 +145,30 @@ def test_headroom_decision_branches(tmp_path):
             if ln]
         assert rows[k][:2] == ["1", "3"]
         assert float(rows[k][2]) == k * b         # bounds unchanged
+
+
+def test_round_schedule_covers_every_chunk_once(tmp_path):
+    """The chunk schedule of a transport round (csrc/ctd_schedule.h and the
+    claim protocol of k_transport, played on the CPU with pseudo-random
+    interleavings): every workgroup starts inside its home case's range,
+    the home waves add up to the grid, every chunk runs exactly once and
+    every workgroup exits -- over single cases, many small cases, cases
+    with no home workgroup, grids larger than the round, one-wave groups."""
+    import os
+    import random
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = tmp_path / "schedule"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I",
+                    os.path.join(root, "paper_1109_3266_amd", "csrc"),
+                    os.path.join(root, "tests", "native", "schedule_check.cpp"), "-o", str(exe)],
+                   check=True)
+    r = random.Random(11)
+    lines = ["1 1280 4 97656", "2 1280 4 1", "3 5 4 3 1 1 1 2", "4 300 1 10 20 30"]
+    for s in range(300):
+        nrc = r.randint(1, 48)
+        lines.append(" ".join(map(str, [100 + s, r.randint(1, 400), r.choice([1, 2, 4, 8])] +
+                                  [r.randint(1, 300) for _ in range(nrc)])))
+    out = subprocess.run([str(exe)], input="\n".join(lines) + "\n", check=True,
+                         capture_output=True, text=True).stdout.split()
+    assert out == ["ok"] * len(lines), [o for o in out if o != "ok"][:3]
