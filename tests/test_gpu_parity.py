@@ -326,6 +326,39 @@ def test_run_many_matches_solo(ctx):
             o.close()
 
 
+def test_run_many_mixed_tables_and_layouts(ctx):
+    """One batched round over cases whose staged tables differ in size and
+    layout -- the head at 1/8 scale (8-byte records, bound grid, six
+    materials), a batched case on a 2 keV energy grid of 90 nodes (palette
+    phantom) and a random six-material phantom -- equals the solo runs bit for
+    bit: each workgroup stages the tables of the case it works on, sized for
+    the round's largest, and moves between cases as their chunks run out.
+    The case on the coarser grid is also paired with the oracle."""
+    from dataclasses import replace
+    say("batched round over mixed tables")
+    rng = np.random.default_rng(41)
+    coarse = replace(W.batched_case(rng, 4141, "coarse", 0.2, 1e-3), de=2.0, ne=90)
+    cases = [W.head(n_histories=300_000, scale=8), coarse,
+             random_phantom((9, 10, 11), 6, seed=42, n_hist=200_000)]
+    ns = [300_000, coarse.n_histories, 200_000]
+    solo = [gpu_run(ctx, wl, n=n) for wl, n in zip(cases, ns)]
+    objs = [Case(ctx, wl) for wl in cases]
+    try:
+        L.ctd_run_many(ctx, [o.cs for o in objs], ns)
+        for o, s in zip(objs, solo):
+            s1, hi, lo, nb = o.tally()
+            assert nb == s["nb"]
+            assert np.array_equal(s1, s["s1"])
+            assert np.array_equal(hi, s["s2_hi"]) and np.array_equal(lo, s["s2_lo"])
+            assert o.balance().q_incident == s["bal"].q_incident
+        s1, hi, lo, nb = objs[1].tally()
+        paired_compare(dict(s1=s1, s2_hi=hi, s2_lo=lo, nb=nb, bal=objs[1].balance()),
+                       O.run(O.OracleCase(coarse), threads=8))
+    finally:
+        for o in objs:
+            o.close()
+
+
 @pytest.mark.parametrize("n", [0, 1, 7, 63, 64, 65, 100_003])
 def test_ragged_and_tiny_runs(ctx, n):
     say(f"ragged n={n}")
