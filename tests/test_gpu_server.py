@@ -48,9 +48,9 @@ def _requests(n, seed=77):
     return [W.batched_case(rng, 9000 + i, f"r{i}", size_scale=0.25) for i in range(n)]
 
 
-def _solo(ctx, wl):
+def _solo(ctx, wl, max_h=MAX_H):
     with Case(ctx, wl) as c:
-        sig = L.ctd_run_to_sigma(ctx, c.cs, TARGET, 0.5, L.CTD_SIGMA_LOCAL, BATCH, MAX_H)
+        sig = L.ctd_run_to_sigma(ctx, c.cs, TARGET, 0.5, L.CTD_SIGMA_LOCAL, BATCH, max_h)
         s1, hi, lo, nb = c.tally()
     return sig, s1, hi, lo, nb
 
@@ -251,3 +251,67 @@ def test_server_admission_keeps_own_phantom(ctx):
     finally:
         ia.close()
         ib.close()
+
+
+def test_server_many_requests_with_evictions_and_cancels(ctx):
+    """Sixteen requests over four phantoms with at most three admitted and a
+    budget that holds the largest request with its phantom and one more
+    phantom: requests queue,
+    resident phantoms are evicted and reloaded, admissions and result copies
+    overlap the rounds, and two requests are cancelled (one while queued,
+    one while running).  Every other request ends done with the sums of its
+    solo run; at the end nothing is queued, running or resident beyond the
+    phantoms, and the byte count matches them."""
+    say("server: 16 requests, evictions, cancels")
+    rng = np.random.default_rng(23)
+    base = [W.batched_case(rng, 9300 + i, f"m{i}", size_scale=0.2) for i in range(4)]
+    inputs = [Inputs(ctx, wl) for wl in base]
+    keys = [int(k) for k in rng.integers(0, 4, 16)]
+    solo = {k: _solo(ctx, base[k], max_h=10**15) for k in set(keys)}
+    # room for the largest request's tallies and phantom plus one more
+    # phantom: switching between phantoms keeps evicting unused ones
+    Vs = sorted(wl.n_voxels for wl in base)
+    budget = 32 * Vs[-1] + (320 << 10) + 10 * (Vs[-1] + Vs[-2]) + (16 << 10)
+    sv = L.ctd_server_start(0, _cfg(budget=budget, max_active=3, max_h=10**15))
+    try:
+        for k, wl in enumerate(base):
+            L.ctd_server_add_phantom(sv, k, grid(wl), wl.mat, wl.rho)
+        tickets = []
+        for i, k in enumerate(keys):
+            tickets.append(L.ctd_server_submit(sv, k, inputs[k].ms, inputs[k].sp,
+                                               inputs[k].geo, params(base[k]), TARGET))
+            if i == 3:   # out of reach: runs until cancelled
+                L.ctd_server_cancel(sv, tickets[-1])
+        # a request with an unreachable target, cancelled once running
+        long_t = L.ctd_server_submit(sv, keys[0], inputs[keys[0]].ms, inputs[keys[0]].sp,
+                                     inputs[keys[0]].geo, params(base[keys[0]]), 1e-9)
+        cancel_at = time.time() + 0.5
+        for i, (t, k) in enumerate(zip(tickets, keys)):
+            if time.time() > cancel_at and long_t is not None:
+                L.ctd_server_cancel(sv, long_t)
+                long_t_done = long_t
+                long_t = None
+            rc, info = L.ctd_server_wait(sv, t)
+            if i == 3:
+                assert rc == L.CTD_ECANCELLED and info.state == 3
+                continue
+            assert rc == L.CTD_OK and info.state == 2, L.ctd_server_last_error(sv)
+            s1, hi, lo, nb = L.ctd_server_read_tally(sv, t, base[k].n_voxels)
+            sig, r1, rhi, rlo, rnb = solo[k]
+            assert nb == rnb and info.sigma == pytest.approx(sig, rel=0, abs=0)
+            assert np.array_equal(s1, r1) and np.array_equal(hi, rhi) and np.array_equal(lo, rlo)
+            L.ctd_server_release(sv, t)
+        if long_t is not None:
+            L.ctd_server_cancel(sv, long_t)
+            long_t_done = long_t
+        rc, info = L.ctd_server_wait(sv, long_t_done)
+        assert rc == L.CTD_ECANCELLED and info.state == 3
+        st = L.ctd_server_read_stats(sv)
+        assert st.completed == 15 and st.active == 0 and st.queued == 0
+        assert st.evictions >= 1 and st.phantom_loads >= 5
+        assert 0 < st.resident_bytes <= sum(9 * wl.n_voxels + wl.n_voxels // 8 +
+                                            wl.n_voxels // 64 + 8192 for wl in base)
+    finally:
+        L.ctd_server_stop(sv)
+        for inp in inputs:
+            inp.close()
