@@ -123,14 +123,17 @@ def _pmc_rows(d: str):
 def summarize_counters(workload: str):
     """Write profiles/k_transport_<workload>_pmc.json from the counter runs."""
     import statistics
-    kern = "k_transport<false, false,"     # the unlogged global-majorant instances
+    # the unlogged global-majorant instances: plain steps (0) and steps
+    # with collision passes (1)
+    kerns = ("k_transport<false, 0,", "k_transport<false, 1,")
 
     def per_launch(d, name):
-        v = [x for k, n, x, _ in _pmc_rows(d) if kern in k and n == name]
+        v = [x for k, n, x, _ in _pmc_rows(d) if any(p in k for p in kerns) and n == name]
         return statistics.mean(v), len(v)
 
     names = sorted({k.split("(")[0].replace("void ctd::", "")
-                    for k, n, x, _ in _pmc_rows(f"gpurun_out/pmc_{workload}_fetch") if kern in k})
+                    for k, n, x, _ in _pmc_rows(f"gpurun_out/pmc_{workload}_fetch")
+                    if any(p in k for p in kerns)})
 
     def copy_scale(d, name):
         v = sorted((x for k, n, x, _ in _pmc_rows(d) if "copy" in k.lower() and n == name),

@@ -953,6 +953,12 @@ ctd_tuning ctd::default_tuning(const ctd_ctx *ctx) {
   return t;
 }
 
+int ctd::step_kind(const ctd_case *cs, const ctd_tuning &t) {
+  if (cs->mc_cs > 0) return kStepMacro;
+  return cs->use_bound_grid && t.bound_block != 0 && t.defer_min > 0 ? kStepDeferred
+                                                                      : kStepPlain;
+}
+
 static bool tuning_ok(const ctd_tuning &t) {
   return (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
          t.waves_per_simd >= 1 && t.waves_per_simd <= 8 && t.refill_min >= 1 &&
@@ -1059,7 +1065,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
                       bool with_log) {
   const int nrc = (int)items.size();
   if (nrc == 0) return CTD_OK;
-  const bool macro = items[0].macro;
+  const int kind = items[0].step_kind;
   size_t bytes = sizeof(RoundCase) * nrc;
   std::vector<size_t> poff((size_t)nrc);
   for (int i = 0; i < nrc; ++i) {
@@ -1111,7 +1117,7 @@ int ctd::submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const c
   }
   if (chunks > 0 &&
       launch_transport((const RoundCase *)d, nrc, chunks, (unsigned long long *)(d + ctr_off),
-                       cfg, with_log, macro, ctx->stream) != 0)
+                       cfg, with_log, kind, ctx->stream) != 0)
     return hip_err(ctx, hipGetLastError(), "transport launch");
   HIPCHK(ctx, hipEventRecord(s.ev, ctx->stream));
   return CTD_OK;
@@ -1185,7 +1191,7 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     it.cd = cases[i]->d_desc;
     it.h_begin = cases[i]->h_next;
     it.n = n[i];
-    it.macro = cases[i]->mc_cs > 0;
+    it.step_kind = step_kind(cases[i], t);
     it.tab_n = cases[i]->ms->M * cases[i]->ms->eg.ne;
     it.tab_ne = cases[i]->ms->eg.ne;
     if (cases[i]->d_mh_state) {
@@ -1231,9 +1237,9 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
       return hip_err(ctx, hipGetLastError(), "Metropolis-Hastings fill launch");
   }
   int rc = CTD_OK;
-  std::vector<RoundItem> group[2];
-  for (auto &it : items) group[it.macro ? 1 : 0].push_back(std::move(it));
-  for (int gi = 0; gi < 2 && rc == CTD_OK; ++gi)
+  std::vector<RoundItem> group[3];
+  for (auto &it : items) group[it.step_kind].push_back(std::move(it));
+  for (int gi = 0; gi < 3 && rc == CTD_OK; ++gi)
     if (!group[gi].empty()) rc = submit_round(ctx, group[gi], t, with_log);
   if (rc != CTD_OK) return rc;
   if (timed) HIPCHK(ctx, hipEventRecord(tm.b, ctx->stream));
@@ -1439,7 +1445,7 @@ extern "C" int32_t ctd_run_batches_static(ctd_ctx *ctx, ctd_case *cs, uint64_t b
     if (launch_static_round_setup(table, a, ctx->stream) != 0 ||
         launch_transport((const RoundCase *)table, 1, chunks,
                          (unsigned long long *)(table + kStaticCounterOff), cfg, with_log,
-                         cs->mc_cs > 0, ctx->stream) != 0 ||
+                         step_kind(cs, t), ctx->stream) != 0 ||
         launch_fold(cs->d_tally, t.tally_mode ? kTallyCopies : 1, cs->d_s1, cs->d_s2,
                     cs->ph->V, cs->d_acc, ctx->stream) != 0)
       return hip_err(ctx, hipGetLastError(), "static round launch");

@@ -20,7 +20,7 @@ struct RoundItem {
   uint64_t h_begin, n;
   std::vector<unsigned long long> prefix;
   const int32_t *beamlets = nullptr;   // Alg. A1 beamlets of the round, or null
-  bool macro = false;                  // MACRO tracking case
+  int step_kind = 0;                   // kStepPlain, kStepDeferred or kStepMacro
   int tab_n = 0, tab_ne = 0;           // the case's mu/rho rows and energy nodes
 };
 
@@ -157,10 +157,12 @@ int hip_err(ctd_ctx *ctx, hipError_t e, const char *what);
 int upload_desc(ctd_ctx *ctx, ctd_case *cs);
 void fill_desc(ctd_case *cs);
 void free_case_buffers(ctd_case *cs);
-// One transport launch over items, which share one tracking mode.
+// One transport launch over items, which share one step kind.
 int submit_round(ctd_ctx *ctx, const std::vector<RoundItem> &items, const ctd_tuning &t,
                  bool with_log);
 ctd_tuning default_tuning(const ctd_ctx *ctx);
+// The step a case's histories take under tuning t (kStep*).
+int step_kind(const ctd_case *cs, const ctd_tuning &t);
 int batch_prefix(ctd_ctx *ctx, const ctd_case *cs, uint64_t n,
                  std::vector<unsigned long long> &prefix);
 int run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vector<uint64_t> &n,

@@ -186,11 +186,18 @@ struct LaunchCfg {
   size_t lds_budget; // LDS a workgroup may take without lowering the residency
 };
 
+// Step of a transport launch, the same for every case of it: kStepPlain
+// (GLOBAL tracking, one Woodcock step at a time, with or without the bound
+// grid's early rejection), kStepDeferred (GLOBAL tracking with the bound grid
+// and collision passes: every case has a bound grid and defer_min > 0),
+// kStepMacro (MACRO tracking).  A round whose cases need different steps is
+// split into one launch per step.
+constexpr int kStepPlain = 0, kStepDeferred = 1, kStepMacro = 2;
+
 // Kernel launchers (ctd_kernels.hip).  All enqueue on `stream`.
-// macro: every case of rc_dev uses MACRO tracking (else every case GLOBAL).
 int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
-                     bool macro, void *stream);
+                     int step_kind, void *stream);
 // Whether a transport workgroup of `block` threads in tally_mode fits the
 // device's LDS limit (mode 2 adds a sub-tally per wave).
 bool transport_lds_fits(int block, int tally_mode, int device);

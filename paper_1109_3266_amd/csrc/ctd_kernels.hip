@@ -880,14 +880,15 @@ __device__ __forceinline__ void stage_case(CaseDev *dst, uint2 *pal, const CaseD
     for (int i = threadIdx.x; i < 256; i += blockDim.x) pal[i] = sc[i];
 }
 
-// MACRO selects the macro-cell step for every case of the launch (a round
-// with both tracking modes is split into one launch per mode), so each
-// instance carries only its own step's registers.  Every instance is held to
-// 96 VGPRs (5 waves per SIMD): the global step fits without spilling, the
-// macro-cell step spills a few words outside its cell walk and gains more
-// from the fifth wave hiding its dependent cell/majorant loads than the
-// spills cost.
-template <bool LOG, bool MACRO, bool TAB>
+// KIND selects the step for every case of the launch (kStepPlain,
+// kStepDeferred, kStepMacro; a round whose cases need different steps is
+// split into one launch per step), so each instance carries only its own
+// step's registers and a tight loop of its steps between refills.  Every
+// instance is held to 96 VGPRs (5 waves per SIMD): the global steps fit
+// without spilling, the macro-cell step spills a few words outside its cell
+// walk and gains more from the fifth wave hiding its dependent cell/majorant
+// loads than the spills cost.
+template <bool LOG, int KIND, bool TAB>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k_transport(const RoundCase *__restrict__ rcs, int nrc,
                                                    uint64_t total_chunks,
                                                    unsigned long long *chunk_ctr, int refill_min,
@@ -1026,9 +1027,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
         if (claims_done && pool_next >= pool_end) break;   // case c done for this wave
         continue;
       }
-      if constexpr (MACRO) {
+      if constexpr (KIND == kStepMacro) {
+        // one call per pass of the loop: a tight loop of macro-cell calls
+        // spills more than it saves
         if (alive) alive = step_macro<LOG, TAB>(p, S, G, pal_lds, cnt);
-      } else if (S.bgrid && defer_min > 0) {
+      } else if constexpr (KIND == kStepDeferred) {
         // collision pass: the pending tentative collisions of the wave, once
         // defer_min of them have gathered (or every live lane waits on one)
         const unsigned long long pm = __ballot(alive && pvox >= 0);
@@ -1040,12 +1043,23 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
             pvox = -1;
           }
         }
-        if (alive && pvox < 0) {
-          const int st = step_fast<LOG, TAB>(p, S, G, pal_lds, cnt, pvox);
-          alive = st <= kStepPending;
+        // fast steps until a refill or a collision pass is due: a tight
+        // loop in which a photon's direction, energy and tables stay put
+        for (;;) {
+          if (alive && pvox < 0) {
+            const int st = step_fast<LOG, TAB>(p, S, G, pal_lds, cnt, pvox);
+            alive = st <= kStepPending;
+          }
+          const unsigned long long al = __ballot(alive);
+          if (64 - __popcll(al) >= refill_min) break;
+          const unsigned long long pw = __ballot(alive && pvox >= 0);
+          if (pw && (__popcll(pw) >= defer_min || pw == al)) break;
         }
-      } else if (alive) {
-        alive = step<LOG, TAB>(p, S, G, pal_lds, cnt);
+      } else {
+        for (;;) {   // steps until a refill is due
+          if (alive) alive = step<LOG, TAB>(p, S, G, pal_lds, cnt);
+          if (64 - __popcll(__ballot(alive)) >= refill_min) break;
+        }
       }
     }
     if (!first) {   // the wave ran histories of case c
@@ -1470,7 +1484,7 @@ int launch_static_round_setup(void *table, const StaticRoundArgs &args, void *st
 
 int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
                      unsigned long long *chunk_ctr, const LaunchCfg &cfg, bool with_log,
-                     bool macro, void *stream) {
+                     int step_kind, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   // stage the tables (room for the round's largest case) only where the
   // workgroup's LDS then still allows the resident workgroups the grid is
@@ -1483,12 +1497,15 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
   }
   using Kern = void (*)(const RoundCase *, int, uint64_t, unsigned long long *, int, int, int,
                         int, int, int, int);
-  static const Kern kerns[2][2][2] = {
-      {{k_transport<false, false, false>, k_transport<false, false, true>},
-       {k_transport<false, true, false>, k_transport<false, true, true>}},
-      {{k_transport<true, false, false>, k_transport<true, false, true>},
-       {k_transport<true, true, false>, k_transport<true, true, true>}}};
-  const Kern kern = kerns[with_log ? 1 : 0][macro ? 1 : 0][tab_n > 0 ? 1 : 0];
+  static const Kern kerns[2][3][2] = {
+      {{k_transport<false, kStepPlain, false>, k_transport<false, kStepPlain, true>},
+       {k_transport<false, kStepDeferred, false>, k_transport<false, kStepDeferred, true>},
+       {k_transport<false, kStepMacro, false>, k_transport<false, kStepMacro, true>}},
+      {{k_transport<true, kStepPlain, false>, k_transport<true, kStepPlain, true>},
+       {k_transport<true, kStepDeferred, false>, k_transport<true, kStepDeferred, true>},
+       {k_transport<true, kStepMacro, false>, k_transport<true, kStepMacro, true>}}};
+  if (step_kind < kStepPlain || step_kind > kStepMacro) return -1;
+  const Kern kern = kerns[with_log ? 1 : 0][step_kind][tab_n > 0 ? 1 : 0];
   hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.block), lds, s, rc_dev, nrc, total_chunks,
                      chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode, cfg.bound_shift,
                      cfg.defer_min, tab_n, tab_n > 0 ? cfg.tab_ne : 0);
