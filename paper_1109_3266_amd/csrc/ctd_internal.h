@@ -182,7 +182,7 @@ struct LaunchCfg {
   int tally_mode;
   int bound_shift;   // bound grid of 2^s-voxel blocks, or -1 (no early rejection)
   int defer_min;     // with a bound grid: collision pass once this many wait (0: none)
-  int tab_n, tab_ne; // single-case launch: mu/rho rows and energy nodes to stage in LDS
+  int tab_n, tab_ne; // the round's largest case: mu/rho rows and energy nodes to stage in LDS
   size_t lds_budget; // LDS a workgroup may take without lowering the residency
 };
 
@@ -201,8 +201,10 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
 // Whether a transport workgroup of `block` threads in tally_mode fits the
 // device's LDS limit (mode 2 adds a sub-tally per wave).
 bool transport_lds_fits(int block, int tally_mode, int device);
-// Dynamic LDS of a transport workgroup: per-wave slots, the tally-mode-2
-// sub-tallies, and tab_n mu/rho rows plus tab_ne majorant nodes (0: none).
+// Dynamic LDS of a transport workgroup: its header, case descriptor and
+// class table, per-wave counters, the tally-mode-2 sub-tallies, and room for
+// tab_n mu/rho rows, tab_ne majorant nodes and tab_n bound-test sums (0:
+// none).
 size_t transport_lds_bytes(int block, int tally_mode, int tab_n, int tab_ne);
 // Fold ncopies batch tallies [ncopies][V]: S1 += sum, S2 += sum^2, zero them;
 // fold the batch counters of acc into its 128-bit totals and record the

@@ -123,10 +123,10 @@ __device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned l
 }
 
 // The fields the step loop reads, as one wave-uniform record.  It is filled
-// with readfirstlane on every case switch, so the compiler keeps it in scalar
-// registers; everything else about a case (source geometry, the angular
-// surfaces and cutoff used at real scatters, counters, log) is read from the
-// wave's LDS copy of the full descriptor.
+// with readfirstlane when a wave takes its first chunk of a case, so the
+// compiler keeps it in scalar registers; everything else about a case (source
+// geometry, the angular surfaces and cutoff used at real scatters, counters,
+// log) is read from the workgroup's LDS copy of the full descriptor.
 struct StepCase {
   const GLOBAL uint2 *vox;
   const GLOBAL uint8_t *vox8;
@@ -552,7 +552,7 @@ __device__ __forceinline__ bool collide(Photon &p, const StepCase &S, const Case
   if (xi < c1) {  // Compton (Sec. 2.2.3): angle from the C surface
     c.add(ACC_N_COMPTON, 1);
     p.k |= kScatBit;
-    // surface fields from the wave's LDS copy of the case (read only here)
+    // surface fields from the workgroup's LDS copy of the case (read only here)
     const int nzc = G.nzc;
     const GLOBAL float4 *Q = (const GLOBAL float4 *)G.comp_quad;
     if (G.comp_per_mat) Q += (size_t)m * (size_t)(S.ne - 1) * (size_t)(nzc - 1);
@@ -593,7 +593,7 @@ __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const Cas
                                          const LOCAL uint2 *pal, Counters &c, const uint4 &r,
                                          uint32_t k, int32_t vox, float mumax) {
   uint32_t rbits, m;
-  if (S.npal) {  // 1-byte index into the wave's LDS table
+  if (S.npal) {  // 1-byte index into the workgroup's LDS palette
     const uint32_t i8 = S.vox8[vox];
     rbits = pal[i8].x;
     m = pal[i8].y;
@@ -612,7 +612,7 @@ __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const Cas
 }
 
 // Tentative collision in a single-material block of the bound grid (class cls
-// in the wave's LDS class table: the block's material and a density level at
+// in the workgroup's LDS class table: the block's material and a density level at
 // or above every voxel's).  The cumulative sum at the level, formed by the
 // same float operations as the selection, bounds the voxel's own sum (float
 // rounding is monotone), so xi at or above it is a fictitious collision
