@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "ctd_api_internal.h"
+#include "ctd_bound.h"
 #include "ctd_headroom.h"
 #include "ctd_tables.h"
 
@@ -602,34 +603,10 @@ int ctd::upload_desc(ctd_ctx *ctx, ctd_case *cs) {
   return CTD_OK;
 }
 
-// Bound-test sums (CaseDev::bnd): for material m and energy cell j the sum
-// over the processes of the largest value the column's linear interpolation
-// takes in the cell, rounded up to float with a relative margin of 2^-20.
-// Inside the grid the weight w = f - j lies in [0, 1) exactly, and the float
-// interpolation fma(w, x1 - x0, x0) stays within (1 + u)^2 of the larger node
-// (u = 2^-24); the selection's sums of the rho-scaled terms add at most
-// (1 + u)^3.  So a class level rho_c times this sum, rounded, is at or above
-// the selection's sum at rho_c, hence at every density of the block (float
-// rounding is monotone).  In the top cell (E up to the last node) the
-// rounding of f = (E - e0) / dE can put w a little past 1 (by at most about
-// 3u (ne - 1)); there the column is extended to w = 1 + 4u ne.
+// Bound-test sums (CaseDev::bnd; ctd_bound.h).
 static std::vector<float> bound_sums(const ctd_matset *ms, bool rayleigh) {
-  const int ne = ms->eg.ne;
-  std::vector<float> out((size_t)ms->M * (size_t)(ne - 1));
-  const double w_top = 1.0 + 4.0 * 0x1p-24 * ne;
-  for (int m = 0; m < ms->M; ++m) {
-    const float *r = ms->mu_rho.data() + (size_t)m * ne * 3;
-    for (int j = 0; j + 1 < ne; ++j) {
-      const float *x0 = r + (size_t)j * 3, *x1 = x0 + 3;
-      const double w = j + 2 == ne ? w_top : 1.0;
-      auto peak = [&](int k) {   // largest value of the column over the cell
-        return std::max((double)x0[k], (double)x0[k] + w * ((double)x1[k] - (double)x0[k]));
-      };
-      double sum = peak(0) + peak(1);
-      if (rayleigh) sum += peak(2);
-      out[(size_t)m * (ne - 1) + j] = round_up_to_float(sum * (1.0 + 0x1p-20));
-    }
-  }
+  std::vector<float> out((size_t)ms->M * (size_t)(ms->eg.ne - 1));
+  ctd::bound_sums(ms->mu_rho.data(), ms->M, ms->eg.ne, rayleigh, out.data());
   return out;
 }
 

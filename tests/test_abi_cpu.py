@@ -172,3 +172,38 @@ def test_round_schedule_covers_every_chunk_once(tmp_path):
     out = subprocess.run([str(exe)], input="\n".join(lines) + "\n", check=True,
                          capture_output=True, text=True).stdout.split()
     assert out == ["ok"] * len(lines), [o for o in out if o != "ok"][:3]
+
+
+def test_bound_test_sums_never_reject_a_collision(tmp_path):
+    """The bound grid's per-cell sums (csrc/ctd_bound.h) bound the float32
+    selection sum the transport forms, at the block's level and below, for
+    random tables with steep columns, edges and zero columns, energies at
+    the nodes, inside the cells and at the top of the grid (where the cell
+    weight can pass 1).  Also: without the 2^-20 margin, or without the
+    top-cell extension, the check finds a violation."""
+    import os
+    import shutil
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, "paper_1109_3266_amd", "csrc")
+    src = os.path.join(root, "tests", "native", "bound_check.cpp")
+
+    def run(include, seed, trials):
+        exe = tmp_path / f"bound_{seed}_{os.path.basename(include)}"
+        subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-I", include, src,
+                        "-o", str(exe)], check=True)
+        return subprocess.run([str(exe), str(seed), str(trials)], check=True,
+                              capture_output=True, text=True).stdout.split()
+
+    for seed in (1, 7):
+        out = run(csrc, seed, 300)
+        assert out[0] == "ok", " ".join(out)
+        assert 0.99999 < float(out[2]) < 1.0
+    header = open(os.path.join(csrc, "ctd_bound.h")).read()
+    for old, new in [("sum * (1.0 + 0x1p-20)", "sum"),
+                     ("const double w = j + 2 == ne ? w_top : 1.0;", "const double w = 1.0;")]:
+        assert old in header
+        d = tmp_path / ("planted" + str(len(new)))
+        d.mkdir()
+        (d / "ctd_bound.h").write_text(header.replace(old, new))
+        assert run(str(d), 1, 1000)[0] == "violation:"
