@@ -210,9 +210,11 @@ typedef struct {
                             of a 1-byte bound grid built at phantom load.  A
                             block of one material carries a density level at
                             or above all of its voxels'; a tentative
-                            collision whose xi reaches the Woodcock sum at
-                            that level is fictitious in every voxel of the
-                            block (float rounding is monotone), so it is
+                            collision whose xi reaches the level times the
+                            material's largest interaction sum over the
+                            photon's 1 keV-class energy cell (rounded up
+                            with a margin that covers float rounding) is
+                            fictitious in every voxel of the block, so it is
                             decided without reading the voxel.  Decisions,
                             and so results, are those of 0, bit for bit. */
   int32_t defer_min;     /* With a bound grid: a tentative collision the

@@ -932,8 +932,7 @@ ctd_tuning ctd::default_tuning(const ctd_ctx *ctx) {
 
 int ctd::step_kind(const ctd_case *cs, const ctd_tuning &t) {
   if (cs->mc_cs > 0) return kStepMacro;
-  return cs->use_bound_grid && t.bound_block != 0 && t.defer_min > 0 ? kStepDeferred
-                                                                      : kStepPlain;
+  return cs->use_bound_grid && t.bound_block != 0 ? kStepDeferred : kStepPlain;
 }
 
 static bool tuning_ok(const ctd_tuning &t) {

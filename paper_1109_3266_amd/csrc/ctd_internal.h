@@ -181,15 +181,15 @@ struct LaunchCfg {
   int chunk;
   int tally_mode;
   int bound_shift;   // bound grid of 2^s-voxel blocks, or -1 (no early rejection)
-  int defer_min;     // with a bound grid: collision pass once this many wait (0: none)
+  int defer_min;     // with a bound grid: collision pass once this many wait (0: at once)
   int tab_n, tab_ne; // the round's largest case: mu/rho rows and energy nodes to stage in LDS
   size_t lds_budget; // LDS a workgroup may take without lowering the residency
 };
 
 // Step of a transport launch, the same for every case of it: kStepPlain
-// (GLOBAL tracking, one Woodcock step at a time, with or without the bound
-// grid's early rejection), kStepDeferred (GLOBAL tracking with the bound grid
-// and collision passes: every case has a bound grid and defer_min > 0),
+// (GLOBAL tracking, every tentative collision read from its voxel),
+// kStepDeferred (GLOBAL tracking with the bound grid's early rejection and
+// collision passes: every case has a bound grid in use),
 // kStepMacro (MACRO tracking).  A round whose cases need different steps is
 // split into one launch per step.
 constexpr int kStepPlain = 0, kStepDeferred = 1, kStepMacro = 2;

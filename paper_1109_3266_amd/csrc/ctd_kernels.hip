@@ -611,34 +611,9 @@ __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const Cas
                       unif(r.y) * mumax);
 }
 
-// Tentative collision in a single-material block of the bound grid (class cls
-// in the workgroup's LDS class table: the block's material and a density level at
-// or above every voxel's).  The cumulative sum at the level, formed by the
-// same float operations as the selection, bounds the voxel's own sum (float
-// rounding is monotone), so xi at or above it is a fictitious collision
-// whatever the voxel holds, decided without reading the voxel; otherwise the
-// voxel's density is read and the selection is the one interact() makes.
-template <bool LOG, bool TAB>
-__device__ __forceinline__ bool interact_bounded(Photon &p, const StepCase &S, const CaseDev &G,
-                                                 const LOCAL uint2 *cls_tab, Counters &c,
-                                                 const uint4 &r, uint32_t k, int32_t vox,
-                                                 uint32_t cls) {
-  const uint2 ce = cls_tab[cls];
-  const uint32_t m = ce.y;
-  const float rho_c = __uint_as_float(ce.x);
-  const float xi = unif(r.y) * p.mumax;
-  if (xi >= rho_c * bound_sum<TAB>(S, m, p.je)) return true;
-  const uint32_t ti = __umul24(m, (uint32_t)S.ne) + (uint32_t)p.je;
-  float4 t0, t1;
-  table_rows<TAB>(S, ti, t0, t1);
-  const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
-  const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
-  const float rho = __uint_as_float(S.vox[vox].x);
-  return collide<LOG, TAB>(p, S, G, c, r, k, vox, m, rho, a, b, cr, xi);
-}
-
-// One Woodcock step (Sec. 2.1) against the global majorant; returns false
-// when the photon is done.
+// One Woodcock step (Sec. 2.1) against the global majorant, every tentative
+// collision read from its voxel (cases with a bound grid take step_fast and
+// the collision passes instead); returns false when the photon is done.
 template <bool LOG, bool TAB>
 __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G,
                                      const LOCAL uint2 *pal, Counters &c) {
@@ -660,14 +635,6 @@ __device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev
   const uint32_t ix = (uint32_t)p.px, iy = (uint32_t)p.py, iz = (uint32_t)p.pz;
   const int32_t vox = (int32_t)__umul24(__umul24(iz, (uint32_t)S.ny) + iy, (uint32_t)S.nx) +
                       (int32_t)ix;
-  if (S.bgrid) {
-    const uint32_t e = (1u << S.bshift) - 1u;   // wave-uniform: scalar ops
-    const uint32_t bgx = ((uint32_t)S.nx + e) >> S.bshift, bgy = ((uint32_t)S.ny + e) >> S.bshift;
-    const uint32_t blk = __umul24(__umul24(iz >> S.bshift, bgy) + (iy >> S.bshift), bgx) +
-                         (ix >> S.bshift);
-    const uint32_t cls = S.bgrid[blk];
-    if (cls != kMixedClass) return interact_bounded<LOG, TAB>(p, S, G, pal, c, r, k, vox, cls);
-  }
   return interact<LOG, TAB>(p, S, G, pal, c, r, k, vox, p.mumax);
 }
 
