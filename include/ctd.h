@@ -363,10 +363,13 @@ int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, double dose_
                          double *achieved);
 
 /* Batched engine: run n[i] histories of each case i in ONE persistent launch
- * per batch round over a (case, history-chunk) task queue (one launch per
- * tracking mode when the cases mix GLOBAL and MACRO), with the launch
- * configuration of cs[0].  Per-case results equal ctd_run(cs[i], n[i]) bit
- * for bit.  CTD_EINVAL if a case is listed twice.  Async. */
+ * per batch round over a (case, history-chunk) task queue: each workgroup
+ * works on one case at a time, with that case's tables staged in its LDS,
+ * and moves on to the next case with chunks left when its case runs out
+ * (one launch per step kind when the cases mix MACRO tracking, the bound
+ * grid and plain GLOBAL steps), with the launch configuration of cs[0].
+ * Per-case results equal ctd_run(cs[i], n[i]) bit for bit.  CTD_EINVAL if a
+ * case is listed twice.  Async. */
 int32_t ctd_run_many(ctd_ctx *ctx, ctd_case *const *cs, const uint64_t *n, int32_t count);
 
 /* Wait until all work enqueued for the case (its stream) is complete. */
