@@ -38,6 +38,11 @@
  *   - Determinism: tallies are a pure function of (inputs, seed, the sequence
  *     of batch sizes); they do not depend on the stream, tuning, thread
  *     count or work co-scheduled in a batched launch.
+ *   - A ctd_run* call that fails before enqueueing any work leaves its cases
+ *     as they were (e.g. CTD_EOVERFLOW from the headroom check).  One that
+ *     fails after enqueueing part of a round (a launch or copy error) leaves
+ *     their sums, counters and history ids undefined: the calls that run or
+ *     read such a case return CTD_EINVAL until ctd_case_reset.
  */
 #ifndef CTD_H
 #define CTD_H
@@ -449,6 +454,11 @@ int32_t ctd_debug_deposit_log(ctd_ctx *ctx, ctd_case *cs, uint64_t h0, uint64_t 
                               uint64_t capacity);
 int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out, uint64_t capacity,
                            uint64_t *n);
+/* For callers that test their handling of a failed run: the next round on
+ * ctx returns CTD_EDEVICE right after its first transport launch (which
+ * completes normally), leaving its cases in the failed state described under
+ * Conventions.  One-shot. */
+int32_t ctd_debug_fail_next_round(ctd_ctx *ctx);
 
 /* ---------------- serving (continuous batching) ----------------
  * A server owns two private contexts on `device` and two host threads: one
@@ -460,7 +470,7 @@ int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out, uint64_t 
  * queue in arrival order and are admitted while their device footprint fits
  * hbm_budget_bytes.  Each round runs one batch of batch_histories for every
  * admitted request in a single launch of the batched engine; the host waits
- * for the device once per iteration of up to 24 rounds or 2e8 histories,
+ * for the device once per iteration of up to 21 rounds or 2e8 histories,
  * and requests admitted meanwhile join the next iteration.  Every request
  * follows the batch schedule of ctd_run_to_sigma with the same batch size, so
  * its result is identical alone or among others.  Beyond the budget the

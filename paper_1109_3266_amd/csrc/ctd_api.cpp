@@ -54,6 +54,13 @@ int ctd::hip_err(ctd_ctx *ctx, hipError_t e, const char *what) {
     if (!(cond)) return ctd::set_err((ctx), CTD_EINVAL, __VA_ARGS__); \
   } while (0)
 
+// A case whose last run call failed part-way (ctd_case::failed) is refused
+// by the calls that run or read it until ctd_case_reset.
+#define NEED_INTACT(ctx, cs)                                                                \
+  NEED(ctx, !(cs)->failed,                                                                  \
+       "a run call on this case failed after enqueueing part of its work; its sums are "    \
+       "undefined until ctd_case_reset")
+
 static void dfree(void *p) {
   if (p) (void)hipFree(p);
 }
@@ -914,6 +921,7 @@ extern "C" int32_t ctd_case_reset(ctd_ctx *ctx, ctd_case *cs) {
   }
   cs->timing.clear();
   cs->transport_ms = cs->fold_ms = 0.0;
+  cs->failed = false;
   return CTD_OK;
 }
 
@@ -1155,6 +1163,8 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
                    const ctd_tuning &t) {
   std::vector<RoundItem> items;
   bool with_log = false;
+  for (size_t i = 0; i < cases.size(); ++i)
+    if (n[i]) NEED_INTACT(ctx, cases[i]);
   for (size_t i = 0; i < cases.size(); ++i) {
     if (n[i] == 0) continue;
     int rc0 = check_headroom(ctx, cases[i], n[i]);
@@ -1193,6 +1203,18 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     }
   } guard;
   ctd_case::Timing &tm = guard.tm;
+  // from the first enqueue that changes a case on, a failure leaves the
+  // round's cases part-way through it
+  struct FailMark {
+    const std::vector<ctd_case *> &cases;
+    const std::vector<uint64_t> &n;
+    bool armed = false;
+    ~FailMark() {
+      if (!armed) return;
+      for (size_t i = 0; i < cases.size(); ++i)
+        if (n[i]) cases[i]->failed = true;
+    }
+  } mark{cases, n};
   const bool timed = cases.size() == 1;
   if (timed) {
     HIPCHK(ctx, hipEventCreate(&tm.a));
@@ -1200,6 +1222,7 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     HIPCHK(ctx, hipEventCreate(&tm.c));
     HIPCHK(ctx, hipEventRecord(tm.a, ctx->stream));
   }
+  mark.armed = true;
   // Alg. A1 chains of this round's histories (same stream: ordered before the
   // transport that reads them and after the previous round's)
   for (size_t i = 0, k = 0; i < cases.size(); ++i) {
@@ -1215,8 +1238,14 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
   int rc = CTD_OK;
   std::vector<RoundItem> group[3];
   for (auto &it : items) group[it.step_kind].push_back(std::move(it));
-  for (int gi = 0; gi < 3 && rc == CTD_OK; ++gi)
-    if (!group[gi].empty()) rc = submit_round(ctx, group[gi], t, with_log);
+  for (int gi = 0; gi < 3 && rc == CTD_OK; ++gi) {
+    if (group[gi].empty()) continue;
+    rc = submit_round(ctx, group[gi], t, with_log);
+    if (rc == CTD_OK && ctx->fail_next_round) {
+      ctx->fail_next_round = false;
+      rc = set_err(ctx, CTD_EDEVICE, "failure injected after a transport launch");
+    }
+  }
   if (rc != CTD_OK) return rc;
   if (timed) HIPCHK(ctx, hipEventRecord(tm.b, ctx->stream));
   for (size_t i = 0; i < cases.size(); ++i) {
@@ -1237,6 +1266,7 @@ int ctd::run_round(ctd_ctx *ctx, std::vector<ctd_case *> &cases, const std::vect
     first->timing.push_back(tm);
     guard.keep = true;
   }
+  mark.armed = false;
   return CTD_OK;
 }
 
@@ -1307,6 +1337,7 @@ int ctd::check_batch_sizes(ctd_ctx *ctx, const ctd_case *cs, uint64_t next_size)
 }
 
 int ctd::sigma_async(ctd_ctx *ctx, ctd_case *cs, int kind, double frac, double *host_out) {
+  NEED_INTACT(ctx, cs);
   if (cs->batches < 2) return set_err(ctx, CTD_EINVAL, "sigma needs >= 2 folded batches");
   int rc = check_batch_sizes(ctx, cs, 0);
   if (rc != CTD_OK) return rc;
@@ -1382,6 +1413,7 @@ extern "C" int32_t ctd_run_batches_static(ctd_ctx *ctx, ctd_case *cs, uint64_t b
        "Metropolis-Hastings beamlets for %llu histories; run ctd_run_batches once with batches "
        "of %llu histories first", (unsigned long long)cs->mh_cap,
        (unsigned long long)batch_histories);
+  NEED_INTACT(ctx, cs);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   if (batch_histories == 0 || count == 0) return CTD_OK;
   StaticRoundArgs a;
@@ -1413,6 +1445,8 @@ extern "C" int32_t ctd_run_batches_static(ctd_ctx *ctx, ctd_case *cs, uint64_t b
                      (double)batch_histories);
     a.h_begin = cs->h_next;
     a.n = batch_histories;
+    // from here on a failure leaves the case part-way through a batch
+    cs->failed = true;
     if (a.beamlets &&
         launch_mh_fill(cs->d_fl_f, (int)cs->geo->fl_f.size(), cs->geo->g.fluence_chains,
                        a.h_begin, a.n, cs->desc.key0, cs->desc.key1, cs->d_mh_state,
@@ -1425,6 +1459,7 @@ extern "C" int32_t ctd_run_batches_static(ctd_ctx *ctx, ctd_case *cs, uint64_t b
         launch_fold(cs->d_tally, t.tally_mode ? kTallyCopies : 1, cs->d_s1, cs->d_s2,
                     cs->ph->V, cs->d_acc, ctx->stream) != 0)
       return hip_err(ctx, hipGetLastError(), "static round launch");
+    cs->failed = false;
     cs->s1_bound = s1;
     cs->s2_bound = s2;
     cs->h_next += batch_histories;
@@ -1470,6 +1505,7 @@ extern "C" int32_t ctd_run_to_sigma(ctd_ctx *ctx, ctd_case *cs, double target, d
 
 extern "C" int32_t ctd_tally_device(ctd_ctx *ctx, ctd_case *cs, void **s1, void **s2) {
   if (!ctx || !cs) return CTD_EINVAL;
+  NEED_INTACT(ctx, cs);
   if (s1) *s1 = cs->d_s1;
   if (s2) *s2 = cs->d_s2;
   return CTD_OK;
@@ -1478,6 +1514,7 @@ extern "C" int32_t ctd_tally_device(ctd_ctx *ctx, ctd_case *cs, void **s1, void 
 extern "C" int32_t ctd_read_tally(ctd_ctx *ctx, ctd_case *cs, int64_t *s1, uint64_t *s2_hi,
                                   uint64_t *s2_lo, uint32_t *n_batches) {
   if (!ctx || !cs) return CTD_EINVAL;
+  NEED_INTACT(ctx, cs);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   const int64_t V = cs->ph->V;
@@ -1548,6 +1585,7 @@ extern "C" int32_t ctd_read_dose(ctd_ctx *ctx, ctd_case *cs, double *dose, doubl
 
 extern "C" int32_t ctd_read_balance(ctd_ctx *ctx, ctd_case *cs, ctd_balance *out) {
   if (!ctx || !cs || !out) return CTD_EINVAL;
+  NEED_INTACT(ctx, cs);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   uint64_t w[kAccWords];
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1572,6 +1610,7 @@ extern "C" int32_t ctd_read_balance(ctd_ctx *ctx, ctd_case *cs, ctd_balance *out
 
 extern "C" int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out) {
   if (!ctx || !cs || !out) return CTD_EINVAL;
+  NEED_INTACT(ctx, cs);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   uint64_t w[kAccWords];
@@ -1636,9 +1675,16 @@ extern "C" int32_t ctd_debug_deposit_log(ctd_ctx *ctx, ctd_case *cs, uint64_t h0
   return upload_desc(ctx, cs);
 }
 
+extern "C" int32_t ctd_debug_fail_next_round(ctd_ctx *ctx) {
+  if (!ctx) return CTD_EINVAL;
+  ctx->fail_next_round = true;
+  return CTD_OK;
+}
+
 extern "C" int32_t ctd_read_event_log(ctd_ctx *ctx, ctd_case *cs, ctd_event *out,
                                       uint64_t capacity, uint64_t *n) {
   if (!ctx || !cs || !n) return CTD_EINVAL;
+  NEED_INTACT(ctx, cs);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   *n = 0;
@@ -1679,6 +1725,7 @@ extern "C" int32_t ctd_autotune(ctd_ctx *ctx, ctd_case *cs, uint64_t trial_histo
   tw.d_mh_state = nullptr;
   tw.d_mh_beam = nullptr;
   tw.mh_cap = 0;
+  tw.failed = false;
   const int64_t V = cs->ph->V;
   auto release = [&]() {
     dfree(tw.d_tally);

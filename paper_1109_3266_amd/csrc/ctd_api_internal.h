@@ -49,6 +49,8 @@ struct ctd_ctx {
   // device address of this device's static round table (ctd_run_batches_static),
   // looked up at creation with the device current; null if the lookup failed
   void *static_table = nullptr;
+  // ctd_debug_fail_next_round: the next round fails after its first launch
+  bool fail_next_round = false;
 };
 
 struct ctd_phantom {
@@ -148,6 +150,9 @@ struct ctd_case {
   double sigma_local = NAN, sigma_paper = NAN;
   double s1_bound = 0.0, s2_bound = 0.0;  // upper bounds on any voxel's S1, S2
   bool in_server = false;
+  // a run call failed after enqueueing part of its work: the sums, counters
+  // and history ids are undefined until ctd_case_reset
+  bool failed = false;
 };
 
 namespace ctd {

@@ -54,10 +54,11 @@ namespace {
 // Work the runner enqueues between two host waits: about 20-40 ms of
 // transport on MI355X, long next to the wait and the re-planning between
 // iterations and short next to a request's seconds of service.  The round
-// cap keeps an iteration within a context's 64 launch-table slots (two per
-// round when global and MACRO cases share it).
+// cap keeps an iteration within a context's 64 launch-table slots (up to
+// three launches per round, one per step kind, when the requests mix them),
+// so no launch of an iteration waits for an earlier one to free its slot.
 constexpr uint64_t kIterationHistories = 200000000ull;
-constexpr int kIterationRounds = 24;
+constexpr int kIterationRounds = 21;
 
 struct PhantomEntry {
   ctd_grid g{};

@@ -176,6 +176,7 @@ _SIGS = {
     "ctd_gamma": (I32, [P, C.POINTER(ctd_grid), P, P, I32, C.POINTER(ctd_gamma_params), P,
                         C.POINTER(U64), C.POINTER(U64)]),
     "ctd_debug_deposit_log": (I32, [P, P, U64, U64, U64]),
+    "ctd_debug_fail_next_round": (I32, [P]),
     "ctd_server_start": (I32, [I32, C.POINTER(ctd_server_config), PP]),
     "ctd_server_last_error": (C.c_char_p, [P]),
     "ctd_server_now": (F64, [P]),
@@ -438,6 +439,10 @@ def ctd_gamma(ctx, grid: ctd_grid, ref, ev, dose_tol: float, dta_cm: float, regi
     check(lib().ctd_gamma(ctx, C.byref(grid), ptr(r), ptr(e), CTD_MEM_HOST, C.byref(p),
                           ptr(g) if g is not None else None, C.byref(nr), C.byref(npass)), ctx)
     return g, nr.value, npass.value
+
+
+def ctd_debug_fail_next_round(ctx):
+    check(lib().ctd_debug_fail_next_round(ctx), ctx)
 
 
 def ctd_debug_deposit_log(ctx, cs, h0: int, nh: int, capacity: int):

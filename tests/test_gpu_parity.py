@@ -455,6 +455,47 @@ def test_error_paths(ctx):
         L.ctd_geometry_set(ctx, _geom(dict(bow.geometry, feed=float("nan"))))
 
 
+def test_failed_run_refused_until_reset(ctx):
+    """A run that fails after enqueueing part of a round (the failure is
+    injected from the host right after a transport launch, which completes
+    normally) leaves its cases refused by the calls that run or read them;
+    ctd_case_reset restores a case, and its runs after the reset give the
+    sums of a fresh case."""
+    say("failed run refused until reset")
+    wl = W.tiny(n_histories=20000)
+    ref = gpu_run(ctx, wl)
+    with Case(ctx, wl) as c:
+        c.run(wl.n_histories)
+        L.ctd_debug_fail_next_round(ctx)
+        with pytest.raises(L.CtdError) as e:
+            c.run(wl.n_histories)
+        assert e.value.code == L.CTD_EDEVICE
+        refused = (c.tally, c.balance, c.stats, lambda: c.run(1000),
+                   lambda: L.ctd_sigma(ctx, c.cs, L.CTD_SIGMA_LOCAL, 0.5))
+        for call in refused:
+            with pytest.raises(L.CtdError) as e:
+                call()
+            assert e.value.code == L.CTD_EINVAL and "ctd_case_reset" in str(e.value)
+        L.ctd_case_reset(ctx, c.cs)
+        c.run(wl.n_histories)
+        s1, hi, lo, nb = c.tally()
+        check_balance(dict(bal=c.balance(), s1=s1), wl.n_histories)
+    assert nb == ref["nb"]
+    assert np.array_equal(s1, ref["s1"])
+    assert np.array_equal(hi, ref["s2_hi"]) and np.array_equal(lo, ref["s2_lo"])
+    # a batched round: every case in it is refused; a case outside it is not
+    with Case(ctx, wl) as a, Case(ctx, wl, seed=7) as b, Case(ctx, wl, seed=9) as d:
+        L.ctd_debug_fail_next_round(ctx)
+        with pytest.raises(L.CtdError) as e:
+            L.ctd_run_many(ctx, [a.cs, b.cs], [wl.n_histories, wl.n_histories])
+        assert e.value.code == L.CTD_EDEVICE
+        for x in (a, b):
+            with pytest.raises(L.CtdError):
+                x.tally()
+        d.run(wl.n_histories)
+        assert int(d.tally()[0].sum()) == d.balance().q_deposited
+
+
 def test_run_to_sigma_and_host_sigma(ctx):
     say("run to sigma water_cbct/4")
     wl = W.water_cbct(scale=4)
