@@ -46,10 +46,17 @@ BATCH = 100_000_000
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 256 CUs x 64 lanes/clk x 2.4 GHz (non-packed)
 
 # Algorithmic 32-bit lane operations per unit of work (counted from the kernel's
-# arithmetic; the roofline figure divides their sum by the launch time):
-OPS_STEP = 132       # Philox block 100, 2 uniforms 6, free path 2, move 3, inside 6,
-                     # voxel index 5, two table lerps + cumulative 7, selection 3
-OPS_SCATTER = 46     # 2 uniforms 6, bilinear surface 12, rotation 28
+# arithmetic; the roofline figure divides their sum by the launch time).  A
+# Philox4x32-10 block is 100; with the global majorant a step and a scatter
+# each take a pair of its four words (half a block), with MACRO tracking a
+# flight takes a block whose other words also serve its scatter.
+OPS_STEP = 82        # half a Philox block 50, 2 uniforms 6, free path 2, move 3,
+                     # inside 6, voxel index 5, two table lerps + cumulative 7,
+                     # selection 3
+OPS_SCATTER = 96     # half a Philox block 50, 2 uniforms 6, bilinear surface 12,
+                     # rotation 28
+OPS_FLIGHT_MACRO = 132   # a MACRO flight: a whole block instead of half
+OPS_SCATTER_MACRO = 46   # a MACRO scatter: no block of its own
 OPS_COMPTON = 13     # kinematics 4, energy-grid update 7, deposit conversion 2
 OPS_HISTORY = 170    # source block 100 + 4 uniforms 12, projection/source/field 12,
                      # direction 8, slab entry 30, energy-grid set-up 8
@@ -651,7 +658,9 @@ def transport_leg(ctx, L, W, Case, torch, stream, name: str, steps: int, warmup:
     d_scat = (st1.n_compton - st0.n_compton) + (st1.n_rayleigh - st0.n_rayleigh)
     d_comp = st1.n_compton - st0.n_compton
     d_dep = st1.n_deposits - st0.n_deposits
-    ops = (OPS_STEP * d_steps + OPS_SCATTER * d_scat + OPS_COMPTON * d_comp +
+    macro = st1.tracking == L.CTD_TRACK_MACRO
+    ops = ((OPS_FLIGHT_MACRO if macro else OPS_STEP) * d_steps +
+           (OPS_SCATTER_MACRO if macro else OPS_SCATTER) * d_scat + OPS_COMPTON * d_comp +
            OPS_HISTORY * n_timed)
     launch_ms = (st1.transport_ms - st0.transport_ms) / steps
     launch_s = launch_ms * 1e-3

@@ -15,8 +15,11 @@
  * Where the paper is silent the following readings are used (the GPU library
  * follows the same rules, written independently):
  *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
- *     counter = (step k, history id lo, history id hi, 0); k = 0 is the source
- *     block, k >= 1 the Woodcock steps; u(r) = (2*(r>>9)+1) * 2^-24;
+ *     counter = (k, history id lo, history id hi, 0); k = 0 is the source
+ *     block; blocks k >= 1 give the transport uniforms, taken two at a time
+ *     in order (a Woodcock step: free path and selection; a Compton or
+ *     Rayleigh scatter: polar-angle sample and azimuth), so two fictitious
+ *     steps share a block; u(r) = (2*(r>>9)+1) * 2^-24;
  *   - outside the voxel box is vacuum; entry by the slab method;
  *   - majorant rounded up to float with a 2^-20 relative margin (Sec. 2.1);
  *   - direction update after a scatter: standard polar/azimuth rotation,
@@ -130,7 +133,7 @@ static double unif(uint32_t r) { return (double)(2u * (r >> 9) + 1u) * (1.0 / Q_
 double or_uniform(uint32_t r) { return unif(r); }
 
 /* Four uniforms of history h: counter (k, h_lo, h_hi, s); k = 0 is the
- * source, k >= 1 the k-th transport step; s = 1 only for the source's second
+ * source, k >= 1 the transport blocks; s = 1 only for the source's second
  * block (fluence-map beamlet). */
 static void block_s(const or_case *c, uint64_t h, uint32_t k, uint32_t s, double u[4]) {
   uint32_t ctr[4] = {k, (uint32_t)h, (uint32_t)(h >> 32), s};
@@ -141,6 +144,24 @@ static void block_s(const or_case *c, uint64_t h, uint32_t k, uint32_t s, double
 }
 
 static void block(const or_case *c, uint64_t h, uint32_t k, double u[4]) { block_s(c, h, k, 0u, u); }
+
+/* Transport uniforms of a history, taken two at a time in order: pair P
+ * (P = 0, 1, ...) is uniforms 2 (P mod 2) and 2 (P mod 2) + 1 of block
+ * floor(P / 2) + 1.  A Woodcock step takes the next pair (free path,
+ * selection); a Compton or Rayleigh scatter takes the pair after its step
+ * (polar-angle sample, azimuth). */
+typedef struct {
+  uint32_t P;     /* pairs taken */
+  double u[4];    /* the current block */
+} pairs_t;
+
+static void next_pair(const or_case *c, uint64_t h, pairs_t *s, double v[2]) {
+  const uint32_t half = s->P & 1u;
+  if (half == 0) block(c, h, s->P / 2u + 1u, s->u);
+  v[0] = s->u[2 * half];
+  v[1] = s->u[2 * half + 1];
+  s->P += 1;
+}
 
 /* ---------------- Tables: linear interpolation (Sec. 2.2.7 (3)) ---------------- */
 
@@ -466,10 +487,12 @@ static int history(const or_case *c, uint64_t h, int j, tally_t *t, log_t *L) {
   const double o3[3] = {c->ox, c->oy, c->oz};
   const double d3[3] = {c->dx, c->dy, c->dz};
   int scattered = 0;
+  pairs_t ps;
+  ps.P = 0;
   for (uint32_t k = 1;; ++k) {
-    if (k > K_MAX) return OR_ESTEPS;
-    double u[4];
-    block(c, h, k, u);
+    if (ps.P >= K_MAX) return OR_ESTEPS;   /* a guard on the pairs taken */
+    double u[2], v[2];
+    next_pair(c, h, &ps, u);
     int je;
     double we;
     egrid(c, E, &je, &we);
@@ -510,10 +533,11 @@ static int history(const or_case *c, uint64_t h, int j, tally_t *t, log_t *L) {
       t->n_real += 1; t->n_compton += 1;
       scattered = 1;
       const float *CS = c->comp_surf + (c->comp_per_mat ? (size_t)m * c->ne * c->nzeta : 0);
-      double mu = surface(CS, c->nzeta, je, we, u[2]);
+      next_pair(c, h, &ps, v);
+      double mu = surface(CS, c->nzeta, je, we, v[0]);
       double Ep = E / (1.0 + (E / ME_C2_KEV) * (1.0 - mu));
       deposit(t, vox, E - Ep);
-      rotate(d, mu, TWO_PI * u[3]);
+      rotate(d, mu, TWO_PI * v[1]);
       log_event(L, h, &seq, k, EV_COMPTON, vox, E - Ep, Ep);
       E = Ep;
       if (E < c->e_cut) {
@@ -526,8 +550,9 @@ static int history(const or_case *c, uint64_t h, int j, tally_t *t, log_t *L) {
       t->n_real += 1; t->n_rayleigh += 1;
       scattered = 1;
       const float *S = c->rayl_surf + (size_t)m * c->ne * c->nzeta;
-      double mu = surface(S, c->nzeta, je, we, u[2]);
-      rotate(d, mu, TWO_PI * u[3]);
+      next_pair(c, h, &ps, v);
+      double mu = surface(S, c->nzeta, je, we, v[0]);
+      rotate(d, mu, TWO_PI * v[1]);
       log_event(L, h, &seq, k, EV_RAYLEIGH, vox, 0.0, E);
     }
     /* else fictitious: state unchanged */

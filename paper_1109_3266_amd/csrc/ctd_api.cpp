@@ -1625,7 +1625,10 @@ extern "C" int32_t ctd_read_stats(ctd_ctx *ctx, ctd_case *cs, ctd_stats *out) {
   }
   out->sigma_local = cs->sigma_local;
   out->sigma_paper = cs->sigma_paper;
-  out->n_steps = a[ACC_N_STEPS];
+  // the step counter holds, per finished history, the random pairs it took
+  // (global majorant: one per step and one per scatter) or its flights (MACRO)
+  out->n_steps = cs->mc_cs > 0 ? a[ACC_N_STEPS]
+                               : a[ACC_N_STEPS] - a[ACC_N_COMPTON] - a[ACC_N_RAYLEIGH];
   out->n_photo = a[ACC_N_PHOTO];
   out->n_compton = a[ACC_N_COMPTON];
   out->n_rayleigh = a[ACC_N_RAYLEIGH];

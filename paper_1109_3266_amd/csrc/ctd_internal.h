@@ -51,7 +51,7 @@ constexpr int kTallyCopies = 8;         // one batch tally per XCD of an MI355X
 constexpr int kMacroBands = 16;         // MACRO tracking: most energy bands
 constexpr int kPackStats = 770;         // words of k_pack's statistics
 constexpr uint32_t kMixedClass = 255;   // bound grid: a block of several materials
-constexpr uint32_t kStepGuard = 1000000u;
+constexpr uint32_t kStepGuard = 1000000u;  // random pairs (MACRO: flights) a history may take
 constexpr float kInvMeC2 = (float)(1.0 / 510.99895);
 
 struct CaseDev {

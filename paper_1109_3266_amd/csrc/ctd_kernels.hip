@@ -52,10 +52,12 @@ constexpr int kCacheBytesPerWave = kCacheSlots * (8 + 4);
 // Dynamic LDS of a transport workgroup, in this order: a 16-byte header
 // (the workgroup's next case); the descriptor of the case the workgroup works
 // on and its 256-entry palette or bound-class table (every wave of a
-// workgroup works on the same case); per wave, its event counters; in tally
-// mode 2, each wave's sub-tally; where the tables fit, the case's majorant
-// nodes (padded to 16 B) and mu/rho rows.
+// workgroup works on the same case); per wave, its event counters and an
+// 8-byte word per lane (what a lane's waiting collision or scatter needs
+// later); in tally mode 2, each wave's sub-tally; where the tables fit, the
+// case's majorant nodes (padded to 16 B) and mu/rho rows.
 constexpr int kWaveAccBytes = (ACC_COUNT * 8 + 15) & ~15;
+constexpr int kWaveSlotBytes = kWaveAccBytes + 64 * 8;
 constexpr int kWaveCaseBytes = ((int)sizeof(CaseDev) + 15) & ~15;
 constexpr int kWgHeaderBytes = 16;
 constexpr int kWgCaseOff = kWgHeaderBytes;
@@ -286,8 +288,9 @@ struct Photon {
   float we;           // energy-grid weight
   int je;             // energy-grid cell
   uint32_t hlo, hhi;  // history id
-  uint32_t k;         // Woodcock step counter; bit 31 = has scattered
+  uint32_t k;         // random pairs taken (MACRO tracking: flights), flag bits
   uint32_t seq;       // event sequence (debug log only)
+  uint32_t ks;        // Woodcock steps taken (debug log only)
   // MACRO tracking: a flight (optical depth tau to spend) may span several
   // calls; its random words for the collision and its current cell persist
   float tau;            // < 0: no flight in progress
@@ -295,12 +298,16 @@ struct Photon {
   uint32_t cell;        // x | y << 10 | z << 20; all ones: take it from the position
 };
 
-// Photon.k: the Woodcock step count in the low bits, kScatBit once the photon
-// has scattered, kGoneBit while an escaped photon's counters wait for the
-// wave's next refill step (deferred collisions only).
+// Photon.k: in the low bits the random pairs the photon has taken (global
+// majorant) or its flights (MACRO tracking), kScatBit once the photon has
+// scattered, kGoneBit while an escaped photon's counters wait for the wave's
+// next refill step (deferred collisions), kDueBit while a scatter selected
+// at a block's second pair waits for the next block (plain steps; the
+// voxel, material and process wait in the lane's LDS slot).
 constexpr uint32_t kScatBit = 0x80000000u;
 constexpr uint32_t kGoneBit = 0x40000000u;
-constexpr uint32_t kStepMask = 0x3FFFFFFFu;
+constexpr uint32_t kDueBit = 0x20000000u;
+constexpr uint32_t kStepMask = 0x1FFFFFFFu;
 
 // mu/rho rows ti and ti + 1 (energy nodes je, je + 1 of one material): from
 // the workgroup's LDS copy (TAB) or through the caches.
@@ -371,7 +378,7 @@ __device__ __forceinline__ void log_event(const CaseDev &G, Photon &p, int type,
     ctd_event ev;
     ev.h = h;
     ev.seq = p.seq;
-    ev.k = p.k & kStepMask;
+    ev.k = p.ks;
     ev.type = type;
     ev.reserved = 0;
     ev.vox = vox;
@@ -424,6 +431,7 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
   p.hhi = (uint32_t)(h >> 32);
   p.k = 0;
   p.seq = 0;
+  p.ks = 0;
   p.tau = -1.0f;
   const uint4 r = philox10(0u, p.hlo, p.hhi, 0u, S.key0, S.key1);
   const float E = fmaf(unif(r.x), G.bin_width, G.bin_lo[j]);
@@ -530,69 +538,46 @@ __device__ __forceinline__ bool escape(Photon &p, const CaseDev &G, Counters &c,
   return false;
 }
 
-// Selection at a tentative collision (Sec. 2.1) in voxel vox of material m
-// and density rho, given the mass attenuation coefficients (a, b, cr) =
-// (photoelectric, Compton, Rayleigh) interpolated at E and xi = u1 * the
-// majorant: photoelectric, Compton, Rayleigh or fictitious by comparing xi
-// with the cumulative sums in that order; returns false when the photon is
-// done.
-template <bool LOG, bool TAB>
-__device__ __forceinline__ bool collide(Photon &p, const StepCase &S, const CaseDev &G,
-                                        Counters &c, const uint4 &r, uint32_t k, int32_t vox,
-                                        uint32_t m, float rho, float a, float b, float cr,
-                                        float xi) {
+// Outcome of the selection at a tentative collision; kSelPhoto and kSelDone
+// end the photon.
+constexpr int kSelFict = 0, kSelCompton = 1, kSelRayleigh = 2, kSelPhoto = 3, kSelDone = 4;
+
+// Selection at a tentative collision (Sec. 2.1) in voxel vox of density rho,
+// given the mass attenuation coefficients (a, b, cr) = (photoelectric,
+// Compton, Rayleigh) interpolated at E and xi = u1 * the majorant:
+// photoelectric, Compton, Rayleigh or fictitious by comparing xi with the
+// cumulative sums in that order.  A photoelectric absorption deposits E
+// locally here; nsteps is what the photon adds to the step counter when it
+// ends.
+template <bool LOG>
+__device__ __forceinline__ int select_process(Photon &p, const StepCase &S, const CaseDev &G,
+                                              Counters &c, int32_t vox, float rho, float a,
+                                              float b, float cr, float xi, uint32_t nsteps) {
   const float mpe = rho * a;
   const float c1 = mpe + rho * b;
   if (xi < mpe) {  // photoelectric: absorb, deposit E locally
-    c.add(ACC_N_STEPS, k);
+    c.add(ACC_N_STEPS, nsteps);
     c.add(ACC_N_PHOTO, 1);
     deposit<LOG>(S, G, p, c, vox, p.E, 1, 0.0f);
-    return false;
+    return kSelPhoto;
   }
-  if (xi < c1) {  // Compton (Sec. 2.2.3): angle from the C surface
-    c.add(ACC_N_COMPTON, 1);
-    p.k |= kScatBit;
-    // surface fields from the workgroup's LDS copy of the case (read only here)
-    const int nzc = G.nzc;
-    const GLOBAL float4 *Q = (const GLOBAL float4 *)G.comp_quad;
-    if (G.comp_per_mat) Q += (size_t)m * (size_t)(S.ne - 1) * (size_t)(nzc - 1);
-    const float mu = surface(Q, nzc, p.je, p.we, unif(r.z));
-    const float E = p.E;
-    const float Ep = E * __builtin_amdgcn_rcpf(fmaf(E * kInvMeC2, 1.0f - mu, 1.0f));
-    deposit<LOG>(S, G, p, c, vox, E - Ep, 2, Ep);  // exact: Ep > E/2 (Sterbenz)
-    rotate(p, mu, unif(r.w));
-    set_energy<TAB>(p, S, Ep);
-    if (Ep < G.e_cut) {
-      c.add(ACC_N_STEPS, k);
-      c.add(ACC_N_CUTOFF, 1);
-      deposit<LOG>(S, G, p, c, vox, Ep, 4, 0.0f);
-      return false;
-    }
-    return true;
-  }
+  if (xi < c1) return kSelCompton;
   if (S.rayleigh) {
     const float c2 = c1 + rho * cr;
-    if (xi < c2) {  // Rayleigh (Sec. 2.2.2): angle from the R surface, E unchanged
-      c.add(ACC_N_RAYLEIGH, 1);
-      p.k |= kScatBit;
-      const int nzr = G.nzr;
-      const GLOBAL float4 *Q =
-          (const GLOBAL float4 *)G.rayl_quad + (size_t)m * (size_t)(S.ne - 1) * (size_t)(nzr - 1);
-      const float mu = surface(Q, nzr, p.je, p.we, unif(r.z));
-      rotate(p, mu, unif(r.w));
-      log_event<LOG>(G, p, 3, vox, 0.0f, p.E);
-    }
+    if (xi < c2) return kSelRayleigh;
   }
-  return true;  // fictitious or scattered: keep going
+  return kSelFict;
 }
 
-// Tentative collision at voxel vox against majorant mumax: read the voxel
-// (1-byte palette index or 8-byte record), then select.
+// Tentative collision at voxel vox against majorant mumax with selection
+// word ry: read the voxel (1-byte palette index or 8-byte record) and its
+// table rows, then select; m receives the voxel's material.
 template <bool LOG, bool TAB>
-__device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const CaseDev &G,
-                                         const LOCAL uint2 *pal, Counters &c, const uint4 &r,
-                                         uint32_t k, int32_t vox, float mumax) {
-  uint32_t rbits, m;
+__device__ __forceinline__ int select_at(Photon &p, const StepCase &S, const CaseDev &G,
+                                         const LOCAL uint2 *pal, Counters &c, int32_t vox,
+                                         uint32_t ry, float mumax, uint32_t nsteps,
+                                         uint32_t &m) {
+  uint32_t rbits;
   if (S.npal) {  // 1-byte index into the workgroup's LDS palette
     const uint32_t i8 = S.vox8[vox];
     rbits = pal[i8].x;
@@ -607,61 +592,115 @@ __device__ __forceinline__ bool interact(Photon &p, const StepCase &S, const Cas
   table_rows<TAB>(S, ti, t0, t1);
   const float a = lerpf(t0.x, t1.x, p.we), b = lerpf(t0.y, t1.y, p.we);
   const float cr = S.rayleigh ? lerpf(t0.z, t1.z, p.we) : 0.0f;
-  return collide<LOG, TAB>(p, S, G, c, r, k, vox, m, __uint_as_float(rbits), a, b, cr,
-                      unif(r.y) * mumax);
+  return select_process<LOG>(p, S, G, c, vox, __uint_as_float(rbits), a, b, cr,
+                             unif(ry) * mumax, nsteps);
 }
 
-// One Woodcock step (Sec. 2.1) against the global majorant, every tentative
-// collision read from its voxel (cases with a bound grid take step_fast and
-// the collision passes instead); returns false when the photon is done.
+// Compton (sel = kSelCompton, Sec. 2.2.3) or Rayleigh (Sec. 2.2.2) scatter in
+// voxel vox of material m: the polar angle from the process's surface at
+// uniform w0, the azimuth from w1; returns false when the photon is done
+// (Compton below the cutoff).  nsteps as in select_process.
 template <bool LOG, bool TAB>
-__device__ __forceinline__ bool step(Photon &p, const StepCase &S, const CaseDev &G,
-                                     const LOCAL uint2 *pal, Counters &c) {
-  p.k += 1;
-  const uint32_t k = p.k & kStepMask;
-  if (k > kStepGuard) {
-    c.add(ACC_STEP_GUARD, 1);
-    c.add(ACC_N_STEPS, k);
-    return false;
+__device__ __forceinline__ bool scatter(Photon &p, const StepCase &S, const CaseDev &G,
+                                        Counters &c, int sel, int32_t vox, uint32_t m,
+                                        uint32_t w0, uint32_t w1, uint32_t nsteps) {
+  p.k |= kScatBit;
+  if (sel == kSelCompton) {
+    c.add(ACC_N_COMPTON, 1);
+    // surface fields from the workgroup's LDS copy of the case (read only here)
+    const int nzc = G.nzc;
+    const GLOBAL float4 *Q = (const GLOBAL float4 *)G.comp_quad;
+    if (G.comp_per_mat) Q += (size_t)m * (size_t)(S.ne - 1) * (size_t)(nzc - 1);
+    const float mu = surface(Q, nzc, p.je, p.we, unif(w0));
+    const float E = p.E;
+    const float Ep = E * __builtin_amdgcn_rcpf(fmaf(E * kInvMeC2, 1.0f - mu, 1.0f));
+    deposit<LOG>(S, G, p, c, vox, E - Ep, 2, Ep);  // exact: Ep > E/2 (Sterbenz)
+    rotate(p, mu, unif(w1));
+    set_energy<TAB>(p, S, Ep);
+    if (Ep < G.e_cut) {
+      c.add(ACC_N_STEPS, nsteps);
+      c.add(ACC_N_CUTOFF, 1);
+      deposit<LOG>(S, G, p, c, vox, Ep, 4, 0.0f);
+      return false;
+    }
+    return true;
   }
-  const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
-  const float s = -__log2f(unif(r.x)) * p.sc;  // -ln(u) / mu_max
+  c.add(ACC_N_RAYLEIGH, 1);
+  const int nzr = G.nzr;
+  const GLOBAL float4 *Q =
+      (const GLOBAL float4 *)G.rayl_quad + (size_t)m * (size_t)(S.ne - 1) * (size_t)(nzr - 1);
+  const float mu = surface(Q, nzr, p.je, p.we, unif(w0));
+  rotate(p, mu, unif(w1));
+  log_event<LOG>(G, p, 3, vox, 0.0f, p.E);
+  return true;
+}
+
+// Random words of the global-majorant steps: the history's transport blocks
+// are read two words (a pair) at a time in order; pair P (the low bits of
+// Photon.k count the pairs taken) is words 2 (P mod 2), 2 (P mod 2) + 1 of
+// block P / 2 + 1.  A step takes a pair (free path, selection), a Compton or
+// Rayleigh scatter the pair after its step (polar angle, azimuth).
+__device__ __forceinline__ uint4 pair_block(const Photon &p, const StepCase &S, uint32_t P) {
+  return philox10((P >> 1) + 1u, p.hlo, p.hhi, 0u, S.key0, S.key1);
+}
+
+// One Woodcock step (Sec. 2.1) against the global majorant with words w0
+// (free path) and w1 (selection), the tentative collision read from its voxel
+// (cases with a bound grid take step_fast and the collision passes instead).
+// Returns the selection; a Compton or Rayleigh scatter is left to the
+// caller, with the voxel and its material in vox and m.
+template <bool LOG, bool TAB>
+__device__ __forceinline__ int step(Photon &p, const StepCase &S, const CaseDev &G,
+                                    const LOCAL uint2 *pal, Counters &c, uint32_t w0,
+                                    uint32_t w1, int32_t &vox, uint32_t &m) {
+  const uint32_t P = p.k & kStepMask;
+  if (P >= kStepGuard) {
+    c.add(ACC_STEP_GUARD, 1);
+    c.add(ACC_N_STEPS, P);
+    return kSelDone;
+  }
+  p.k += 1;
+  if (LOG) p.ks += 1;
+  const float s = -__log2f(unif(w0)) * p.sc;  // -ln(u) / mu_max
   p.px = fmaf(s, p.ux * S.inv_dx, p.px);
   p.py = fmaf(s, p.uy * S.inv_dy, p.py);
   p.pz = fmaf(s, p.uz * S.inv_dz, p.pz);
   const bool inside = (p.px >= 0.0f) & (p.px < S.fnx) & (p.py >= 0.0f) & (p.py < S.fny) &
                       (p.pz >= 0.0f) & (p.pz < S.fnz);
-  if (!inside) return escape<LOG>(p, G, c, k);
+  if (!inside) {
+    escape<LOG>(p, G, c, P + 1u);
+    return kSelDone;
+  }
   const uint32_t ix = (uint32_t)p.px, iy = (uint32_t)p.py, iz = (uint32_t)p.pz;
-  const int32_t vox = (int32_t)__umul24(__umul24(iz, (uint32_t)S.ny) + iy, (uint32_t)S.nx) +
-                      (int32_t)ix;
-  return interact<LOG, TAB>(p, S, G, pal, c, r, k, vox, p.mumax);
+  vox = (int32_t)__umul24(__umul24(iz, (uint32_t)S.ny) + iy, (uint32_t)S.nx) + (int32_t)ix;
+  return select_at<LOG, TAB>(p, S, G, pal, c, vox, w1, p.mumax, P + 1u, m);
 }
 
-// One Woodcock step with deferred collisions (bound grid present): the fast
-// part of step() -- free path, move, exit test and the bound-grid rejection
-// of fictitious collisions -- for every live lane of the wave, leaving the
-// rest to the wave's next collision pass.  Returns kStepOn (fictitious,
-// decided by the bound), kStepPending (a tentative collision at *pvox that
-// needs the voxel: the collision pass reads it and selects exactly as
-// interact() does, with the step's random block recomputed from its counter),
-// kStepGone (left the box: kGoneBit set, its counters added at the next
-// refill step) or kStepDone (stopped by the step guard).
+// One Woodcock step with deferred collisions (bound grid present), words w0
+// (free path) and w1 (selection): the fast part of step() -- free path,
+// move, exit test and the bound-grid rejection of fictitious collisions --
+// for every live lane of the wave, leaving the rest to the wave's next
+// collision pass.  Returns kStepOn (fictitious, decided by the bound),
+// kStepPending (a tentative collision at *pvox that needs the voxel; w1 is
+// kept in the lane's LDS word *u1 for the pass, which reads the voxel and
+// selects as step() does), kStepGone (left the box: kGoneBit set, its
+// counters added at the next refill step) or kStepDone (stopped by the step
+// guard).
 constexpr int kStepOn = 0, kStepPending = 1, kStepGone = 2, kStepDone = 3;
 
 template <bool LOG, bool TAB>
-__device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const CaseDev &G,
-                                         const LOCAL uint2 *cls_tab, Counters &c,
-                                         int32_t &pvox) {
-  p.k += 1;
-  const uint32_t k = p.k & kStepMask;
-  if (k > kStepGuard) {
+__device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const LOCAL uint2 *cls_tab,
+                                         Counters &c, int32_t &pvox, LOCAL uint32_t *u1,
+                                         uint32_t w0, uint32_t w1) {
+  const uint32_t P = p.k & kStepMask;
+  if (P >= kStepGuard) {
     c.add(ACC_STEP_GUARD, 1);
-    c.add(ACC_N_STEPS, k);
+    c.add(ACC_N_STEPS, P);
     return kStepDone;
   }
-  const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
-  const float s = -__log2f(unif(r.x)) * p.sc;  // -ln(u) / mu_max
+  p.k += 1;
+  if (LOG) p.ks += 1;
+  const float s = -__log2f(unif(w0)) * p.sc;  // -ln(u) / mu_max
   p.px = fmaf(s, p.ux * S.inv_dx, p.px);
   p.py = fmaf(s, p.uy * S.inv_dy, p.py);
   p.pz = fmaf(s, p.uz * S.inv_dz, p.pz);
@@ -682,9 +721,10 @@ __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const Cas
   if (cls != kMixedClass) {
     const uint2 ce = cls_tab[cls];
     const float rho_c = __uint_as_float(ce.x);
-    if (unif(r.y) * p.mumax >= rho_c * bound_sum<TAB>(S, ce.y, p.je)) return kStepOn;
+    if (unif(w1) * p.mumax >= rho_c * bound_sum<TAB>(S, ce.y, p.je)) return kStepOn;
   }
   pvox = vox;
+  *u1 = w1;
   return kStepPending;
 }
 
@@ -705,6 +745,7 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
                                            const LOCAL uint2 *pal, Counters &c) {
   if (p.tau < 0.0f) {  // a new flight
     p.k += 1;
+    if (LOG) p.ks += 1;
     const uint32_t k0 = p.k & kStepMask;
     if (k0 > kStepGuard) {
       c.add(ACC_STEP_GUARD, 1);
@@ -797,7 +838,11 @@ __device__ __forceinline__ bool step_macro(Photon &p, const StepCase &S, const C
   const int iz = min(max((int)p.pz, cz * cs), min(cz * cs + cs, (int)S.fnz) - 1);
   const int32_t vox = (int32_t)__umul24(__umul24((uint32_t)iz, (uint32_t)S.ny) + (uint32_t)iy,
                                          (uint32_t)S.nx) + ix;
-  return interact<LOG, TAB>(p, S, G, pal, c, make_uint4(0u, p.ry, p.rz, p.rw), k, vox, mu_c);
+  uint32_t m;
+  const int sel = select_at<LOG, TAB>(p, S, G, pal, c, vox, p.ry, mu_c, k, m);
+  if (sel == kSelFict) return true;
+  if (sel == kSelPhoto) return false;
+  return scatter<LOG, TAB>(p, S, G, c, sel, vox, m, p.rz, p.rw, k);
 }
 
 // ------------------------------------------------------- transport kernel
@@ -871,8 +916,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
   CaseDev &G = *(CaseDev *)(base + kWgCaseOff);
   uint2 *pal = (uint2 *)(base + kWgPalOff);
   const LOCAL uint2 *pal_lds = (const LOCAL uint2 *)pal;
-  unsigned char *slot = base + kWgSlotsOff + w * kWaveAccBytes;
-  unsigned char *after_slots = base + kWgSlotsOff + nw * kWaveAccBytes;
+  unsigned char *slot = base + kWgSlotsOff + w * kWaveSlotBytes;
+  unsigned char *after_slots = base + kWgSlotsOff + nw * kWaveSlotBytes;
+  LOCAL uint2 *lane_word = (LOCAL uint2 *)(slot + kWaveAccBytes) + lane;
   // staged tables: the majorant nodes and mu/rho rows of the workgroup's
   // current case and its bound-test sums, shared by its waves (room for the
 // round's largest case)
@@ -1004,17 +1050,34 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
         const unsigned long long pm = __ballot(alive && pvox >= 0);
         if (pm && (__popcll(pm) >= defer_min || pm == __ballot(alive))) {
           if (alive && pvox >= 0) {
-            const uint32_t k = p.k & kStepMask;
-            const uint4 r = philox10(k, p.hlo, p.hhi, 0u, S.key0, S.key1);
-            alive = interact<LOG, TAB>(p, S, G, pal_lds, cnt, r, k, pvox, p.mumax);
+            // the step's selection word waited in the lane's LDS word
+            const uint32_t P = p.k & kStepMask;
+            uint32_t m;
+            const int sel =
+                select_at<LOG, TAB>(p, S, G, pal_lds, cnt, pvox, lane_word->y, p.mumax, P, m);
+            if (sel == kSelPhoto) {
+              alive = false;
+            } else if (sel != kSelFict) {   // the scatter takes the next pair
+              const uint4 q = pair_block(p, S, P);
+              const bool odd = (P & 1u) != 0u;
+              p.k += 1;
+              alive = scatter<LOG, TAB>(p, S, G, cnt, sel, pvox, m, odd ? q.z : q.x,
+                                        odd ? q.w : q.y, P + 1u);
+            }
             pvox = -1;
           }
         }
         // fast steps until a refill or a collision pass is due: a tight
-        // loop in which a photon's direction, energy and tables stay put
+        // loop in which a photon's direction, energy and tables stay put;
+        // one block serves two steps (a photon at an odd pair takes one)
         for (;;) {
           if (alive && pvox < 0) {
-            const int st = step_fast<LOG, TAB>(p, S, G, pal_lds, cnt, pvox);
+            const uint32_t P = p.k & kStepMask;
+            const uint4 r = pair_block(p, S, P);
+            LOCAL uint32_t *u1 = &lane_word->y;
+            int st = kStepOn;
+            if ((P & 1u) == 0u) st = step_fast<LOG, TAB>(p, S, pal_lds, cnt, pvox, u1, r.x, r.y);
+            if (st == kStepOn) st = step_fast<LOG, TAB>(p, S, pal_lds, cnt, pvox, u1, r.z, r.w);
             alive = st <= kStepPending;
           }
           const unsigned long long al = __ballot(alive);
@@ -1023,8 +1086,44 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
           if (pw && (__popcll(pw) >= defer_min || pw == al)) break;
         }
       } else {
-        for (;;) {   // steps until a refill is due
-          if (alive) alive = step<LOG, TAB>(p, S, G, pal_lds, cnt);
+        // steps until a refill is due, one block per pass of the loop: its
+        // first pair takes a step (and its second pair that step's scatter)
+        // or the scatter a photon left waiting; its second pair takes the
+        // next step, whose scatter then waits for the next block.  A photon
+        // starts every pass at an even pair.
+        for (;;) {
+          if (alive) {
+            const uint4 r = pair_block(p, S, p.k & kStepMask);
+            int sel;
+            int32_t vox = 0;
+            uint32_t m = 0, w0 = r.z, w1 = r.w;
+            if (p.k & kDueBit) {   // the waiting scatter takes the first pair
+              const uint2 lw = *lane_word;
+              vox = (int32_t)lw.x;
+              m = lw.y & 0xFFFFu;
+              sel = (int)(lw.y >> 16);
+              p.k &= ~kDueBit;
+              w0 = r.x;
+              w1 = r.y;
+            } else {
+              sel = step<LOG, TAB>(p, S, G, pal_lds, cnt, r.x, r.y, vox, m);
+            }
+            if (sel == kSelCompton || sel == kSelRayleigh) {
+              p.k += 1;
+              alive = scatter<LOG, TAB>(p, S, G, cnt, sel, vox, m, w0, w1, p.k & kStepMask);
+            } else if (sel >= kSelPhoto) {
+              alive = false;
+            }
+            if (alive && (p.k & 1u)) {   // the block's second pair: a step
+              sel = step<LOG, TAB>(p, S, G, pal_lds, cnt, r.z, r.w, vox, m);
+              if (sel == kSelCompton || sel == kSelRayleigh) {
+                *lane_word = make_uint2((uint32_t)vox, m | ((uint32_t)sel << 16));
+                p.k |= kDueBit;
+              } else if (sel >= kSelPhoto) {
+                alive = false;
+              }
+            }
+          }
           if (64 - __popcll(__ballot(alive)) >= refill_min) break;
         }
       }
@@ -1481,7 +1580,7 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
 
 size_t transport_lds_bytes(int block, int tally_mode, int tab_n, int tab_ne) {
   const size_t nw = (size_t)(block / 64);
-  size_t b = kWgSlotsOff + nw * kWaveAccBytes + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0);
+  size_t b = kWgSlotsOff + nw * kWaveSlotBytes + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0);
   // majorant nodes, mu/rho rows and (room for) the bound-test sums
   if (tab_n > 0) b += (size_t)((tab_ne + 3) & ~3) * 4 + (size_t)tab_n * 20;
   return b;
