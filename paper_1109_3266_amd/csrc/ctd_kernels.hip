@@ -18,9 +18,13 @@
 // E of a photoelectric or cutoff event) and every escape is an exact
 // multiple of q = 2^-24 keV for E < 256 keV, so deposits enter the int64 tally
 // exactly and incident = deposited + escaped holds exactly in q units.
-// Random numbers: Philox4x32-10 keyed by the case seed, counter (step k,
-// history id lo, hi, 0); k = 0 draws the source, step k >= 1 draws
-// (free path, interaction type, polar zeta, azimuth).  Two more streams use
+// Random numbers: Philox4x32-10 keyed by the case seed, counter (k,
+// history id lo, hi, 0); k = 0 draws the source.  With the global majorant
+// blocks k >= 1 are read two words (a pair) at a time: a Woodcock step takes
+// a pair (free path, interaction type), a Compton or Rayleigh scatter the
+// pair after its step (polar zeta, azimuth); with MACRO tracking flight k
+// takes block k (optical depth, interaction type, zeta, azimuth).  Two more
+// streams use
 // the fourth counter word: (0, h lo, h hi, 1) the fluence-map beamlet of
 // history h (inverse CDF, or trial and acceptance of Alg. A1), and
 // (0, c, 0, 2) the starting beamlet of Metropolis-Hastings chain c.
