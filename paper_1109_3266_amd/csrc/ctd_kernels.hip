@@ -639,6 +639,17 @@ __device__ __forceinline__ bool scatter(Photon &p, const StepCase &S, const Case
   return true;
 }
 
+// Step guard of the global-majorant steps, checked once per block: a photon
+// that has taken kStepGuard pairs stops (a runaway history, which
+// ctd_read_balance reports as an error); returns false then.
+__device__ __forceinline__ bool guard_ok(const Photon &p, Counters &c) {
+  const uint32_t P = p.k & kStepMask;
+  if (P < kStepGuard) return true;
+  c.add(ACC_STEP_GUARD, 1);
+  c.add(ACC_N_STEPS, P);
+  return false;
+}
+
 // Random words of the global-majorant steps: the history's transport blocks
 // are read two words (a pair) at a time in order; pair P (the low bits of
 // Photon.k count the pairs taken) is words 2 (P mod 2), 2 (P mod 2) + 1 of
@@ -652,17 +663,13 @@ __device__ __forceinline__ uint4 pair_block(const Photon &p, const StepCase &S, 
 // (free path) and w1 (selection), the tentative collision read from its voxel
 // (cases with a bound grid take step_fast and the collision passes instead).
 // Returns the selection; a Compton or Rayleigh scatter is left to the
-// caller, with the voxel and its material in vox and m.
+// caller, with the voxel and its material in vox and m.  The caller applies
+// the step guard, once per block.
 template <bool LOG, bool TAB>
 __device__ __forceinline__ int step(Photon &p, const StepCase &S, const CaseDev &G,
                                     const LOCAL uint2 *pal, Counters &c, uint32_t w0,
                                     uint32_t w1, int32_t &vox, uint32_t &m) {
   const uint32_t P = p.k & kStepMask;
-  if (P >= kStepGuard) {
-    c.add(ACC_STEP_GUARD, 1);
-    c.add(ACC_N_STEPS, P);
-    return kSelDone;
-  }
   p.k += 1;
   if (LOG) p.ks += 1;
   const float s = -__log2f(unif(w0)) * p.sc;  // -ln(u) / mu_max
@@ -687,21 +694,15 @@ __device__ __forceinline__ int step(Photon &p, const StepCase &S, const CaseDev 
 // collision pass.  Returns kStepOn (fictitious, decided by the bound),
 // kStepPending (a tentative collision at *pvox that needs the voxel; w1 is
 // kept in the lane's LDS word *u1 for the pass, which reads the voxel and
-// selects as step() does), kStepGone (left the box: kGoneBit set, its
-// counters added at the next refill step) or kStepDone (stopped by the step
-// guard).
-constexpr int kStepOn = 0, kStepPending = 1, kStepGone = 2, kStepDone = 3;
+// selects as step() does) or kStepGone (left the box: kGoneBit set, its
+// counters added at the next refill step).  The caller applies the step
+// guard, once per block.
+constexpr int kStepOn = 0, kStepPending = 1, kStepGone = 2;
 
 template <bool LOG, bool TAB>
 __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const LOCAL uint2 *cls_tab,
-                                         Counters &c, int32_t &pvox, LOCAL uint32_t *u1,
-                                         uint32_t w0, uint32_t w1) {
-  const uint32_t P = p.k & kStepMask;
-  if (P >= kStepGuard) {
-    c.add(ACC_STEP_GUARD, 1);
-    c.add(ACC_N_STEPS, P);
-    return kStepDone;
-  }
+                                         int32_t &pvox, LOCAL uint32_t *u1, uint32_t w0,
+                                         uint32_t w1) {
   p.k += 1;
   if (LOG) p.ks += 1;
   const float s = -__log2f(unif(w0)) * p.sc;  // -ln(u) / mu_max
@@ -1075,13 +1076,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
         // loop in which a photon's direction, energy and tables stay put;
         // one block serves two steps (a photon at an odd pair takes one)
         for (;;) {
-          if (alive && pvox < 0) {
+          if (alive && pvox < 0 && (alive = guard_ok(p, cnt))) {
             const uint32_t P = p.k & kStepMask;
             const uint4 r = pair_block(p, S, P);
             LOCAL uint32_t *u1 = &lane_word->y;
             int st = kStepOn;
-            if ((P & 1u) == 0u) st = step_fast<LOG, TAB>(p, S, pal_lds, cnt, pvox, u1, r.x, r.y);
-            if (st == kStepOn) st = step_fast<LOG, TAB>(p, S, pal_lds, cnt, pvox, u1, r.z, r.w);
+            if ((P & 1u) == 0u) st = step_fast<LOG, TAB>(p, S, pal_lds, pvox, u1, r.x, r.y);
+            if (st == kStepOn) st = step_fast<LOG, TAB>(p, S, pal_lds, pvox, u1, r.z, r.w);
             alive = st <= kStepPending;
           }
           const unsigned long long al = __ballot(alive);
@@ -1096,7 +1097,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
         // next step, whose scatter then waits for the next block.  A photon
         // starts every pass at an even pair.
         for (;;) {
-          if (alive) {
+          if (alive && (alive = guard_ok(p, cnt))) {
             const uint4 r = pair_block(p, S, p.k & kStepMask);
             int sel;
             int32_t vox = 0;
