@@ -726,3 +726,91 @@ def test_sigma_bar_definitions_by_hand():
     assert O.sigma_bar(dose, sd, rho, "paper") == pytest.approx((1 + 1.5 + 1) / 3 / 10)
     # local: D > 5 -> {10, 6}: mean(1/10, 1.5/6)
     assert O.sigma_bar(dose, sd, rho, "local") == pytest.approx((0.1 + 0.25) / 2)
+
+
+# ---------------- P9: the transport's random words (reading 7) ----------------
+
+def _pair(seed: int, h: int, P: int):
+    """Uniforms of pair P of history h, straight from Philox4x32-10: words
+    2 (P mod 2) and 2 (P mod 2) + 1 of block P // 2 + 1."""
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    w = O.philox([P // 2 + 1, h & 0xFFFFFFFF, h >> 32, 0], key)
+    return O.uniform(int(w[2 * (P % 2)])), O.uniform(int(w[2 * (P % 2) + 1]))
+
+
+def test_random_pairs_fictitious_steps_share_a_block():
+    """A photoelectric-only cube (water's table at density 20, so that a
+    photon takes several steps inside) under a doubled majorant: a tentative
+    collision is real when u1 mu_max < mu (probability about 1/2), so
+    histories take one, two, three ... steps.  Walking the pencil beam's axis
+    with the pairs read off the raw Philox blocks (free path -ln(u0)/mu_max)
+    must give, history by history, the step and voxel of the absorption or
+    the step of the escape that the oracle logs: this pins which words a step
+    takes, including a block's second pair after a fictitious step."""
+    wl = W.tiny(n_histories=1)
+    wl.rho = np.full_like(wl.rho, 20.0)
+    c = O.OracleCase(wl, mu_rho=_table_only(wl, [0]), majorant_scale=2.0)
+    je = int(round((60.0 - wl.e0) / wl.de))       # 60 keV is a node: weight 0
+    mumax = float(c.mu_max[je])
+    mu = 20.0 * float(c.mu_rho[0, je, 0])
+    assert 0.45 < mu / mumax < 0.55
+    steps = []
+    for h in range(400):
+        z, P = 0.0, 0                              # the beam enters at z = 0
+        while True:
+            u0, u1 = _pair(wl.seed, h, P)
+            P += 1
+            z += -math.log(u0) / mumax
+            if not (0.0 <= z / 0.5 < 32):
+                want = (O.EV_ESCAPE, P, -1)
+                break
+            if u1 * mumax < mu:
+                want = (O.EV_PHOTO, P, (int(math.floor(z / 0.5)) * 32 + 16) * 32 + 16)
+                break
+        ev = O.history(c, h, 0)
+        end = ev[np.isin(ev["type"], [O.EV_PHOTO, O.EV_ESCAPE])]
+        assert len(end) == 1
+        got = (int(end["type"][0]), int(end["k"][0]),
+               int(end["vox"][0]) if end["type"][0] == O.EV_PHOTO else -1)
+        assert got == want, f"history {h}"
+        steps.append(P)
+    steps = np.array(steps)
+    assert (steps >= 2).sum() > 100 and (steps >= 3).sum() > 40 and (steps >= 4).sum() > 15
+
+
+def test_random_pairs_scatter_takes_the_pair_after_its_step():
+    """A Compton-only water cube under a doubled majorant: walking the axis
+    with the pairs read off the raw Philox blocks, the first real collision
+    takes place at the predicted step and voxel, and its scatter takes the
+    next pair -- the same block's second pair after a step at a first pair,
+    the next block's first pair after a step at a second pair -- whose first
+    uniform is the surface sample: the logged energy of that Compton event
+    must be E - E' with E' the Compton relation at the angle the surface
+    gives for it."""
+    wl = W.tiny(n_histories=1)
+    c = O.OracleCase(wl, mu_rho=_table_only(wl, [1]), majorant_scale=2.0)
+    je = int(round((60.0 - wl.e0) / wl.de))
+    mumax = float(c.mu_max[je])
+    mu = float(c.mu_rho[0, je, 1])
+    parity = [0, 0]
+    for h in range(400):
+        z, P = 0.0, 0
+        while True:
+            u0, u1 = _pair(wl.seed, h, P)
+            P += 1
+            z += -math.log(u0) / mumax
+            if not (z / 0.5 < 32) or u1 * mumax < mu:
+                break
+        if not (z / 0.5 < 32):
+            continue                                # escaped before any collision
+        zeta, _ = _pair(wl.seed, h, P)             # the pair after the step
+        mu_c = float(O.sample_surface(c.comp, 60.0, [zeta], wl.e0, wl.de)[0])
+        Ep = 60.0 / (1.0 + (60.0 / O.ME_C2_KEV) * (1.0 - mu_c))
+        ev = O.history(c, h, 0)
+        first = ev[ev["type"] == O.EV_COMPTON][0]
+        assert int(first["k"]) == P, f"history {h}"
+        assert int(first["vox"]) == (int(math.floor(z / 0.5)) * 32 + 16) * 32 + 16
+        assert first["e"] == pytest.approx(60.0 - Ep, rel=1e-9, abs=1e-7), f"history {h}"
+        assert first["E"] == pytest.approx(Ep, rel=1e-12)
+        parity[(P - 1) % 2] += 1                   # the step's pair: first or second
+    assert parity[0] > 80 and parity[1] > 60
