@@ -186,6 +186,15 @@ def test_deposit_log_replay_bit_exact(ctx, shape, seed, tally_mode):
     assert np.array_equal(np.sort(ends["h"]), np.arange(10_000))
 
 
+# Paired histories: the GPU and the oracle draw the same random words for
+# each history id, so a history's events differ only where float32 and
+# float64 arithmetic fall on opposite sides of a tie (a voxel face, a
+# selection threshold).  Every pairing in this suite is observed at 1.0000;
+# the bar allows one such divergence per thousand histories, so a fault in
+# any branch that a thousandth of the histories take fails it.
+PAIR_MIN = 0.999
+
+
 def _pair_histories(gev, oev_by_h, hs):
     same = 0
     for h in hs:
@@ -212,7 +221,7 @@ def test_per_history_event_pairing(ctx, name, compton):
     by_h = {h: oev[oev["h"] == h] for h in range(5000)}
     frac = _pair_histories(g["log"], by_h, range(5000))
     say(f"identical histories {frac:.4f}")
-    assert frac >= 0.99
+    assert frac >= PAIR_MIN
 
 
 def test_independent_seeds(ctx):
@@ -375,7 +384,9 @@ def test_ragged_and_tiny_runs(ctx, n):
         bs = O.batch_sizes(n, wl.n_batches)
         hs = range(min(n, 500))
         by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
-        assert _pair_histories(ev, by_h, hs) >= 0.99
+        frac = _pair_histories(ev, by_h, hs)
+        say(f"ragged pairing {frac:.4f}")
+        assert frac >= PAIR_MIN
 
 
 def test_all_histories_miss(ctx):
@@ -567,7 +578,7 @@ def test_full_size_water_cbct_sampled(ctx):
     by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
     frac = _pair_histories(g["log"], by_h, hs)
     say(f"full-size pairing {frac:.4f}")
-    assert frac >= 0.99
+    assert frac >= PAIR_MIN
 
 
 def test_full_size_head_grid_sampled(ctx):
@@ -590,7 +601,7 @@ def test_full_size_head_grid_sampled(ctx):
     by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
     frac = _pair_histories(g["log"], by_h, hs)
     say(f"head pairing {frac:.4f}")
-    assert frac >= 0.99
+    assert frac >= PAIR_MIN
 
 
 @pytest.mark.parametrize("variant", ["head_helical", "head_bound_compton", "water_box_bowtie",
@@ -620,7 +631,7 @@ def test_full_size_variants_sampled(ctx, variant):
     by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
     frac = _pair_histories(g["log"], by_h, hs)
     say(f"{variant} pairing {frac:.4f}")
-    assert frac >= 0.99
+    assert frac >= PAIR_MIN
 
 
 def test_microbenchmarks_report_sane_rates(ctx):
