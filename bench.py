@@ -748,6 +748,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--serving-warmup", type=int, default=0,
                     help="leading requests left out of the latency percentiles")
+    ap.add_argument("--serving-rate", type=float, default=2.0,
+                    help="mean arrival rate of the Poisson trace [requests/s]")
     ap.add_argument("--serving-modes", default="global,auto",
                     help="tracking modes of the serving leg: global, auto or both")
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -838,9 +840,11 @@ def main():
         modes = set(args.serving_modes.split(","))
         if "global" in modes:
             out["serving"] = serving_leg(ctx, L, W, torch, args.serving_requests,
+                                         rate_hz=args.serving_rate,
                                          warmup_req=args.serving_warmup)
         if "auto" in modes:
             out["serving_auto_tracking"] = serving_leg(ctx, L, W, torch, args.serving_requests,
+                                                       rate_hz=args.serving_rate,
                                                        tracking=L.CTD_TRACK_AUTO,
                                                        warmup_req=args.serving_warmup)
     if "extensions" in legs:
