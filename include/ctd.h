@@ -177,6 +177,9 @@ typedef struct {
 typedef struct {
   double sigma_local;    /* CTD_SIGMA_LOCAL with f = 0.5 after the last run */
   double sigma_paper;    /* CTD_SIGMA_PAPER with f = 0.2 after the last run */
+  /* n_steps: Woodcock steps (MACRO tracking: flights); n_real: real
+   * collisions = n_photo + n_compton + n_rayleigh; n_refills: wave refill
+   * steps of the transport kernel */
   uint64_t n_steps, n_real, n_photo, n_compton, n_rayleigh, n_deposits,
       n_escapes, n_refills;
   double transport_ms;   /* GPU time of the transport launches (HIP events) */
