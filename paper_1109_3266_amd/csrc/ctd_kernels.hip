@@ -701,8 +701,8 @@ constexpr int kStepOn = 0, kStepPending = 1, kStepGone = 2;
 
 template <bool LOG, bool TAB>
 __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const LOCAL uint2 *cls_tab,
-                                         int32_t &pvox, LOCAL uint32_t *u1, uint32_t w0,
-                                         uint32_t w1) {
+                                         const GLOBAL uint8_t *bgrid, int32_t &pvox,
+                                         LOCAL uint32_t *u1, uint32_t w0, uint32_t w1) {
   p.k += 1;
   if (LOG) p.ks += 1;
   const float s = -__log2f(unif(w0)) * p.sc;  // -ln(u) / mu_max
@@ -722,7 +722,7 @@ __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const LOC
   const uint32_t bgx = ((uint32_t)S.nx + e) >> S.bshift, bgy = ((uint32_t)S.ny + e) >> S.bshift;
   const uint32_t blk = __umul24(__umul24(iz >> S.bshift, bgy) + (iy >> S.bshift), bgx) +
                        (ix >> S.bshift);
-  const uint32_t cls = S.bgrid[blk];
+  const uint32_t cls = bgrid[blk];
   if (cls != kMixedClass) {
     const uint2 ce = cls_tab[cls];
     const float rho_c = __uint_as_float(ce.x);
@@ -1080,9 +1080,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
             const uint32_t P = p.k & kStepMask;
             const uint4 r = pair_block(p, S, P);
             LOCAL uint32_t *u1 = &lane_word->y;
+            // the bound grid's address into scalar registers once per block
+            // (held in vector registers, it was re-read before every step)
+            const GLOBAL uint8_t *bg = uniform_ptr(S.bgrid);
             int st = kStepOn;
-            if ((P & 1u) == 0u) st = step_fast<LOG, TAB>(p, S, pal_lds, pvox, u1, r.x, r.y);
-            if (st == kStepOn) st = step_fast<LOG, TAB>(p, S, pal_lds, pvox, u1, r.z, r.w);
+            if ((P & 1u) == 0u) st = step_fast<LOG, TAB>(p, S, pal_lds, bg, pvox, u1, r.x, r.y);
+            if (st == kStepOn) st = step_fast<LOG, TAB>(p, S, pal_lds, bg, pvox, u1, r.z, r.w);
             alive = st <= kStepPending;
           }
           const unsigned long long al = __ballot(alive);
