@@ -523,9 +523,12 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
     return false;
   }
   // entry point, kept inside [0, n) against rounding
-  p.px = fminf(fmaxf(fmaf(tin, D[0], Sv[0]), 0.0f), __int_as_float(__float_as_int(N[0]) - 1));
-  p.py = fminf(fmaxf(fmaf(tin, D[1], Sv[1]), 0.0f), __int_as_float(__float_as_int(N[1]) - 1));
-  p.pz = fminf(fmaxf(fmaf(tin, D[2], Sv[2]), 0.0f), __int_as_float(__float_as_int(N[2]) - 1));
+  // (+ 0.0f turns a -0 into +0 and leaves every other value as it is; a
+  // step's fma from a position that is not -0 never gives -0, so positions
+  // are never -0: see inside_box)
+  p.px = fminf(fmaxf(fmaf(tin, D[0], Sv[0]), 0.0f), __int_as_float(__float_as_int(N[0]) - 1)) + 0.0f;
+  p.py = fminf(fmaxf(fmaf(tin, D[1], Sv[1]), 0.0f), __int_as_float(__float_as_int(N[1]) - 1)) + 0.0f;
+  p.pz = fminf(fmaxf(fmaf(tin, D[2], Sv[2]), 0.0f), __int_as_float(__float_as_int(N[2]) - 1)) + 0.0f;
   p.ux = dx; p.uy = dy; p.uz = dz;
   set_energy<TAB>(p, S, E);
   return true;
@@ -639,6 +642,17 @@ __device__ __forceinline__ bool scatter(Photon &p, const StepCase &S, const Case
   return true;
 }
 
+// 0 <= position < n on each axis, as one unsigned compare of the float bits:
+// positions are finite and never -0 (the entry point is made +0, and a
+// step's fma x + s d from an x that is not -0 cannot give -0), and for such
+// floats the bits order like the values while any negative one, sign bit
+// set, compares above every positive bound.
+__device__ __forceinline__ bool inside_box(const Photon &p, const StepCase &S) {
+  return (__float_as_uint(p.px) < __float_as_uint(S.fnx)) &
+         (__float_as_uint(p.py) < __float_as_uint(S.fny)) &
+         (__float_as_uint(p.pz) < __float_as_uint(S.fnz));
+}
+
 // Step guard of the global-majorant steps, checked once per block: a photon
 // that has taken kStepGuard pairs stops (a runaway history, which
 // ctd_read_balance reports as an error); returns false then.
@@ -676,8 +690,7 @@ __device__ __forceinline__ int step(Photon &p, const StepCase &S, const CaseDev 
   p.px = fmaf(s, p.ux * S.inv_dx, p.px);
   p.py = fmaf(s, p.uy * S.inv_dy, p.py);
   p.pz = fmaf(s, p.uz * S.inv_dz, p.pz);
-  const bool inside = (p.px >= 0.0f) & (p.px < S.fnx) & (p.py >= 0.0f) & (p.py < S.fny) &
-                      (p.pz >= 0.0f) & (p.pz < S.fnz);
+  const bool inside = inside_box(p, S);
   if (!inside) {
     escape<LOG>(p, G, c, P + 1u);
     return kSelDone;
@@ -709,8 +722,7 @@ __device__ __forceinline__ int step_fast(Photon &p, const StepCase &S, const LOC
   p.px = fmaf(s, p.ux * S.inv_dx, p.px);
   p.py = fmaf(s, p.uy * S.inv_dy, p.py);
   p.pz = fmaf(s, p.uz * S.inv_dz, p.pz);
-  const bool inside = (p.px >= 0.0f) & (p.px < S.fnx) & (p.py >= 0.0f) & (p.py < S.fny) &
-                      (p.pz >= 0.0f) & (p.pz < S.fnz);
+  const bool inside = inside_box(p, S);
   if (!inside) {
     p.k |= kGoneBit;
     return kStepGone;
