@@ -642,11 +642,12 @@ __device__ __forceinline__ bool scatter(Photon &p, const StepCase &S, const Case
   return true;
 }
 
-// 0 <= position < n on each axis, as one unsigned compare of the float bits:
-// positions are finite and never -0 (the entry point is made +0, and a
-// step's fma x + s d from an x that is not -0 cannot give -0), and for such
-// floats the bits order like the values while any negative one, sign bit
-// set, compares above every positive bound.
+// 0 <= position < n on each axis, as one unsigned compare of the float bits.
+// Positions are never -0 (the entry point is made +0, and a step's fma
+// x + s d from an x that is not -0 cannot give -0); for the other floats the
+// bits of non-negative values order like the values, while negative values,
+// infinities and NaNs (sign bit set, or exponent all ones) compare above
+// every finite positive bound -- outside, as the two float compares say.
 __device__ __forceinline__ bool inside_box(const Photon &p, const StepCase &S) {
   return (__float_as_uint(p.px) < __float_as_uint(S.fnx)) &
          (__float_as_uint(p.py) < __float_as_uint(S.fny)) &
