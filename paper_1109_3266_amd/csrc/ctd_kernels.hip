@@ -93,8 +93,10 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 }
 
 // (2 (r >> 9) + 1) 2^-24 exactly: [1,2) mantissa trick minus (1 - 2^-24).
+// The float 1.m with m = r >> 9 is bits [40:9] of the 64-bit {0x7F, r}: one
+// v_alignbit_b32 instead of a shift and an or.
 __device__ __forceinline__ float unif(uint32_t r) {
-  return __uint_as_float((r >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9u)) - 0x1.fffffep-1f;
 }
 
 __device__ __forceinline__ float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
