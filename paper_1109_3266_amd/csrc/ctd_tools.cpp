@@ -21,23 +21,31 @@ struct Dev {
   }
 };
 
+// One search offset, laid out as the kernel's double4 (four doubles) but
+// with the alignment of a double: std::stable_sort's temporary buffer is not
+// aligned for the 32-byte HIP vector type.
+struct Offset {
+  double x, y, z, r2;
+};
+static_assert(sizeof(Offset) == sizeof(double4), "Offset must match double4");
+
 // Lattice offsets h*(i,j,k), h = dta/substeps, with |offset| <= cap*dta, as
 // (voxel-unit x, y, z, |offset|^2/dta^2), ascending in distance.
-std::vector<double4> gamma_offsets(const ctd_grid &g, const ctd_gamma_params &p) {
+std::vector<Offset> gamma_offsets(const ctd_grid &g, const ctd_gamma_params &p) {
   const int s = p.substeps;
   const double rmax = p.gamma_cap * s;          // radius in lattice steps
   const int L = (int)std::ceil(rmax);
   const double h = p.dta_cm / s;
-  std::vector<double4> out;
+  std::vector<Offset> out;
   for (int k = -L; k <= L; ++k)
     for (int j = -L; j <= L; ++j)
       for (int i = -L; i <= L; ++i) {
         const double r2 = (double)(i * i + j * j + k * k);
         if (r2 > rmax * rmax) continue;
-        out.push_back(make_double4(i * h / g.dx, j * h / g.dy, k * h / g.dz, r2 / ((double)s * s)));
+        out.push_back(Offset{i * h / g.dx, j * h / g.dy, k * h / g.dz, r2 / ((double)s * s)});
       }
   std::stable_sort(out.begin(), out.end(),
-                   [](const double4 &a, const double4 &b) { return a.w < b.w; });
+                   [](const Offset &a, const Offset &b) { return a.r2 < b.r2; });
   return out;
 }
 
@@ -58,7 +66,7 @@ extern "C" int32_t ctd_gamma(ctd_ctx *ctx, const ctd_grid *g, const float *ref, 
     return set_err(ctx, CTD_EINVAL, "dose_tol and dta_cm must be > 0, region_min finite");
   if (!(p->gamma_cap >= 1.0 && p->gamma_cap <= 4.0) || p->substeps < 1 || p->substeps > 20)
     return set_err(ctx, CTD_EINVAL, "need 1 <= gamma_cap <= 4 and 1 <= substeps <= 20");
-  const std::vector<double4> offs = gamma_offsets(*g, *p);
+  const std::vector<Offset> offs = gamma_offsets(*g, *p);
   if ((int64_t)offs.size() > kMaxOffsets)
     return set_err(ctx, CTD_EINVAL, "%zu search offsets exceed %d", offs.size(), kMaxOffsets);
   const int64_t V = (int64_t)g->nx * g->ny * g->nz;
@@ -66,7 +74,7 @@ extern "C" int32_t ctd_gamma(ctd_ctx *ctx, const ctd_grid *g, const float *ref, 
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, CTD_EDEVICE, "hipSetDevice");
   Dev d_offs, d_cnt, d_ref, d_ev, d_gam;
   hipError_t e;
-  if ((e = hipMalloc(&d_offs.p, sizeof(double4) * offs.size())) != hipSuccess ||
+  if ((e = hipMalloc(&d_offs.p, sizeof(Offset) * offs.size())) != hipSuccess ||
       (e = hipMalloc(&d_cnt.p, 2 * sizeof(unsigned long long))) != hipSuccess)
     return hip_err(ctx, e, "gamma alloc");
   const float *r = ref, *v = ev;
@@ -83,7 +91,7 @@ extern "C" int32_t ctd_gamma(ctd_ctx *ctx, const ctd_grid *g, const float *ref, 
     v = (const float *)d_ev.p;
     gout = (float *)d_gam.p;
   }
-  if ((e = hipMemcpyAsync(d_offs.p, offs.data(), sizeof(double4) * offs.size(),
+  if ((e = hipMemcpyAsync(d_offs.p, offs.data(), sizeof(Offset) * offs.size(),
                           hipMemcpyHostToDevice, st)) != hipSuccess)
     return hip_err(ctx, e, "gamma upload");
   if (launch_zero(d_cnt.p, 2 * sizeof(unsigned long long), st) != 0 ||
