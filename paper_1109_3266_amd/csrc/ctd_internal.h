@@ -204,8 +204,8 @@ bool transport_lds_fits(int block, int tally_mode, int device);
 // Dynamic LDS of a transport workgroup: its header, case descriptor and
 // class table, per-wave counters, the tally-mode-2 sub-tallies, and room for
 // tab_n mu/rho rows, tab_ne majorant nodes and tab_n bound-test sums (0:
-// none).
-size_t transport_lds_bytes(int block, int tally_mode, int tab_n, int tab_ne);
+// none), and a source stash of stash_cap records per wave.
+size_t transport_lds_bytes(int block, int tally_mode, int tab_n, int tab_ne, int stash_cap);
 // Fold ncopies batch tallies [ncopies][V]: S1 += sum, S2 += sum^2, zero them;
 // fold the batch counters of acc into its 128-bit totals and record the
 // per-voxel maxima of S1 and of S2's high word.

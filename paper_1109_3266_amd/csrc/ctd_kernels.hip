@@ -58,9 +58,13 @@ constexpr int kCacheBytesPerWave = kCacheSlots * (8 + 4);
 // on and its 256-entry palette or bound-class table (every wave of a
 // workgroup works on the same case); per wave, its event counters and an
 // 8-byte word per lane (what a lane's waiting collision or scatter needs
-// later); in tally mode 2, each wave's sub-tally; where the tables fit, the
-// case's majorant nodes (padded to 16 B) and mu/rho rows.
+// later); in tally mode 2, each wave's sub-tally; per wave, its source
+// stash of stash_cap records (stash_cap entry points and energies as float4,
+// then stash_cap directions as float4, w = the record's history offset);
+// where the tables fit, the case's majorant nodes (padded to 16 B) and mu/rho
+// rows.
 constexpr int kWaveAccBytes = (ACC_COUNT * 8 + 15) & ~15;
+constexpr int kStashRecBytes = 32;
 constexpr int kWaveSlotBytes = kWaveAccBytes + 64 * 8;
 constexpr int kWaveCaseBytes = ((int)sizeof(CaseDev) + 15) & ~15;
 constexpr int kWgHeaderBytes = 16;
@@ -428,17 +432,19 @@ __device__ __forceinline__ void deposit(const StepCase &S, const CaseDev &G, Pho
   log_event<LOG>(G, p, type, vox, e, Eafter);
 }
 
-// Source photon of history h from spectrum bin j (Sec. 2.2.5-2.2.6); returns
-// false when the ray misses the voxel box (the photon escapes at once).
-template <bool LOG, bool TAB>
-__device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t h, int j,
-                       const int32_t *__restrict__ mh_beam, uint64_t local, Counters &c) {
+// Source photon of history h from spectrum bin j (Sec. 2.2.5-2.2.6): its
+// entry point into the voxel box (voxel units) and energy in pe, its unit
+// direction in dir.xyz; returns false when the ray misses the box (the photon
+// escapes at once).  Its start event is logged here (event 0 of the history).
+template <bool LOG>
+__device__ bool source(const StepCase &S, const CaseDev &G, uint64_t h, int j,
+                       const int32_t *__restrict__ mh_beam, uint64_t local, Counters &c,
+                       float4 &pe, float4 &dir) {
+  Photon p;   // only the history id and log fields are used here
   p.hlo = (uint32_t)h;
   p.hhi = (uint32_t)(h >> 32);
-  p.k = 0;
   p.seq = 0;
   p.ks = 0;
-  p.tau = -1.0f;
   const uint4 r = philox10(0u, p.hlo, p.hhi, 0u, S.key0, S.key1);
   const float E = fmaf(unif(r.x), G.bin_width, G.bin_lo[j]);
   float sx, sy, sz, dx, dy, dz;
@@ -498,7 +504,6 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
   }
   c.add(ACC_N_HIST, 1);
   c.add(ACC_Q_INC, (uint32_t)(E * kQScale));
-  p.E = E;
   log_event<LOG>(G, p, 0, beamlet, E, E);
   // slab entry into the box [0, n) in voxel units
   const float Sv[3] = {(sx - G.ox) * S.inv_dx, (sy - G.oy) * S.inv_dy, (sz - G.oz) * S.inv_dz};
@@ -528,11 +533,11 @@ __device__ bool source(Photon &p, const StepCase &S, const CaseDev &G, uint64_t 
   // (+ 0.0f turns a -0 into +0 and leaves every other value as it is; a
   // step's fma from a position that is not -0 never gives -0, so positions
   // are never -0: see inside_box)
-  p.px = fminf(fmaxf(fmaf(tin, D[0], Sv[0]), 0.0f), __int_as_float(__float_as_int(N[0]) - 1)) + 0.0f;
-  p.py = fminf(fmaxf(fmaf(tin, D[1], Sv[1]), 0.0f), __int_as_float(__float_as_int(N[1]) - 1)) + 0.0f;
-  p.pz = fminf(fmaxf(fmaf(tin, D[2], Sv[2]), 0.0f), __int_as_float(__float_as_int(N[2]) - 1)) + 0.0f;
-  p.ux = dx; p.uy = dy; p.uz = dz;
-  set_energy<TAB>(p, S, E);
+  pe.x = fminf(fmaxf(fmaf(tin, D[0], Sv[0]), 0.0f), __int_as_float(__float_as_int(N[0]) - 1)) + 0.0f;
+  pe.y = fminf(fmaxf(fmaf(tin, D[1], Sv[1]), 0.0f), __int_as_float(__float_as_int(N[1]) - 1)) + 0.0f;
+  pe.z = fminf(fmaxf(fmaf(tin, D[2], Sv[2]), 0.0f), __int_as_float(__float_as_int(N[2]) - 1)) + 0.0f;
+  pe.w = E;
+  dir.x = dx; dir.y = dy; dir.z = dz;
   return true;
 }
 
@@ -925,7 +930,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
                                                    uint64_t total_chunks,
                                                    unsigned long long *chunk_ctr, int refill_min,
                                                    int chunk, int tally_mode, int bound_shift,
-                                                   int defer_min, int tab_n, int tab_ne) {
+                                                   int defer_min, int tab_n, int tab_ne,
+                                                   int stash_cap) {
   extern __shared__ unsigned long long dyn_lds[];   // layout: see kWgSlotsOff
   const int lane = __lane_id();
   const int w = threadIdx.x >> 6;
@@ -945,8 +951,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
   LOCAL float *tabmax = nullptr;
   LOCAL float4 *tab = nullptr;
   LOCAL float *tabbnd = nullptr;
+  unsigned char *after_cache = after_slots + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0);
+  LOCAL float4 *st_a = (LOCAL float4 *)(after_cache + w * stash_cap * kStashRecBytes);
+  LOCAL float4 *st_b = st_a + stash_cap;
   if (TAB) {
-    tabmax = (LOCAL float *)(after_slots + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0));
+    tabmax = (LOCAL float *)(after_cache + nw * stash_cap * kStashRecBytes);
     tab = (LOCAL float4 *)(tabmax + ((tab_ne + 3) & ~3));
     tabbnd = (LOCAL float *)(tab + tab_n);
   }
@@ -972,6 +981,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
   StepCase S;
   uint64_t pool_next = 0, pool_end = 0;  // local history indices of case c
   int wbin = 0;                          // bin of pool_next
+  // the stash: records [st_pos, st_n) are sources not yet handed out, of the
+  // histories st_base + their offsets
+  uint64_t st_base = 0;
+  uint32_t st_pos = 0, st_n = 0;
   bool first = true, claims_done = false;
   uint32_t refills = 0;
   Photon p;
@@ -994,6 +1007,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
     __syncthreads();   // case and tables staged before any wave steps
     pool_next = pool_end = 0;
     wbin = 0;
+    st_pos = st_n = 0;
     first = true;
     claims_done = false;
     refills = 0;
@@ -1007,57 +1021,99 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(5))) k
           p.k &= ~kGoneBit;
           escape<LOG>(p, G, cnt, p.k & kStepMask);
         }
-        // claim a chunk of case c when the pool is empty
-        while (pool_next >= pool_end && !claims_done) {
-          uint64_t t;
-          if (home && first) {
-            t = (uint64_t)__builtin_amdgcn_readfirstlane(
-                (blockIdx.x - rcs[c].wg_lo) * (uint32_t)nw + (uint32_t)w);
-          } else {
-            unsigned long long a = 0;
-            if (lane == 0) a = atomicAdd(chunk_ctr + c, 1ull);
-            t = rcs[c].home_waves + lane0_u64(a);
+        // idle lanes take the stash's records in order, lowest lanes first;
+        // an empty stash is refilled from the pool (a chunk of case c is
+        // claimed when the pool is empty) with the sources of the pool's
+        // next stash_cap ids, sampled by the whole wave at once
+        const bool want = !alive;
+        const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
+        uint32_t filled = 0;
+        for (;;) {
+          if (st_pos < st_n) {
+            const uint32_t take = min((uint32_t)ndead - filled, st_n - st_pos);
+            if (want && rank >= filled && rank < filled + take) {
+              const uint32_t i = st_pos + (rank - filled);
+              const float4 a = st_a[i], b = st_b[i];
+              const uint64_t h = rcs[c].h_begin + st_base + __float_as_uint(b.w);
+              p.hlo = (uint32_t)h;
+              p.hhi = (uint32_t)(h >> 32);
+              p.k = 0;
+              p.seq = LOG ? 1u : 0u;   // event 0 (the start) was logged at sampling
+              p.ks = 0;
+              p.tau = -1.0f;
+              p.px = a.x; p.py = a.y; p.pz = a.z;
+              p.ux = b.x; p.uy = b.y; p.uz = b.z;
+              set_energy<TAB>(p, S, a.w);
+              alive = true;
+            }
+            st_pos += take;
+            filled += take;
+            if (filled == (uint32_t)ndead) break;
           }
-          if (t >= case_chunk_count(rcs, nrc, total_chunks, c)) {
-            claims_done = true;
-            break;
+          while (pool_next >= pool_end && !claims_done) {
+            uint64_t t;
+            if (home && first) {
+              t = (uint64_t)__builtin_amdgcn_readfirstlane(
+                  (blockIdx.x - rcs[c].wg_lo) * (uint32_t)nw + (uint32_t)w);
+            } else {
+              unsigned long long a = 0;
+              if (lane == 0) a = atomicAdd(chunk_ctr + c, 1ull);
+              t = rcs[c].home_waves + lane0_u64(a);
+            }
+            if (t >= case_chunk_count(rcs, nrc, total_chunks, c)) {
+              claims_done = true;
+              break;
+            }
+            const uint64_t lo = t * (uint64_t)chunk;
+            const uint64_t hi = min(lo + (uint64_t)chunk, rcs[c].n);
+            // the wave's step constants at its first chunk; a wave's claims
+            // of one case increase, so later bin searches start from the last
+            if (first) {
+              S = make_step_case(G, tally_mode, bound_shift, cache);
+              S.tab = tab;
+              S.tabmax = tabmax;
+              S.tabbnd = tabbnd;
+              wbin = find_bin(rcs[c].prefix, G.nbins, lo);
+            }
+            first = false;
+            pool_next = lo;
+            pool_end = hi;
           }
-          const uint64_t lo = t * (uint64_t)chunk;
-          const uint64_t hi = min(lo + (uint64_t)chunk, rcs[c].n);
-          // the wave's step constants at its first chunk; a wave's claims
-          // of one case increase, so later bin searches start from the last
-          if (first) {
-            S = make_step_case(G, tally_mode, bound_shift, cache);
-            S.tab = tab;
-            S.tabmax = tabmax;
-            S.tabbnd = tabbnd;
-            wbin = find_bin(rcs[c].prefix, G.nbins, lo);
-          }
-          first = false;
-          pool_next = lo;
-          pool_end = hi;
-        }
-        // hand out pool ids to idle lanes, lowest lanes first
-        if (pool_next < pool_end && ndead > 0) {
-          const uint64_t avail = pool_end - pool_next;
-          const uint32_t m = (uint32_t)min((uint64_t)ndead, avail);
-          const uint32_t rank = (uint32_t)__popcll(dead & lt_mask);
+          if (pool_next >= pool_end) break;   // nothing left to hand out
+          // sample: lane l takes pool id pool_next + l; the records of the
+          // photons that enter the box are stored compacted, in id order
           const RoundCase &R = rcs[c];
-          if (!alive && rank < m) {
-            const uint64_t local = pool_next + rank;
+          const uint32_t ng = (uint32_t)min((uint64_t)stash_cap, pool_end - pool_next);
+          const uint64_t local = pool_next + (uint64_t)lane;
+          bool ok = false;
+          float4 pe, dir;
+          if ((uint32_t)lane < ng) {
             int j = wbin;
             while (j + 1 < G.nbins && local >= R.prefix[j + 1]) ++j;
-            alive = source<LOG, TAB>(p, S, G, R.h_begin + local, j, R.beamlets, local, cnt);
+            ok = source<LOG>(S, G, R.h_begin + local, j, R.beamlets, local, cnt, pe, dir);
           }
-          pool_next += m;
-          refills += 1;
+          const unsigned long long okm = __ballot(ok);
+          __builtin_amdgcn_wave_barrier();   // the last records were read
+          if (ok) {
+            const uint32_t i = (uint32_t)__popcll(okm & lt_mask);
+            dir.w = __uint_as_float((uint32_t)lane);
+            st_a[i] = pe;
+            st_b[i] = dir;
+          }
+          __builtin_amdgcn_wave_barrier();   // records written before any lane reads them
+          st_base = pool_next;
+          st_pos = 0;
+          st_n = (uint32_t)__popcll(okm);
+          pool_next += ng;
           if (pool_next < pool_end) {
             while (wbin + 1 < G.nbins && pool_next >= R.prefix[wbin + 1]) ++wbin;
           }
         }
+        if (filled > 0) refills += 1;
       }
       if (__ballot(alive) == 0ull) {
-        if (claims_done && pool_next >= pool_end) break;   // case c done for this wave
+        // case c done for this wave
+        if (claims_done && pool_next >= pool_end && st_pos >= st_n) break;
         continue;
       }
       if constexpr (KIND == kStepMacro) {
@@ -1577,15 +1633,24 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
   hipStream_t s = (hipStream_t)stream;
   // stage the tables (room for the round's largest case) only where the
   // workgroup's LDS then still allows the resident workgroups the grid is
-  // sized for
-  int tab_n = cfg.tab_n;
-  size_t lds = transport_lds_bytes(cfg.block, cfg.tally_mode, 0, 0);
+  // sized for, with the largest source stash (64, 32 or 16 records per wave)
+  // that fits beside them; without the tables, the largest stash that fits
+  // (16 at least)
+  int tab_n = cfg.tab_n, cap = 0;
   if (tab_n > 0) {
-    const size_t with = transport_lds_bytes(cfg.block, cfg.tally_mode, tab_n, cfg.tab_ne);
-    if (with <= cfg.lds_budget) lds = with; else tab_n = 0;
+    for (int c = 64; c >= 16 && !cap; c >>= 1)
+      if (transport_lds_bytes(cfg.block, cfg.tally_mode, tab_n, cfg.tab_ne, c) <= cfg.lds_budget)
+        cap = c;
+    if (!cap) tab_n = 0;
   }
+  if (!cap) {
+    cap = 16;
+    for (int c = 64; c > 16 && cap == 16; c >>= 1)
+      if (transport_lds_bytes(cfg.block, cfg.tally_mode, 0, 0, c) <= cfg.lds_budget) cap = c;
+  }
+  const size_t lds = transport_lds_bytes(cfg.block, cfg.tally_mode, tab_n, cfg.tab_ne, cap);
   using Kern = void (*)(const RoundCase *, int, uint64_t, unsigned long long *, int, int, int,
-                        int, int, int, int);
+                        int, int, int, int, int);
   static const Kern kerns[2][3][2] = {
       {{k_transport<false, kStepPlain, false>, k_transport<false, kStepPlain, true>},
        {k_transport<false, kStepDeferred, false>, k_transport<false, kStepDeferred, true>},
@@ -1597,13 +1662,14 @@ int launch_transport(const RoundCase *rc_dev, int nrc, uint64_t total_chunks,
   const Kern kern = kerns[with_log ? 1 : 0][step_kind][tab_n > 0 ? 1 : 0];
   hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.block), lds, s, rc_dev, nrc, total_chunks,
                      chunk_ctr, cfg.refill_min, cfg.chunk, cfg.tally_mode, cfg.bound_shift,
-                     cfg.defer_min, tab_n, tab_n > 0 ? cfg.tab_ne : 0);
+                     cfg.defer_min, tab_n, tab_n > 0 ? cfg.tab_ne : 0, cap);
   return check_launch();
 }
 
-size_t transport_lds_bytes(int block, int tally_mode, int tab_n, int tab_ne) {
+size_t transport_lds_bytes(int block, int tally_mode, int tab_n, int tab_ne, int stash_cap) {
   const size_t nw = (size_t)(block / 64);
   size_t b = kWgSlotsOff + nw * kWaveSlotBytes + (tally_mode == 2 ? nw * kCacheBytesPerWave : 0);
+  b += nw * (size_t)stash_cap * kStashRecBytes;
   // majorant nodes, mu/rho rows and (room for) the bound-test sums
   if (tab_n > 0) b += (size_t)((tab_ne + 3) & ~3) * 4 + (size_t)tab_n * 20;
   return b;
@@ -1616,7 +1682,7 @@ bool transport_lds_fits(int block, int tally_mode, int device) {
     (void)hipGetLastError();  // not a launch error: leave nothing for check_launch
     return false;
   }
-  return transport_lds_bytes(block, tally_mode, 0, 0) <= (size_t)lim;
+  return transport_lds_bytes(block, tally_mode, 0, 0, 16) <= (size_t)lim;
 }
 
 static int grid_for(int64_t n, int block, int cap) {
