@@ -389,6 +389,44 @@ def test_ragged_and_tiny_runs(ctx, n):
         assert frac >= PAIR_MIN
 
 
+def test_source_stash_partial_misses(ctx):
+    """A wave samples the sources of up to 64 ids at once and keeps only the
+    photons that enter the box, compacted, for its idle lanes.  A cone wider
+    than the box makes a large share of each sampled group miss; chunks of
+    100 ids end groups part-full; stashes of 64 (tally modes 0 and 1) and 16
+    records (tally mode 2) and both step kinds must give the same sums, and
+    every logged history must match the oracle's event by event."""
+    say("source stash with partial misses")
+    n = 20_003
+    wl = random_phantom((5, 6, 7), 4, seed=21, n_hist=n)
+    wl.geometry = dict(wl.geometry, a0=-5.5, a1=5.5, b0=-4.5, b1=4.5)   # 54 % miss
+    tunings = [(256, 5, 16, 1024, 0, 2, 16), (256, 4, 1, 100, 0, 2, 16),
+               (512, 2, 64, 4096, 1, 0, 0), (256, 4, 16, 100, 2, 2, 16),
+               (64, 1, 32, 64, 0, 0, 0)]
+    outs = []
+    for t in tunings:
+        say(f"tuning {t}")
+        outs.append(gpu_run(ctx, wl, tuning=L.ctd_tuning(*t),
+                            log=(0, 2000, 200_000) if not outs else None))
+    b = outs[0]["bal"]
+    say(f"missed {b.n_missed} of {n}")
+    assert 0.2 * n < b.n_missed < 0.8 * n
+    for o in outs[1:]:
+        assert np.array_equal(o["s1"], outs[0]["s1"])
+        assert np.array_equal(o["s2_hi"], outs[0]["s2_hi"])
+        assert np.array_equal(o["s2_lo"], outs[0]["s2_lo"])
+        assert o["bal"].n_missed == b.n_missed
+        assert o["bal"].q_escaped == b.q_escaped
+        assert o["st"].n_steps == outs[0]["st"].n_steps
+    oc = O.OracleCase(wl)
+    bs = O.batch_sizes(n, wl.n_batches)
+    hs = range(2000)
+    by_h = {h: O.history(oc, h, O.bin_of_history(oc, h, bs)) for h in hs}
+    frac = _pair_histories(outs[0]["log"], by_h, hs)
+    say(f"stash pairing {frac:.4f}")
+    assert frac >= PAIR_MIN
+
+
 def test_all_histories_miss(ctx):
     say("pencil missing the box")
     wl = W.tiny(n_histories=1000)
