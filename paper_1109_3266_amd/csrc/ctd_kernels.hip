@@ -10,8 +10,10 @@
 // 64-lane wave owns one case at a time and a pool of history ids claimed one
 // chunk per atomic; lanes are one photon each (Sec. 2.2, one thread per
 // photon).  When at least `refill_min` lanes of a wave are idle the wave
-// refills them from its pool in one step, so a wave keeps ~all lanes busy and
-// its lanes hold photons of neighbouring ids, i.e. similar energies.  A wave
+// refills them in one step from its source stash in LDS, which the whole wave
+// fills by sampling the sources of its pool's next ids at once, so a wave
+// keeps ~all lanes busy without sampling on a few lanes at a time, and its
+// lanes hold photons of neighbouring ids, i.e. similar energies.  A wave
 // that claims a chunk of a different case finishes its live photons first.
 //
 // Numerics.  Transport is float32.  Every deposit (E - E' of a Compton event,
